@@ -1,0 +1,621 @@
+// Host side of the richards library: descriptor validation, workspace
+// planning, the multigrid level hierarchy, V-cycle orchestration and the
+// C ABI declared in include/richards.h.  All arithmetic on solver data runs
+// in the kernels; the host only sequences launches and reads back norms.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/richards.h"
+#include "rs_internal.h"
+
+namespace rs {
+void launch_root_beta(int nlev, const int *nvert, const double *hvert, double *const *beta,
+                      double Lz, double Tp, double root_len, hipStream_t s);
+}
+
+using namespace rs;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCALL(x)                                                                     \
+    do {                                                                               \
+        hipError_t e_ = (x);                                                           \
+        if (e_ != hipSuccess) return fail(RS_EHIP, "%s: %s", #x, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+bool pow2p1(int n)
+{
+    if (n < 3) return false;
+    int m = n - 1;
+    return (m & (m - 1)) == 0;
+}
+
+int validate_desc(const rs_grid_desc *d)
+{
+    if (!d) return fail(RS_EINVAL, "null grid descriptor");
+    if (d->struct_size != sizeof(rs_grid_desc))
+        return fail(RS_EINVAL, "rs_grid_desc.struct_size %zu != %zu", d->struct_size,
+                    sizeof(rs_grid_desc));
+    if (d->dim < 1 || d->dim > 3) return fail(RS_EINVAL, "dim must be 1, 2 or 3");
+    for (int l = 0; l < d->dim; ++l) {
+        if (!pow2p1(d->n[l])) return fail(RS_EINVAL, "n[%d]=%d is not 2^k+1 >= 3", l, d->n[l]);
+        if (!(d->L[l] > 0.0)) return fail(RS_EINVAL, "L[%d] must be positive", l);
+    }
+    for (int f = 0; f < 2 * d->dim; ++f) {
+        int b = d->face_bc[f];
+        if (b != RS_BC_DIRICHLET && b != RS_BC_NOFLUX && b != RS_BC_FREEDRAIN)
+            return fail(RS_EINVAL, "face_bc[%d]=%d invalid", f, b);
+        if (b == RS_BC_FREEDRAIN && f != 2 * (d->dim - 1))
+            return fail(RS_EINVAL, "free drainage is only allowed on the bottom face");
+        if (!std::isfinite(d->face_value[f])) return fail(RS_EINVAL, "face_value[%d] not finite", f);
+    }
+    if (d->patch_face >= 0) {
+        if (d->patch_face >= 2 * d->dim) return fail(RS_EINVAL, "patch_face out of range");
+        if (d->dim < 2) return fail(RS_EINVAL, "a face patch needs dim >= 2");
+        int ax = d->patch_face / 2, t = 0;
+        for (int l = 0; l < d->dim; ++l) {
+            if (l == ax) continue;
+            if (d->patch_lo[t] < 0 || d->patch_hi[t] >= d->n[l] || d->patch_lo[t] > d->patch_hi[t])
+                return fail(RS_EINVAL, "patch range invalid on axis %d", l);
+            ++t;
+        }
+    }
+    return RS_OK;
+}
+
+int level_count(const rs_grid_desc *d)
+{
+    int m = d->n[0];
+    for (int l = 1; l < d->dim; ++l) m = d->n[l] < m ? d->n[l] : m;
+    int k = 1;
+    while (m > 3) { m = (m - 1) / 2 + 1; ++k; }
+    return k;
+}
+
+Geo make_geo(const rs_grid_desc *d, int lev)
+{
+    Geo g;
+    memset(&g, 0, sizeof g);
+    g.dim = d->dim;
+    g.vert = d->dim - 1;
+    long long N = 1;
+    for (int l = 0; l < 3; ++l) {
+        if (l < d->dim) {
+            g.n[l] = ((d->n[l] - 1) >> lev) + 1;
+            g.h[l] = d->L[l] / (g.n[l] - 1);
+            g.ih2[l] = 1.0 / (g.h[l] * g.h[l]);
+        } else {
+            g.n[l] = 1;
+            g.h[l] = 1.0;
+            g.ih2[l] = 0.0;
+        }
+        N *= g.n[l];
+    }
+    g.N = N;
+    g.stride[0] = 1;
+    g.stride[1] = g.n[0];
+    g.stride[2] = g.n[0] * g.n[1];
+    for (int f = 0; f < 6; ++f) {
+        g.bc[f] = f < 2 * d->dim ? d->face_bc[f] : 0;
+        g.bcval[f] = f < 2 * d->dim ? d->face_value[f] : 0.0;
+    }
+    g.pface = d->patch_face;
+    int s = 1 << lev;
+    for (int t = 0; t < 2; ++t) {
+        g.plo[t] = (d->patch_lo[t] + s - 1) / s;
+        g.phi[t] = d->patch_hi[t] / s;
+    }
+    g.pval = d->patch_value;
+    return g;
+}
+
+// Workspace layout: per level psi, K, g, d, psibar (FP64) and the root
+// density table; fine-level history psi^n, psi^{n-1}, the Ks field; scratch.
+struct Layout {
+    int nlev;
+    size_t lev_off[kMaxLevels][5];
+    size_t beta_off[kMaxLevels];
+    size_t psi_n, psi_nm1, ks, scratch;
+    size_t total;
+};
+
+constexpr int kScratchWords = 64;
+
+void plan(const rs_grid_desc *d, int precision, Layout *L)
+{
+    (void)precision;
+    size_t off = 0;
+    L->nlev = level_count(d);
+    for (int l = 0; l < L->nlev; ++l) {
+        Geo g = make_geo(d, l);
+        for (int a = 0; a < 5; ++a) {
+            L->lev_off[l][a] = off;
+            off = align_up(off + sizeof(double) * (size_t)g.N);
+        }
+        L->beta_off[l] = off;
+        off = align_up(off + sizeof(double) * (size_t)g.n[g.vert]);
+    }
+    size_t N0 = (size_t)make_geo(d, 0).N;
+    L->psi_n = off;   off = align_up(off + sizeof(double) * N0);
+    L->psi_nm1 = off; off = align_up(off + sizeof(double) * N0);
+    L->ks = off;      off = align_up(off + sizeof(double) * N0);
+    L->scratch = off; off = align_up(off + sizeof(unsigned long long) * kScratchWords);
+    L->total = off;
+}
+
+struct LevelData {
+    Geo geo;
+    double *psi, *K, *g, *d, *psibar, *beta;
+    double lambdaU;
+};
+
+}  // namespace
+
+struct rs_grid {
+    rs_grid_desc desc;
+    int precision;
+    hipStream_t stream;
+    int device;
+    int nlev;
+    LevelData lev[kMaxLevels];
+    double *psi_n, *psi_nm1, *ks;
+    bool has_ks;
+    unsigned long long *scratch;
+    unsigned long long *host_bits;   // pinned readback
+    Law law;
+    bool law_set;
+    Step step;
+    bool in_step;
+    int nstep;
+    double t;
+    int nu_coarse;
+};
+
+namespace {
+
+Law make_law(const rs_constitutive *c)
+{
+    Law L;
+    memset(&L, 0, sizeof L);
+    L.model = c->model;
+    L.ts = c->theta_s;
+    L.tr = c->theta_r;
+    L.Ks = c->Ks;
+    L.dT = c->theta_s - c->theta_r;
+    L.vg_alpha = c->vg_alpha;
+    L.vg_n = c->vg_n;
+    L.vg_m = c->model == RS_VGM ? 1.0 - 1.0 / c->vg_n : 0.0;
+    L.hk_alpha = c->hk_alpha;
+    L.hk_beta = c->hk_beta;
+    L.hk_A = c->hk_A;
+    L.hk_gamma = c->hk_gamma;
+    L.unit = c->psi_unit > 0.0 ? c->psi_unit : 1.0;
+    L.lin_c = c->lin_c;
+    L.sink = c->sink;
+    L.h1 = c->h1;
+    L.h2 = c->h2;
+    L.h3 = c->h3;
+    L.h4 = c->h4;
+    L.xi = c->xi;
+    L.kappa_rule = c->kappa_rule;
+    L.kappa = c->kappa;
+    L.newton = c->newton_iters;
+    return L;
+}
+
+int validate_law(const rs_constitutive *c)
+{
+    if (!c) return fail(RS_EINVAL, "null constitutive");
+    if (c->struct_size != sizeof(rs_constitutive))
+        return fail(RS_EINVAL, "rs_constitutive.struct_size %zu != %zu", c->struct_size,
+                    sizeof(rs_constitutive));
+    if (c->model != RS_VGM && c->model != RS_HAVERKAMP && c->model != RS_LINEAR)
+        return fail(RS_EINVAL, "unknown model %d", c->model);
+    if (c->model != RS_LINEAR && !(c->theta_s > c->theta_r && c->theta_r >= 0.0))
+        return fail(RS_EINVAL, "need theta_s > theta_r >= 0");
+    if (!(c->Ks > 0.0) && !c->Ks_field) return fail(RS_EINVAL, "Ks must be positive");
+    if (c->model == RS_VGM && !(c->vg_n > 1.0 && c->vg_alpha > 0.0))
+        return fail(RS_EINVAL, "vGM needs n > 1 and alpha > 0");
+    if (c->model == RS_HAVERKAMP &&
+        !(c->hk_alpha > 0.0 && c->hk_beta > 0.0 && c->hk_A > 0.0 && c->hk_gamma > 0.0))
+        return fail(RS_EINVAL, "Haverkamp parameters must be positive");
+    if (c->model == RS_LINEAR && !(c->lin_c >= 0.0)) return fail(RS_EINVAL, "lin_c must be >= 0");
+    if (c->sink != RS_SINK_NONE && c->sink != RS_SINK_FEDDES_EXP)
+        return fail(RS_EINVAL, "unknown sink %d", c->sink);
+    if (c->sink == RS_SINK_FEDDES_EXP &&
+        !(c->h4 < c->h3 && c->h3 < c->h2 && c->h2 < c->h1 && c->root_len > 0.0 && c->Tp >= 0.0))
+        return fail(RS_EINVAL, "Feddes parameters need h4 < h3 < h2 < h1, root_len > 0, Tp >= 0");
+    if (!(c->xi >= 0.0)) return fail(RS_EINVAL, "xi must be >= 0");
+    if (c->kappa_rule != RS_KAPPA_CONST && c->kappa_rule != RS_KAPPA_REL &&
+        c->kappa_rule != RS_KAPPA_REMARK)
+        return fail(RS_EINVAL, "unknown kappa rule %d", c->kappa_rule);
+    if (c->kappa_rule != RS_KAPPA_REMARK && !(c->kappa >= 0.0))
+        return fail(RS_EINVAL, "kappa must be >= 0");
+    if (c->newton_iters < 1 || c->newton_iters > 64)
+        return fail(RS_EINVAL, "newton_iters must be in 1..64");
+    return RS_OK;
+}
+
+int read_norm(rs_grid *G, double *out)
+{
+    HIPCALL(hipMemcpyAsync(G->host_bits, G->scratch, sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost, G->stream));
+    HIPCALL(hipStreamSynchronize(G->stream));
+    unsigned long long b = G->host_bits[0];
+    double v;
+    memcpy(&v, &b, sizeof v);
+    *out = v;
+    return RS_OK;
+}
+
+int fine_norm(rs_grid *G, double *out)
+{
+    LevelData &f = G->lev[0];
+    launch_fill_u64(G->scratch, 1, 0ull, G->stream);
+    launch_residual(f.geo, G->law, G->step, f.beta, f.K, f.g, f.psi, nullptr, G->scratch, G->stream);
+    HIPCALL(hipGetLastError());
+    return read_norm(G, out);
+}
+
+void vcycle_level(rs_grid *G, int l, int nu1, int nu2)
+{
+    LevelData &f = G->lev[l];
+    if (l == G->nlev - 1) {
+        launch_sweep_rb(f.geo, G->law, G->step, f.beta, f.lambdaU, f.K, f.g, f.psi, G->nu_coarse,
+                        G->stream);
+        return;
+    }
+    LevelData &c = G->lev[l + 1];
+    launch_sweep_rb(f.geo, G->law, G->step, f.beta, f.lambdaU, f.K, f.g, f.psi, nu1, G->stream);
+    launch_residual(f.geo, G->law, G->step, f.beta, f.K, f.g, f.psi, f.d, nullptr, G->stream);
+    launch_restrict(c.geo, f.geo, f.psi, f.d, c.psibar, c.g, G->stream);
+    launch_coarse_rhs(c.geo, G->law, G->step, c.beta, c.K, c.psibar, c.g, c.psi, G->stream);
+    vcycle_level(G, l + 1, nu1, nu2);
+    launch_prolong(f.geo, c.geo, c.psi, c.psibar, f.psi, G->stream);
+    launch_sweep_rb(f.geo, G->law, G->step, f.beta, f.lambdaU, f.K, f.g, f.psi, nu2, G->stream);
+}
+
+double *field_ptr(const rs_grid *G, int level, int field)
+{
+    const LevelData &L = G->lev[level];
+    switch (field) {
+    case RS_FIELD_PSI: return L.psi;
+    case RS_FIELD_KSTAR: return L.K;
+    case RS_FIELD_G: return L.g;
+    case RS_FIELD_PSIBAR: return L.psibar;
+    default: return nullptr;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *rs_last_error(void) { return g_err.c_str(); }
+
+int rs_workspace_bytes(const rs_grid_desc *d, int precision, size_t *out)
+{
+    int e = validate_desc(d);
+    if (e) return e;
+    if (precision != RS_FP64 && precision != RS_MIXED) return fail(RS_EINVAL, "bad precision");
+    if (!out) return fail(RS_EINVAL, "null out");
+    Layout L;
+    plan(d, precision, &L);
+    *out = L.total;
+    return RS_OK;
+}
+
+int rs_create_grid(const rs_grid_desc *d, int precision, void *ws_dev, size_t ws_bytes,
+                   void *stream, rs_grid **out)
+{
+    int e = validate_desc(d);
+    if (e) return e;
+    if (precision != RS_FP64 && precision != RS_MIXED) return fail(RS_EINVAL, "bad precision");
+    if (!out) return fail(RS_EINVAL, "null out");
+    if (!ws_dev) return fail(RS_EINVAL, "null workspace");
+    if (((uintptr_t)ws_dev) % kAlign) return fail(RS_EINVAL, "workspace must be 256-byte aligned");
+    Layout L;
+    plan(d, precision, &L);
+    if (ws_bytes < L.total)
+        return fail(RS_ENOMEM, "workspace %zu bytes < required %zu", ws_bytes, L.total);
+    rs_grid *G = new (std::nothrow) rs_grid();
+    if (!G) return fail(RS_ENOMEM, "host allocation failed");
+    G->desc = *d;
+    G->precision = precision;
+    G->stream = (hipStream_t)stream;
+    if (hipGetDevice(&G->device) != hipSuccess) G->device = -1;
+    G->nlev = L.nlev;
+    char *base = (char *)ws_dev;
+    for (int l = 0; l < L.nlev; ++l) {
+        LevelData &v = G->lev[l];
+        v.geo = make_geo(d, l);
+        v.psi = (double *)(base + L.lev_off[l][0]);
+        v.K = (double *)(base + L.lev_off[l][1]);
+        v.g = (double *)(base + L.lev_off[l][2]);
+        v.d = (double *)(base + L.lev_off[l][3]);
+        v.psibar = (double *)(base + L.lev_off[l][4]);
+        v.beta = (double *)(base + L.beta_off[l]);
+        v.lambdaU = 0.0;
+    }
+    G->psi_n = (double *)(base + L.psi_n);
+    G->psi_nm1 = (double *)(base + L.psi_nm1);
+    G->ks = (double *)(base + L.ks);
+    G->scratch = (unsigned long long *)(base + L.scratch);
+    G->has_ks = false;
+    G->law_set = false;
+    G->in_step = false;
+    G->nstep = 0;
+    G->t = 0.0;
+    G->nu_coarse = 32;
+    if (hipHostMalloc((void **)&G->host_bits, 64 * sizeof(unsigned long long), hipHostMallocDefault) !=
+        hipSuccess) {
+        delete G;
+        return fail(RS_EHIP, "hipHostMalloc failed");
+    }
+    *out = G;
+    return RS_OK;
+}
+
+void rs_destroy_grid(rs_grid *G)
+{
+    if (!G) return;
+    if (G->host_bits) (void)hipHostFree(G->host_bits);
+    delete G;
+}
+
+int rs_set_constitutive(rs_grid *G, const rs_constitutive *c)
+{
+    if (!G) return fail(RS_EINVAL, "null grid");
+    int e = validate_law(c);
+    if (e) return e;
+    G->law = make_law(c);
+    G->step.lag_extrap = c->lag_extrap ? 1 : 0;
+    if (c->Ks_field) {
+        size_t bytes = sizeof(double) * (size_t)G->lev[0].geo.N;
+        HIPCALL(hipMemcpyAsync(G->ks, c->Ks_field, bytes, hipMemcpyHostToDevice, G->stream));
+        HIPCALL(hipStreamSynchronize(G->stream));
+        G->has_ks = true;
+    } else {
+        G->has_ks = false;
+    }
+    if (c->sink == RS_SINK_FEDDES_EXP) {
+        int nv[kMaxLevels];
+        double hv[kMaxLevels];
+        double *bp[kMaxLevels];
+        for (int l = 0; l < G->nlev; ++l) {
+            const Geo &g = G->lev[l].geo;
+            nv[l] = g.n[g.vert];
+            hv[l] = g.h[g.vert];
+            bp[l] = G->lev[l].beta;
+        }
+        int v = G->desc.dim - 1;
+        launch_root_beta(G->nlev, nv, hv, bp, G->desc.L[v], c->Tp, c->root_len, G->stream);
+        HIPCALL(hipGetLastError());
+    }
+    G->law_set = true;
+    return RS_OK;
+}
+
+int rs_set_state(rs_grid *G, const double *psi_n, const double *psi_nm1, int nstep, double t)
+{
+    if (!G || !psi_n) return fail(RS_EINVAL, "null argument");
+    size_t bytes = sizeof(double) * (size_t)G->lev[0].geo.N;
+    HIPCALL(hipMemcpyAsync(G->psi_n, psi_n, bytes, hipMemcpyDeviceToDevice, G->stream));
+    HIPCALL(hipMemcpyAsync(G->psi_nm1, psi_nm1 ? psi_nm1 : psi_n, bytes, hipMemcpyDeviceToDevice,
+                           G->stream));
+    G->nstep = nstep;
+    G->t = t;
+    G->in_step = false;
+    return RS_OK;
+}
+
+int rs_get_state(const rs_grid *G, double *psi_n, double *psi_nm1, int *nstep, double *t)
+{
+    if (!G) return fail(RS_EINVAL, "null grid");
+    size_t bytes = sizeof(double) * (size_t)G->lev[0].geo.N;
+    if (psi_n) HIPCALL(hipMemcpyAsync(psi_n, G->psi_n, bytes, hipMemcpyDeviceToDevice, G->stream));
+    if (psi_nm1)
+        HIPCALL(hipMemcpyAsync(psi_nm1, G->psi_nm1, bytes, hipMemcpyDeviceToDevice, G->stream));
+    if (nstep) *nstep = G->nstep;
+    if (t) *t = G->t;
+    return RS_OK;
+}
+
+int rs_begin_step(rs_grid *G, double dt, int order)
+{
+    if (!G) return fail(RS_EINVAL, "null grid");
+    if (!G->law_set) return fail(RS_ESTATE, "rs_set_constitutive must come first");
+    if (!(dt > 0.0)) return fail(RS_EINVAL, "dt must be positive");
+    if (order != 1 && order != 2) return fail(RS_EINVAL, "order must be 1 or 2");
+    G->step.dt = dt;
+    G->step.order = (order == 2 && G->nstep > 0) ? 2 : 1;
+    G->step.a = (G->step.order == 1) ? 1.0 / dt : 1.5 / dt;
+    LevelData &f = G->lev[0];
+    launch_setup_kstar(f.geo, G->law, G->step, G->psi_n, G->psi_nm1, G->has_ks ? G->ks : nullptr,
+                       f.K, f.psi, G->stream);
+    launch_setup_g(f.geo, G->law, G->step, G->psi_n, G->psi_nm1, f.K, f.g, G->stream);
+    for (int l = 1; l < G->nlev; ++l)
+        launch_inject(G->lev[l].geo, G->lev[l - 1].geo, G->lev[l - 1].K, G->lev[l].K, G->stream);
+    HIPCALL(hipGetLastError());
+    if (G->law.kappa_rule == kKappaRemark) {
+        launch_fill_u64(G->scratch + 1, G->nlev, 0ull, G->stream);
+        for (int l = 0; l < G->nlev; ++l)
+            launch_lambda_u(G->lev[l].geo, G->lev[l].K, G->scratch + 1 + l, G->stream);
+        HIPCALL(hipMemcpyAsync(G->host_bits + 1, G->scratch + 1,
+                               sizeof(unsigned long long) * G->nlev, hipMemcpyDeviceToHost,
+                               G->stream));
+        HIPCALL(hipStreamSynchronize(G->stream));
+        for (int l = 0; l < G->nlev; ++l) {
+            double v;
+            memcpy(&v, &G->host_bits[1 + l], sizeof v);
+            G->lev[l].lambdaU = v;
+        }
+    }
+    G->in_step = true;
+    return RS_OK;
+}
+
+int rs_sweep(rs_grid *G, int level, int nsweeps)
+{
+    if (!G) return fail(RS_EINVAL, "null grid");
+    if (!G->in_step) return fail(RS_ESTATE, "no active step (call rs_begin_step)");
+    if (level < 0 || level >= G->nlev) return fail(RS_EINVAL, "level out of range");
+    if (nsweeps < 0) return fail(RS_EINVAL, "nsweeps < 0");
+    LevelData &f = G->lev[level];
+    launch_sweep_rb(f.geo, G->law, G->step, f.beta, f.lambdaU, f.K, f.g, f.psi, nsweeps, G->stream);
+    HIPCALL(hipGetLastError());
+    return RS_OK;
+}
+
+int rs_vcycle(rs_grid *G, int nu1, int nu2, double *res)
+{
+    if (!G) return fail(RS_EINVAL, "null grid");
+    if (!G->in_step) return fail(RS_ESTATE, "no active step (call rs_begin_step)");
+    if (nu1 < 0 || nu2 < 0) return fail(RS_EINVAL, "negative smoothing count");
+    vcycle_level(G, 0, nu1, nu2);
+    HIPCALL(hipGetLastError());
+    if (res) return fine_norm(G, res);
+    return RS_OK;
+}
+
+int rs_residual_norm(rs_grid *G, double *out)
+{
+    if (!G || !out) return fail(RS_EINVAL, "null argument");
+    if (!G->in_step) return fail(RS_ESTATE, "no active step (call rs_begin_step)");
+    int e = fine_norm(G, out);
+    if (e) return e;
+    if (!std::isfinite(*out)) return fail(RS_ENONFINITE, "residual is not finite");
+    return RS_OK;
+}
+
+int rs_residual(rs_grid *G, double *d_dev)
+{
+    if (!G || !d_dev) return fail(RS_EINVAL, "null argument");
+    if (!G->in_step) return fail(RS_ESTATE, "no active step (call rs_begin_step)");
+    LevelData &f = G->lev[0];
+    launch_residual(f.geo, G->law, G->step, f.beta, f.K, f.g, f.psi, d_dev, nullptr, G->stream);
+    HIPCALL(hipGetLastError());
+    return RS_OK;
+}
+
+int rs_end_step(rs_grid *G)
+{
+    if (!G) return fail(RS_EINVAL, "null grid");
+    if (!G->in_step) return fail(RS_ESTATE, "no active step");
+    double *tmp = G->psi_nm1;
+    G->psi_nm1 = G->psi_n;
+    G->psi_n = tmp;
+    size_t bytes = sizeof(double) * (size_t)G->lev[0].geo.N;
+    HIPCALL(hipMemcpyAsync(G->psi_n, G->lev[0].psi, bytes, hipMemcpyDeviceToDevice, G->stream));
+    G->nstep += 1;
+    G->t += G->step.dt;
+    G->in_step = false;
+    return RS_OK;
+}
+
+int rs_bdf_step(rs_grid *G, double dt, int order, const rs_solve_opts *o, rs_step_stats *st)
+{
+    if (!G || !o) return fail(RS_EINVAL, "null argument");
+    if (o->struct_size != sizeof(rs_solve_opts)) return fail(RS_EINVAL, "rs_solve_opts.struct_size");
+    if (st && st->struct_size != sizeof(rs_step_stats)) return fail(RS_EINVAL, "rs_step_stats.struct_size");
+    if (o->nu1 < 0 || o->nu2 < 0 || o->nu_coarse < 1 || o->max_cycles < 0)
+        return fail(RS_EINVAL, "bad solve options");
+    G->nu_coarse = o->nu_coarse;
+    int e = rs_begin_step(G, dt, order);
+    if (e) return e;
+    double r;
+    e = fine_norm(G, &r);
+    if (e) return e;
+    double r0 = r;
+    int cycles = 0, slow = 0, nh = 0;
+    double hist[64];
+    hist[nh++] = r;
+    bool stagnated = false;
+    while (std::isfinite(r) && r > o->tol_abs && cycles < o->max_cycles) {
+        vcycle_level(G, 0, o->nu1, o->nu2);
+        HIPCALL(hipGetLastError());
+        double rn;
+        e = fine_norm(G, &rn);
+        if (e) return e;
+        ++cycles;
+        if (nh < 64) hist[nh++] = rn;
+        if (o->stagnation) {
+            slow = (rn > 0.5 * r) ? slow + 1 : 0;
+            if (slow >= 2) { r = rn; stagnated = true; break; }
+        }
+        r = rn;
+    }
+    int status = RS_OK;
+    if (!std::isfinite(r)) status = RS_ENONFINITE;
+    else if (r > o->tol_abs && !stagnated) status = RS_ENOTCONV;
+    if (st) {
+        st->cycles = cycles;
+        st->status = status;
+        st->res0 = r0;
+        st->res = r;
+        st->n_hist = nh;
+        memcpy(st->res_hist, hist, sizeof(double) * nh);
+    }
+    if (status != RS_OK) {
+        return fail(status, status == RS_ENONFINITE ? "residual is not finite"
+                                                    : "tolerance not reached in max_cycles");
+    }
+    return rs_end_step(G);
+}
+
+int rs_copy_field(const rs_grid *G, int level, int field, double *dst)
+{
+    if (!G || !dst) return fail(RS_EINVAL, "null argument");
+    if (level < 0 || level >= G->nlev) return fail(RS_EINVAL, "level out of range");
+    double *p = field_ptr(G, level, field);
+    if (!p) return fail(RS_EINVAL, "unknown field %d", field);
+    HIPCALL(hipMemcpyAsync(dst, p, sizeof(double) * (size_t)G->lev[level].geo.N,
+                           hipMemcpyDeviceToDevice, G->stream));
+    return RS_OK;
+}
+
+int rs_set_field(rs_grid *G, int level, int field, const double *src)
+{
+    if (!G || !src) return fail(RS_EINVAL, "null argument");
+    if (level < 0 || level >= G->nlev) return fail(RS_EINVAL, "level out of range");
+    double *p = field_ptr(G, level, field);
+    if (!p) return fail(RS_EINVAL, "unknown field %d", field);
+    HIPCALL(hipMemcpyAsync(p, src, sizeof(double) * (size_t)G->lev[level].geo.N,
+                           hipMemcpyDeviceToDevice, G->stream));
+    return RS_OK;
+}
+
+int rs_num_levels(const rs_grid *G) { return G ? G->nlev : 0; }
+
+int rs_level_shape(const rs_grid *G, int level, int *n_out)
+{
+    if (!G || !n_out) return fail(RS_EINVAL, "null argument");
+    if (level < 0 || level >= G->nlev) return fail(RS_EINVAL, "level out of range");
+    for (int a = 0; a < 3; ++a) n_out[a] = G->lev[level].geo.n[a];
+    return RS_OK;
+}
+
+}  // extern "C"

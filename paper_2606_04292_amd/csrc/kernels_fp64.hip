@@ -1,0 +1,532 @@
+// FP64 kernels of the NGS-FAS V-cycle: step setup (history, lagged K*, right-
+// hand side), red-black NGS sweeps, defect + max-norm, full-weighting
+// restriction with the FAS coarse right-hand side, linear prolongation.
+//
+// Stencil: for node i and a neighbour j across a face normal to axis l,
+// m_ij = (K*_i + K*_j) / 2 / (w_l h_l^2), w_l = 1/2 on a boundary of axis l
+// (half control volume at no-flux / free-drainage faces), else 1
+// (eq. discrete-strong with arithmetic face averages; the matrix M of
+// section 2).  Node kinds come from indices, so a sweep moves only psi, K*
+// and g (8 B each per node) plus the psi write.
+#include "rs_internal.h"
+#include "soil_device.h"
+
+namespace rs {
+
+namespace {
+
+constexpr int kBX = 64;
+constexpr int kBY = 4;
+
+// Visit the existing neighbours of node c (order: axis 0 low/high, axis 1,
+// axis 2), calling fn(jdx, coef, axis, side) with coef = 1/(2 w h^2).
+template <typename Fn>
+__device__ __forceinline__ void for_each_nb(const Geo &g, const int c[3], long long idx, Fn &&fn)
+{
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        if (l >= g.dim) break;
+        double iw = (c[l] == 0 || c[l] == g.n[l] - 1) ? 2.0 : 1.0;
+        double cf = 0.5 * iw * g.ih2[l];
+        if (c[l] > 0) fn(idx - g.stride[l], cf, l, -1);
+        if (c[l] < g.n[l] - 1) fn(idx + g.stride[l], cf, l, +1);
+    }
+}
+
+__device__ __forceinline__ double sink_beta(const Law &L, const double *beta, const int c[3], int vert)
+{
+    return (L.sink == kSinkFeddes) ? beta[c[vert]] : 0.0;
+}
+
+// N(psi)_i = a theta(psi_i) + beta a_F(psi_i) + xi psi_i + (M psi)_i  (eq. Nh-def)
+__device__ __forceinline__ double apply_N(const Geo &g, const Law &L, const Step &st,
+                                          const double *beta, const double *K, const double *psi,
+                                          const int c[3], long long idx)
+{
+    double x = psi[idx];
+    double Ki = K[idx];
+    double s = st.a * theta_only(L, x);
+    if (L.sink == kSinkFeddes) {
+        double fa, dfa;
+        feddes(L, x, fa, dfa);
+        s += beta[c[g.vert]] * fa;
+    }
+    double mpsi = 0.0;
+    for_each_nb(g, c, idx, [&](long long j, double cf, int, int) {
+        mpsi += cf * (Ki + K[j]) * (x - psi[j]);
+    });
+    return s + (L.xi * x + mpsi);
+}
+
+__device__ __forceinline__ double block_max(double v)
+{
+    __shared__ double red[8];
+    int lane = threadIdx.x + threadIdx.y * blockDim.x;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        double o = __shfl_xor(v, off);
+        v = (o > v || o != o) ? o : v;
+    }
+    int wave = lane >> 6;
+    if ((lane & 63) == 0) red[wave] = v;
+    __syncthreads();
+    int nw = (blockDim.x * blockDim.y + 63) >> 6;
+    if (lane == 0) {
+        double m = red[0];
+        for (int w = 1; w < nw; ++w) m = (red[w] > m || red[w] != red[w]) ? red[w] : m;
+        v = m;
+    }
+    return v;
+}
+
+__global__ void k_fill_u64(unsigned long long *p, int n, unsigned long long v)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Step setup (eq. fully-bdf1; BDF2 reading; eq. Nh-def for g)
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_setup_kstar(Geo g, Law L, Step st, const double *psi_n,
+                                                     const double *psi_nm1, const double *Ks,
+                                                     double *K, double *psi)
+{
+    int i = blockIdx.x * kBX + threadIdx.x;
+    int j = blockIdx.y * kBY + threadIdx.y;
+    int k = blockIdx.z;
+    if (i >= g.n[0] || j >= g.n[1]) return;
+    long long idx = i + (long long)j * g.stride[1] + (long long)k * g.stride[2];
+    double bv;
+    double ps;
+    if (dirichlet_at(g, i, j, k, &bv)) {
+        ps = bv;
+        psi[idx] = bv;
+    } else {
+        double pn = psi_n[idx];
+        ps = (st.order == 2 && st.lag_extrap) ? 2.0 * pn - psi_nm1[idx] : pn;
+        psi[idx] = pn;
+    }
+    double ks = Ks ? Ks[idx] : L.Ks;
+    K[idx] = ks * krel(L, ps);
+}
+
+__global__ __launch_bounds__(256) void k_setup_g(Geo g, Law L, Step st, const double *psi_n,
+                                                 const double *psi_nm1, const double *K,
+                                                 double *gv)
+{
+    int i = blockIdx.x * kBX + threadIdx.x;
+    int j = blockIdx.y * kBY + threadIdx.y;
+    int k = blockIdx.z;
+    if (i >= g.n[0] || j >= g.n[1]) return;
+    long long idx = i + (long long)j * g.stride[1] + (long long)k * g.stride[2];
+    if (dirichlet_at(g, i, j, k, nullptr)) {
+        gv[idx] = 0.0;
+        return;
+    }
+    int c[3] = {i, j, k};
+    double pn = psi_n[idx];
+    double H, ps;
+    if (st.order == 1) {
+        H = theta_only(L, pn) / st.dt;
+        ps = pn;
+    } else {
+        double pm = psi_nm1[idx];
+        H = (4.0 * theta_only(L, pn) - theta_only(L, pm)) / (2.0 * st.dt);
+        ps = st.lag_extrap ? 2.0 * pn - pm : pn;
+    }
+    // gravity (M z)_i: only faces along the vertical axis, z_i - z_j = -side h
+    double Ki = K[idx];
+    double mz = 0.0;
+    const int v = g.vert;
+    for_each_nb(g, c, idx, [&](long long jn, double cf, int l, int side) {
+        if (l == v) mz += cf * (Ki + K[jn]) * (-side * g.h[v]);
+    });
+    double gi = H + L.xi * ps - mz;
+    if (c[v] == 0 && g.bc[2 * v] == kBcFreedrain) {
+        double iw = 2.0;   // bottom node: half control volume
+        gi -= Ki * iw / g.h[v];
+    }
+    gv[idx] = gi;
+}
+
+__global__ __launch_bounds__(256) void k_inject(Geo gc, Geo gf, const double *Kf, double *Kc)
+{
+    int i = blockIdx.x * kBX + threadIdx.x;
+    int j = blockIdx.y * kBY + threadIdx.y;
+    int k = blockIdx.z;
+    if (i >= gc.n[0] || j >= gc.n[1]) return;
+    long long I = i + (long long)j * gc.stride[1] + (long long)k * gc.stride[2];
+    long long F = 2LL * i + 2LL * j * gf.stride[1] + 2LL * k * gf.stride[2];
+    Kc[I] = Kf[F];
+}
+
+// max over red unknowns of the row sum of U over unknown neighbours (the red-
+// black ordering puts every neighbour of a red node after it)
+__global__ __launch_bounds__(256) void k_lambda_u(Geo g, const double *K, unsigned long long *out)
+{
+    int i = blockIdx.x * kBX + threadIdx.x;
+    int j = blockIdx.y * kBY + threadIdx.y;
+    int k = blockIdx.z;
+    double v = 0.0;
+    if (i < g.n[0] && j < g.n[1] && ((i + j + k) & 1) == 0 && !dirichlet_at(g, i, j, k, nullptr)) {
+        long long idx = i + (long long)j * g.stride[1] + (long long)k * g.stride[2];
+        int c[3] = {i, j, k};
+        double Ki = K[idx];
+        for_each_nb(g, c, idx, [&](long long jn, double cf, int l, int side) {
+            int d[3] = {i, j, k};
+            d[l] += side;
+            if (!dirichlet_at(g, d[0], d[1], d[2], nullptr)) v += cf * (Ki + K[jn]);
+        });
+    }
+    v = block_max(v);
+    if (threadIdx.x == 0 && threadIdx.y == 0) atomicMax(out, (unsigned long long)__double_as_longlong(v));
+}
+
+// ---------------------------------------------------------------------------
+// Red-black NGS (eq. iterative / eq. point-update)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void ngs_update(const Geo &g, const Law &L, const Step &st,
+                                           const double *beta, double lambdaU, const double *K,
+                                           const double *gv, double *psi, int i, int j, int k,
+                                           int colour)
+{
+    long long idx = i + (long long)j * g.stride[1] + (long long)k * g.stride[2];
+    int c[3] = {i, j, k};
+    double Ki = K[idx];
+    double f = gv[idx];
+    double mii = 0.0, usum = 0.0;
+    const bool remark = (L.kappa_rule == kKappaRemark);
+    for_each_nb(g, c, idx, [&](long long jn, double cf, int l, int side) {
+        double m = cf * (Ki + K[jn]);
+        mii += m;
+        f += m * psi[jn];
+        if (remark && colour == 0) {
+            int d[3] = {i, j, k};
+            d[l] += side;
+            if (!dirichlet_at(g, d[0], d[1], d[2], nullptr)) usum += m;
+        }
+    });
+    double kap;
+    if (L.kappa_rule == kKappaConst) kap = L.kappa;
+    else if (L.kappa_rule == kKappaRel) kap = L.kappa * mii;
+    else kap = (colour == 0) ? lambdaU - usum : lambdaU;
+    double x0 = psi[idx];
+    f += kap * x0;
+    double cc = L.xi + kap + mii;
+    double b = sink_beta(L, beta, c, g.vert);
+    psi[idx] = local_solve(L, st.a, b, cc, f, x0);
+}
+
+__global__ __launch_bounds__(256) void k_sweep_colour(Geo g, Law L, Step st, const double *beta,
+                                                      double lambdaU, const double *K,
+                                                      const double *gv, double *psi, int colour)
+{
+    int j = blockIdx.y * kBY + threadIdx.y;
+    int k = blockIdx.z;
+    if (j >= g.n[1]) return;
+    int i = 2 * (blockIdx.x * kBX + threadIdx.x) + ((j + k + colour) & 1);
+    if (i >= g.n[0]) return;
+    if (dirichlet_at(g, i, j, k, nullptr)) return;
+    ngs_update(g, L, st, beta, lambdaU, K, gv, psi, i, j, k, colour);
+}
+
+// Whole sweeps of a small level in one work-group (coarse levels, where
+// launch latency, not work, dominates).
+__global__ __launch_bounds__(256) void k_sweep_small(Geo g, Law L, Step st, const double *beta,
+                                                     double lambdaU, const double *K,
+                                                     const double *gv, double *psi, int nsweeps)
+{
+    const int N = (int)g.N;
+    for (int s = 0; s < nsweeps; ++s) {
+        for (int colour = 0; colour < 2; ++colour) {
+            for (int t = threadIdx.x; t < N; t += blockDim.x) {
+                int i = t % g.n[0];
+                int r = t / g.n[0];
+                int j = r % g.n[1];
+                int k = r / g.n[1];
+                if (((i + j + k) & 1) != colour) continue;
+                if (dirichlet_at(g, i, j, k, nullptr)) continue;
+                ngs_update(g, L, st, beta, lambdaU, K, gv, psi, i, j, k, colour);
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Defect d = g - N(psi) and its max-norm (step 2 of the FAS algorithm)
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_residual(Geo g, Law L, Step st, const double *beta,
+                                                  const double *K, const double *gv,
+                                                  const double *psi, double *d,
+                                                  unsigned long long *norm_bits)
+{
+    int i = blockIdx.x * kBX + threadIdx.x;
+    int j = blockIdx.y * kBY + threadIdx.y;
+    int k = blockIdx.z;
+    double v = 0.0;
+    if (i < g.n[0] && j < g.n[1]) {
+        long long idx = i + (long long)j * g.stride[1] + (long long)k * g.stride[2];
+        double r = 0.0;
+        if (!dirichlet_at(g, i, j, k, nullptr)) {
+            int c[3] = {i, j, k};
+            r = gv[idx] - apply_N(g, L, st, beta, K, psi, c, idx);
+        }
+        if (d) d[idx] = r;
+        v = fabs(r);
+    }
+    if (norm_bits) {
+        v = block_max(v);
+        if (threadIdx.x == 0 && threadIdx.y == 0)
+            atomicMax(norm_bits, (unsigned long long)__double_as_longlong(v));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Transfers (section 3.2 steps 3, 4 and 6)
+// ---------------------------------------------------------------------------
+
+// psibar_H = FW(psi_h), d_H = FW(d_h) stored in g_H (Dirichlet coarse nodes:
+// injection of psi, zero defect).  FW: tensor (1/4, 1/2, 1/4) around fine node
+// 2I, missing neighbours mirrored at the domain boundary.
+__global__ __launch_bounds__(256) void k_restrict(Geo gc, Geo gf, const double *psi_f,
+                                                  const double *d_f, double *psibar_c,
+                                                  double *g_c)
+{
+    int I0 = blockIdx.x * kBX + threadIdx.x;
+    int I1 = blockIdx.y * kBY + threadIdx.y;
+    int I2 = blockIdx.z;
+    if (I0 >= gc.n[0] || I1 >= gc.n[1]) return;
+    long long I = I0 + (long long)I1 * gc.stride[1] + (long long)I2 * gc.stride[2];
+    int F[3] = {2 * I0, 2 * I1, 2 * I2};
+    if (dirichlet_at(gc, I0, I1, I2, nullptr)) {
+        psibar_c[I] = psi_f[F[0] + (long long)F[1] * gf.stride[1] + (long long)F[2] * gf.stride[2]];
+        g_c[I] = 0.0;
+        return;
+    }
+    int lo[3], hi[3];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        lo[l] = (l < gf.dim) ? -1 : 0;
+        hi[l] = (l < gf.dim) ? 1 : 0;
+    }
+    double sp = 0.0, sd = 0.0;
+    for (int o2 = lo[2]; o2 <= hi[2]; ++o2) {
+        int f2 = F[2] + o2;
+        f2 = f2 < 0 ? -f2 : (f2 > gf.n[2] - 1 ? 2 * (gf.n[2] - 1) - f2 : f2);
+        double w2 = (gf.dim > 2) ? (o2 == 0 ? 0.5 : 0.25) : 1.0;
+        for (int o1 = lo[1]; o1 <= hi[1]; ++o1) {
+            int f1 = F[1] + o1;
+            f1 = f1 < 0 ? -f1 : (f1 > gf.n[1] - 1 ? 2 * (gf.n[1] - 1) - f1 : f1);
+            double w1 = (gf.dim > 1) ? (o1 == 0 ? 0.5 : 0.25) : 1.0;
+            for (int o0 = -1; o0 <= 1; ++o0) {
+                int f0 = F[0] + o0;
+                f0 = f0 < 0 ? -f0 : (f0 > gf.n[0] - 1 ? 2 * (gf.n[0] - 1) - f0 : f0);
+                double w = (o0 == 0 ? 0.5 : 0.25) * w1 * w2;
+                long long fi = f0 + (long long)f1 * gf.stride[1] + (long long)f2 * gf.stride[2];
+                sp += w * psi_f[fi];
+                sd += w * d_f[fi];
+            }
+        }
+    }
+    psibar_c[I] = sp;
+    g_c[I] = sd;
+}
+
+// g_H = N_H(psibar_H) + d_H (g_H holds d_H on entry), psi_H = psibar_H.
+__global__ __launch_bounds__(256) void k_coarse_rhs(Geo g, Law L, Step st, const double *beta,
+                                                    const double *K, const double *psibar,
+                                                    double *gv, double *psi)
+{
+    int i = blockIdx.x * kBX + threadIdx.x;
+    int j = blockIdx.y * kBY + threadIdx.y;
+    int k = blockIdx.z;
+    if (i >= g.n[0] || j >= g.n[1]) return;
+    long long idx = i + (long long)j * g.stride[1] + (long long)k * g.stride[2];
+    if (!dirichlet_at(g, i, j, k, nullptr)) {
+        int c[3] = {i, j, k};
+        gv[idx] = apply_N(g, L, st, beta, K, psibar, c, idx) + gv[idx];
+    }
+    psi[idx] = psibar[idx];
+}
+
+// psi_h += I_h^H (psi_H - psibar_H) at fine unknowns (tensor linear
+// interpolation: even index -> coarse node, odd -> mean of the two).
+__global__ __launch_bounds__(256) void k_prolong(Geo gf, Geo gc, const double *psi_c,
+                                                 const double *psibar_c, double *psi_f)
+{
+    int i = blockIdx.x * kBX + threadIdx.x;
+    int j = blockIdx.y * kBY + threadIdx.y;
+    int k = blockIdx.z;
+    if (i >= gf.n[0] || j >= gf.n[1]) return;
+    if (dirichlet_at(gf, i, j, k, nullptr)) return;
+    int c[3] = {i, j, k};
+    int a0[3], a1[3], cnt[3];
+    double wt[3];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        if (c[l] & 1) {
+            a0[l] = (c[l] - 1) >> 1;
+            a1[l] = (c[l] + 1) >> 1;
+            cnt[l] = 2;
+            wt[l] = 0.5;
+        } else {
+            a0[l] = a1[l] = c[l] >> 1;
+            cnt[l] = 1;
+            wt[l] = 1.0;
+        }
+    }
+    double e = 0.0;
+    for (int q2 = 0; q2 < cnt[2]; ++q2)
+        for (int q1 = 0; q1 < cnt[1]; ++q1)
+            for (int q0 = 0; q0 < cnt[0]; ++q0) {
+                long long J = (q0 ? a1[0] : a0[0]) + (long long)(q1 ? a1[1] : a0[1]) * gc.stride[1] +
+                              (long long)(q2 ? a1[2] : a0[2]) * gc.stride[2];
+                e += wt[0] * wt[1] * wt[2] * (psi_c[J] - psibar_c[J]);
+            }
+    long long idx = i + (long long)j * gf.stride[1] + (long long)k * gf.stride[2];
+    psi_f[idx] += e;
+}
+
+// Root density of the Feddes-exponential sink on every level:
+// beta(z) = Tp exp(-(Lz - z)/root_len) / Z, Z the trapezoidal integral of the
+// exponential over the fine column, so that the column integral is Tp.
+struct BetaArgs {
+    int nlev;
+    int nvert[kMaxLevels];
+    double hvert[kMaxLevels];
+    double *beta[kMaxLevels];
+    double Lz, Tp, rl;
+};
+
+__global__ __launch_bounds__(256) void k_root_beta(BetaArgs a)
+{
+    __shared__ double part[256];
+    const int n0 = a.nvert[0];
+    const double h0 = a.hvert[0];
+    double s = 0.0;
+    for (int k = threadIdx.x; k < n0; k += blockDim.x) {
+        double w = (k == 0 || k == n0 - 1) ? 0.5 : 1.0;
+        s += w * h0 * exp(-(a.Lz - k * h0) / a.rl);
+    }
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
+        __syncthreads();
+    }
+    const double Z = part[0];
+    for (int l = 0; l < a.nlev; ++l)
+        for (int k = threadIdx.x; k < a.nvert[l]; k += blockDim.x)
+            a.beta[l][k] = a.Tp * exp(-(a.Lz - k * a.hvert[l]) / a.rl) / Z;
+}
+
+dim3 node_grid(const Geo &g)
+{
+    return dim3((g.n[0] + kBX - 1) / kBX, (g.n[1] + kBY - 1) / kBY, g.n[2]);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+
+void launch_root_beta(int nlev, const int *nvert, const double *hvert, double *const *beta,
+                      double Lz, double Tp, double root_len, hipStream_t s)
+{
+    BetaArgs a;
+    a.nlev = nlev;
+    for (int l = 0; l < nlev; ++l) {
+        a.nvert[l] = nvert[l];
+        a.hvert[l] = hvert[l];
+        a.beta[l] = beta[l];
+    }
+    a.Lz = Lz;
+    a.Tp = Tp;
+    a.rl = root_len;
+    hipLaunchKernelGGL(k_root_beta, dim3(1), dim3(256), 0, s, a);
+}
+
+void launch_fill_u64(unsigned long long *p, int n, unsigned long long v, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill_u64, dim3((n + 63) / 64), dim3(64), 0, s, p, n, v);
+}
+
+void launch_setup_kstar(const Geo &g, const Law &law, const Step &st, const double *psi_n,
+                        const double *psi_nm1, const double *Ks_field, double *K, double *psi,
+                        hipStream_t s)
+{
+    hipLaunchKernelGGL(k_setup_kstar, node_grid(g), dim3(kBX, kBY), 0, s, g, law, st, psi_n,
+                       psi_nm1, Ks_field, K, psi);
+}
+
+void launch_setup_g(const Geo &g, const Law &law, const Step &st, const double *psi_n,
+                    const double *psi_nm1, const double *K, double *gvec, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_setup_g, node_grid(g), dim3(kBX, kBY), 0, s, g, law, st, psi_n, psi_nm1,
+                       K, gvec);
+}
+
+void launch_inject(const Geo &gc, const Geo &gf, const double *Kf, double *Kc, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_inject, node_grid(gc), dim3(kBX, kBY), 0, s, gc, gf, Kf, Kc);
+}
+
+void launch_lambda_u(const Geo &g, const double *K, unsigned long long *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_lambda_u, node_grid(g), dim3(kBX, kBY), 0, s, g, K, out);
+}
+
+void launch_sweep_rb(const Geo &g, const Law &law, const Step &st, const double *beta,
+                     double lambdaU, const double *K, const double *gvec, double *psi,
+                     int nsweeps, hipStream_t s)
+{
+    if (g.N <= 8192) {
+        hipLaunchKernelGGL(k_sweep_small, dim3(1), dim3(256), 0, s, g, law, st, beta, lambdaU, K,
+                           gvec, psi, nsweeps);
+        return;
+    }
+    int half = (g.n[0] + 1) / 2;
+    dim3 grid((half + kBX - 1) / kBX, (g.n[1] + kBY - 1) / kBY, g.n[2]);
+    for (int sw = 0; sw < nsweeps; ++sw)
+        for (int colour = 0; colour < 2; ++colour)
+            hipLaunchKernelGGL(k_sweep_colour, grid, dim3(kBX, kBY), 0, s, g, law, st, beta,
+                               lambdaU, K, gvec, psi, colour);
+}
+
+void launch_residual(const Geo &g, const Law &law, const Step &st, const double *beta,
+                     const double *K, const double *gvec, const double *psi, double *d,
+                     unsigned long long *norm_bits, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_residual, node_grid(g), dim3(kBX, kBY), 0, s, g, law, st, beta, K, gvec,
+                       psi, d, norm_bits);
+}
+
+void launch_restrict(const Geo &gc, const Geo &gf, const double *psi_f, const double *d_f,
+                     double *psibar_c, double *g_c, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_restrict, node_grid(gc), dim3(kBX, kBY), 0, s, gc, gf, psi_f, d_f,
+                       psibar_c, g_c);
+}
+
+void launch_coarse_rhs(const Geo &gc, const Law &law, const Step &st, const double *beta,
+                       const double *K, const double *psibar, double *gvec, double *psi,
+                       hipStream_t s)
+{
+    hipLaunchKernelGGL(k_coarse_rhs, node_grid(gc), dim3(kBX, kBY), 0, s, gc, law, st, beta, K,
+                       psibar, gvec, psi);
+}
+
+void launch_prolong(const Geo &gf, const Geo &gc, const double *psi_c, const double *psibar_c,
+                    double *psi_f, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_prolong, node_grid(gf), dim3(kBX, kBY), 0, s, gf, gc, psi_c, psibar_c,
+                       psi_f);
+}
+
+}  // namespace rs

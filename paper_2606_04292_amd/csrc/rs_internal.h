@@ -1,0 +1,87 @@
+// Internal structures shared by the kernels and the host orchestration of
+// the richards library.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rs {
+
+constexpr int kMaxLevels = 16;
+constexpr int kBcDirichlet = 1;
+constexpr int kBcNoflux = 2;
+constexpr int kBcFreedrain = 3;
+constexpr int kVgm = 1;
+constexpr int kHaverkamp = 2;
+constexpr int kLinear = 3;
+constexpr int kSinkFeddes = 1;
+constexpr int kKappaConst = 1;
+constexpr int kKappaRel = 2;
+constexpr int kKappaRemark = 3;
+
+// Geometry of one level, passed by value to every kernel.
+struct Geo {
+    int n[3];        // nodes per axis (1 beyond dim)
+    int dim;
+    int vert;        // vertical axis = dim - 1
+    int stride[3];   // 1, n0, n0*n1
+    long long N;     // total nodes
+    double h[3];
+    double ih2[3];   // 1 / h^2
+    int bc[6];       // face kinds
+    double bcval[6];
+    int pface;       // patch face or -1
+    int plo[2], phi[2];
+    double pval;
+};
+
+// Soil law and smoother parameters (by value).
+struct Law {
+    int model;
+    double ts, tr, Ks;
+    double dT;               // theta_s - theta_r
+    double vg_alpha, vg_n, vg_m;
+    double hk_alpha, hk_beta, hk_A, hk_gamma, unit;
+    double lin_c;
+    int sink;
+    double h1, h2, h3, h4;
+    double xi;
+    int kappa_rule;
+    double kappa;
+    int newton;
+};
+
+// Step coefficients (by value).
+struct Step {
+    double a;        // BDF leading coefficient: 1/dt or 3/(2 dt)
+    double dt;
+    int order;       // effective order (1 or 2)
+    int lag_extrap;  // BDF2 lag 2 psi^n - psi^{n-1}
+};
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (kernels_fp64.hip)
+// ---------------------------------------------------------------------------
+void launch_fill_u64(unsigned long long *p, int n, unsigned long long v, hipStream_t s);
+void launch_setup_kstar(const Geo &g, const Law &law, const Step &st, const double *psi_n,
+                        const double *psi_nm1, const double *Ks_field, double *K, double *psi,
+                        hipStream_t s);
+void launch_setup_g(const Geo &g, const Law &law, const Step &st, const double *psi_n,
+                    const double *psi_nm1, const double *K, double *gvec, hipStream_t s);
+void launch_inject(const Geo &gc, const Geo &gf, const double *Kf, double *Kc, hipStream_t s);
+void launch_lambda_u(const Geo &g, const double *K, unsigned long long *out, hipStream_t s);
+void launch_sweep_rb(const Geo &g, const Law &law, const Step &st, const double *beta,
+                     double lambdaU, const double *K, const double *gvec, double *psi,
+                     int nsweeps, hipStream_t s);
+void launch_residual(const Geo &g, const Law &law, const Step &st, const double *beta,
+                     const double *K, const double *gvec, const double *psi, double *d,
+                     unsigned long long *norm_bits, hipStream_t s);
+void launch_restrict(const Geo &gc, const Geo &gf, const double *psi_f, const double *d_f,
+                     double *psibar_c, double *g_c, hipStream_t s);
+void launch_coarse_rhs(const Geo &gc, const Law &law, const Step &st, const double *beta,
+                       const double *K, const double *psibar, double *gvec, double *psi,
+                       hipStream_t s);
+void launch_prolong(const Geo &gf, const Geo &gc, const double *psi_c, const double *psibar_c,
+                    double *psi_f, hipStream_t s);
+
+}  // namespace rs
