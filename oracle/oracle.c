@@ -465,8 +465,10 @@ static void compute_lambdaU(orc_solver *S, orc_level *lv)
  * The paper asks for "a few (damped) Newton steps with optional
  * backtracking"; reading: exactly `iters` Newton steps from x0, each kept
  * inside a bracket [lo, hi] that holds the root (initially
- * [(f - a theta_s - beta)/c, (f - a theta_r)/c], tightened by the sign of F
- * at every iterate); a step that does not land strictly inside the bracket,
+ * [(f - a theta_s - beta)/c, (f - a theta_r)/c], widened by 1e-12 of the sum
+ * of the ends' magnitudes so that a root on an end -- a saturated cell, where
+ * F is linear and its root is the lower end -- lies strictly inside;
+ * tightened by the sign of F at every iterate); a step that does not land strictly inside the bracket,
  * or a non-positive F', is replaced by bisection, except a step that leaves
  * the iterate unchanged (below rounding resolution), which is kept so that a
  * converged cell stays put.  Landing on a bracket end is rejected because a
@@ -481,6 +483,9 @@ double orc_local_solve(const orc_params *p, double a, double beta, double c, dou
     } else {
         lo = (f - a * p->theta_s - beta) / c;
         hi = (f - a * p->theta_r) / c;
+        double pad = 1e-12 * (fabs(lo) + fabs(hi));
+        lo -= pad;
+        hi += pad;
     }
     double x = x0;
     for (int k = 0; k < iters; k++) {

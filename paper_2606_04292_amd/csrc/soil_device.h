@@ -84,8 +84,10 @@ __device__ __forceinline__ void feddes(const Law &L, double x, double &a, double
 // Pointwise equation of the NGS update (eq. point-update with the BDF
 // coefficient a and sink beta * a_F):  a theta(x) + beta a_F(x) + c x = f.
 // Exactly L.newton safeguarded Newton steps from x0: the root stays inside
-// [lo, hi] (initially [(f - a theta_s - beta)/c, (f - a theta_r)/c], narrowed
-// by the sign of F at each iterate); a step that does not land strictly
+// [lo, hi] (initially [(f - a theta_s - beta)/c, (f - a theta_r)/c] widened by
+// 1e-12 of the ends' magnitudes, so that the root of a saturated cell -- the
+// lower end, F being linear there -- lies strictly inside; narrowed by the
+// sign of F at each iterate); a step that does not land strictly
 // inside, or a non-positive F', becomes a bisection, unless the step leaves
 // the iterate unchanged.
 __device__ __forceinline__ double local_solve(const Law &L, double a, double beta, double c,
@@ -98,6 +100,9 @@ __device__ __forceinline__ double local_solve(const Law &L, double a, double bet
     } else {
         lo = (f - a * L.ts - beta) / c;
         hi = (f - a * L.tr) / c;
+        double pad = 1e-12 * (fabs(lo) + fabs(hi));
+        lo -= pad;
+        hi += pad;
     }
     double x = x0;
     for (int k = 0; k < L.newton; ++k) {

@@ -195,3 +195,21 @@ def test_solution_is_a_fixed_point_of_the_sweep(orc, ordering):
     x = S.psi().copy()
     S.sweep(2)
     assert np.abs(S.psi() - x).max() <= 1e-13
+
+
+@pytest.mark.parametrize("k", range(len(LAWS)))
+def test_saturated_cell_root_on_the_bracket_end(orc, k):
+    """For psi >= 0 theta = theta_s and F is linear, with its root exactly at the
+    lower end of the initial bracket; the safeguarded Newton must return that
+    root (one exact Newton step), not a bisection point."""
+    law = LAWS[k]
+    for _ in range(50):
+        a = 10 ** RNG.uniform(-4, -1)
+        c = 10 ** RNG.uniform(-6, 0)
+        root = RNG.uniform(0.0, 2.0)
+        f = a * law.theta_s + c * root
+        x0 = RNG.uniform(-1.0, 3.0) if k != 3 else RNG.uniform(0.0, 3.0)
+        x = orc.local_solve(law, a, 0.0, c, f, abs(x0) + 1e-3, 3)
+        exact = (f - a * law.theta_s) / c
+        cond = np.finfo(float).eps * (abs(f) + a * law.theta_s + c * abs(x0)) / c
+        assert abs(x - exact) <= 16 * cond + 1e-15
