@@ -137,6 +137,7 @@ typedef struct rs_step_stats {
     double res0, res;     /* residual max-norm before and after */
     int n_hist;
     double res_hist[64];  /* residual norm before each cycle and after the last */
+    double cell_updates;  /* pointwise NGS updates in this step, all levels */
 } rs_step_stats;
 
 typedef struct rs_grid rs_grid;
@@ -206,6 +207,15 @@ int rs_set_field(rs_grid *g, int level, int field, const double *src_dev);
 /* Level count and per-level node counts (n_out: 3 ints). */
 int rs_num_levels(const rs_grid *g);
 int rs_level_shape(const rs_grid *g, int level, int *n_out);
+
+/* Instrumentation: when enabled, HIP events on the grid stream bracket every
+ * batch of finest-level sweep launches; rs_profile_read returns their summed
+ * elapsed time (ms), the number of kernel launches (one per colour per sweep)
+ * and the pointwise updates they performed, accumulated since the last reset.
+ * Reading synchronises the stream. */
+int rs_profile_enable(rs_grid *g, int on);
+int rs_profile_read(rs_grid *g, double *sweep_ms, long long *launches, double *cell_updates,
+                    int reset);
 
 void rs_destroy_grid(rs_grid *g);
 const char *rs_last_error(void);

@@ -27,6 +27,7 @@ EXPORTS = [
     "rs_get_state", "rs_begin_step", "rs_sweep", "rs_vcycle", "rs_residual_norm",
     "rs_residual", "rs_end_step", "rs_bdf_step", "rs_copy_field", "rs_set_field",
     "rs_num_levels", "rs_level_shape", "rs_destroy_grid", "rs_last_error",
+    "rs_profile_enable", "rs_profile_read",
 ]
 
 
@@ -64,7 +65,7 @@ class SolveOpts(C.Structure):
 class StepStats(C.Structure):
     _fields_ = [("struct_size", C.c_size_t), ("cycles", C.c_int), ("status", C.c_int),
                 ("res0", C.c_double), ("res", C.c_double), ("n_hist", C.c_int),
-                ("res_hist", C.c_double * 64)]
+                ("res_hist", C.c_double * 64), ("cell_updates", C.c_double)]
 
 
 _lib = None
@@ -98,6 +99,8 @@ def lib():
         L.rs_num_levels.argtypes = [vp]
         L.rs_level_shape.argtypes = [vp, C.c_int, I]
         L.rs_destroy_grid.argtypes = [vp]
+        L.rs_profile_enable.argtypes = [vp, C.c_int]
+        L.rs_profile_read.argtypes = [vp, D, C.POINTER(C.c_longlong), D, C.c_int]
         _lib = L
     return _lib
 
@@ -276,3 +279,15 @@ class Grid:
 
     def psi(self, level=0):
         return self.field(FIELD_PSI, level)
+
+    def profile_enable(self, on=True):
+        check(lib().rs_profile_enable(self.h, 1 if on else 0))
+
+    def profile_read(self, reset=True):
+        """(finest-level sweep ms, kernel launches, pointwise updates)."""
+        ms = C.c_double()
+        n = C.c_longlong()
+        cells = C.c_double()
+        check(lib().rs_profile_read(self.h, C.byref(ms), C.byref(n), C.byref(cells),
+                                    1 if reset else 0))
+        return ms.value, n.value, cells.value

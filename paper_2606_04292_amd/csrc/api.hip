@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "../../include/richards.h"
 #include "rs_internal.h"
@@ -170,7 +171,47 @@ struct LevelData {
     Geo geo;
     double *psi, *K, *g, *d, *psibar, *beta;
     double lambdaU;
+    long long unknowns;
 };
+
+// Unknown (non-Dirichlet) nodes of a level, counted on the host from the same
+// index rules the kernels use.
+long long count_unknowns(const Geo &g)
+{
+    long long dirichlet = 0;
+    for (int k = 0; k < g.n[2]; ++k)
+        for (int j = 0; j < g.n[1]; ++j) {
+            // a row off the boundary of axes 1 and 2 has only its two end nodes
+            // on the domain boundary
+            bool row_on_boundary = (g.dim > 1 && (j == 0 || j == g.n[1] - 1)) ||
+                                   (g.dim > 2 && (k == 0 || k == g.n[2] - 1));
+            int step = row_on_boundary ? 1 : (g.n[0] - 1);
+            for (int i = 0; i < g.n[0]; i += step) {
+                int c[3] = {i, j, k};
+                bool dir = false;
+                for (int l = 0; l < g.dim; ++l) {
+                    if (c[l] == 0 && g.bc[2 * l] == kBcDirichlet) dir = true;
+                    if (c[l] == g.n[l] - 1 && g.bc[2 * l + 1] == kBcDirichlet) dir = true;
+                }
+                if (g.pface >= 0) {
+                    int ax = g.pface >> 1;
+                    int at = (g.pface & 1) ? g.n[ax] - 1 : 0;
+                    if (c[ax] == at) {
+                        bool in = true;
+                        int t = 0;
+                        for (int l = 0; l < g.dim; ++l) {
+                            if (l == ax) continue;
+                            if (c[l] < g.plo[t] || c[l] > g.phi[t]) in = false;
+                            ++t;
+                        }
+                        if (in) dir = true;
+                    }
+                }
+                dirichlet += dir ? 1 : 0;
+            }
+        }
+    return g.N - dirichlet;
+}
 
 }  // namespace
 
@@ -192,6 +233,14 @@ struct rs_grid {
     int nstep;
     double t;
     int nu_coarse;
+    double updates;                   // pointwise updates since the step began
+    bool prof_on;
+    std::vector<hipEvent_t> prof_ev;  // start/stop pairs of finest-level sweeps
+    std::vector<int> prof_sweeps;
+    size_t prof_used;
+    double prof_ms;
+    long long prof_launches;
+    double prof_cells;
 };
 
 namespace {
@@ -259,11 +308,55 @@ int validate_law(const rs_constitutive *c)
     return RS_OK;
 }
 
+int harvest_profile(rs_grid *G)
+{
+    for (size_t q = 0; q < G->prof_used; ++q) {
+        float ms = 0.f;
+        HIPCALL(hipEventElapsedTime(&ms, G->prof_ev[2 * q], G->prof_ev[2 * q + 1]));
+        G->prof_ms += ms;
+        G->prof_launches += 2LL * G->prof_sweeps[q];
+        G->prof_cells += (double)G->prof_sweeps[q] * (double)G->lev[0].unknowns;
+    }
+    G->prof_used = 0;
+    return RS_OK;
+}
+
+// nsweeps red-black sweeps on level l, counted, and timed on the finest level
+// when profiling is on.
+int sweep_level(rs_grid *G, int l, int nsweeps)
+{
+    LevelData &f = G->lev[l];
+    bool timed = G->prof_on && l == 0 && nsweeps > 0;
+    if (timed) {
+        if (2 * (G->prof_used + 1) > G->prof_ev.size()) {
+            for (int e = 0; e < 2; ++e) {
+                hipEvent_t ev;
+                HIPCALL(hipEventCreate(&ev));
+                G->prof_ev.push_back(ev);
+            }
+            G->prof_sweeps.push_back(0);
+        }
+        HIPCALL(hipEventRecord(G->prof_ev[2 * G->prof_used], G->stream));
+    }
+    launch_sweep_rb(f.geo, G->law, G->step, f.beta, f.lambdaU, f.K, f.g, f.psi, nsweeps, G->stream);
+    if (timed) {
+        HIPCALL(hipEventRecord(G->prof_ev[2 * G->prof_used + 1], G->stream));
+        G->prof_sweeps[G->prof_used] = nsweeps;
+        G->prof_used += 1;
+    }
+    G->updates += (double)nsweeps * (double)f.unknowns;
+    return RS_OK;
+}
+
 int read_norm(rs_grid *G, double *out)
 {
     HIPCALL(hipMemcpyAsync(G->host_bits, G->scratch, sizeof(unsigned long long),
                            hipMemcpyDeviceToHost, G->stream));
     HIPCALL(hipStreamSynchronize(G->stream));
+    if (G->prof_used) {
+        int e = harvest_profile(G);
+        if (e) return e;
+    }
     unsigned long long b = G->host_bits[0];
     double v;
     memcpy(&v, &b, sizeof v);
@@ -280,22 +373,20 @@ int fine_norm(rs_grid *G, double *out)
     return read_norm(G, out);
 }
 
-void vcycle_level(rs_grid *G, int l, int nu1, int nu2)
+int vcycle_level(rs_grid *G, int l, int nu1, int nu2)
 {
     LevelData &f = G->lev[l];
-    if (l == G->nlev - 1) {
-        launch_sweep_rb(f.geo, G->law, G->step, f.beta, f.lambdaU, f.K, f.g, f.psi, G->nu_coarse,
-                        G->stream);
-        return;
-    }
+    if (l == G->nlev - 1) return sweep_level(G, l, G->nu_coarse);
     LevelData &c = G->lev[l + 1];
-    launch_sweep_rb(f.geo, G->law, G->step, f.beta, f.lambdaU, f.K, f.g, f.psi, nu1, G->stream);
+    int e = sweep_level(G, l, nu1);
+    if (e) return e;
     launch_residual(f.geo, G->law, G->step, f.beta, f.K, f.g, f.psi, f.d, nullptr, G->stream);
     launch_restrict(c.geo, f.geo, f.psi, f.d, c.psibar, c.g, G->stream);
     launch_coarse_rhs(c.geo, G->law, G->step, c.beta, c.K, c.psibar, c.g, c.psi, G->stream);
-    vcycle_level(G, l + 1, nu1, nu2);
+    e = vcycle_level(G, l + 1, nu1, nu2);
+    if (e) return e;
     launch_prolong(f.geo, c.geo, c.psi, c.psibar, f.psi, G->stream);
-    launch_sweep_rb(f.geo, G->law, G->step, f.beta, f.lambdaU, f.K, f.g, f.psi, nu2, G->stream);
+    return sweep_level(G, l, nu2);
 }
 
 double *field_ptr(const rs_grid *G, int level, int field)
@@ -359,6 +450,7 @@ int rs_create_grid(const rs_grid_desc *d, int precision, void *ws_dev, size_t ws
         v.psibar = (double *)(base + L.lev_off[l][4]);
         v.beta = (double *)(base + L.beta_off[l]);
         v.lambdaU = 0.0;
+        v.unknowns = count_unknowns(v.geo);
     }
     G->psi_n = (double *)(base + L.psi_n);
     G->psi_nm1 = (double *)(base + L.psi_nm1);
@@ -370,6 +462,12 @@ int rs_create_grid(const rs_grid_desc *d, int precision, void *ws_dev, size_t ws
     G->nstep = 0;
     G->t = 0.0;
     G->nu_coarse = 32;
+    G->updates = 0.0;
+    G->prof_on = false;
+    G->prof_used = 0;
+    G->prof_ms = 0.0;
+    G->prof_launches = 0;
+    G->prof_cells = 0.0;
     if (hipHostMalloc((void **)&G->host_bits, 64 * sizeof(unsigned long long), hipHostMallocDefault) !=
         hipSuccess) {
         delete G;
@@ -382,6 +480,8 @@ int rs_create_grid(const rs_grid_desc *d, int precision, void *ws_dev, size_t ws
 void rs_destroy_grid(rs_grid *G)
 {
     if (!G) return;
+    if (G->prof_used) (void)hipStreamSynchronize(G->stream);
+    for (hipEvent_t ev : G->prof_ev) (void)hipEventDestroy(ev);
     if (G->host_bits) (void)hipHostFree(G->host_bits);
     delete G;
 }
@@ -484,8 +584,8 @@ int rs_sweep(rs_grid *G, int level, int nsweeps)
     if (!G->in_step) return fail(RS_ESTATE, "no active step (call rs_begin_step)");
     if (level < 0 || level >= G->nlev) return fail(RS_EINVAL, "level out of range");
     if (nsweeps < 0) return fail(RS_EINVAL, "nsweeps < 0");
-    LevelData &f = G->lev[level];
-    launch_sweep_rb(f.geo, G->law, G->step, f.beta, f.lambdaU, f.K, f.g, f.psi, nsweeps, G->stream);
+    int e = sweep_level(G, level, nsweeps);
+    if (e) return e;
     HIPCALL(hipGetLastError());
     return RS_OK;
 }
@@ -495,7 +595,8 @@ int rs_vcycle(rs_grid *G, int nu1, int nu2, double *res)
     if (!G) return fail(RS_EINVAL, "null grid");
     if (!G->in_step) return fail(RS_ESTATE, "no active step (call rs_begin_step)");
     if (nu1 < 0 || nu2 < 0) return fail(RS_EINVAL, "negative smoothing count");
-    vcycle_level(G, 0, nu1, nu2);
+    int e = vcycle_level(G, 0, nu1, nu2);
+    if (e) return e;
     HIPCALL(hipGetLastError());
     if (res) return fine_norm(G, res);
     return RS_OK;
@@ -554,8 +655,10 @@ int rs_bdf_step(rs_grid *G, double dt, int order, const rs_solve_opts *o, rs_ste
     double hist[64];
     hist[nh++] = r;
     bool stagnated = false;
+    G->updates = 0.0;
     while (std::isfinite(r) && r > o->tol_abs && cycles < o->max_cycles) {
-        vcycle_level(G, 0, o->nu1, o->nu2);
+        e = vcycle_level(G, 0, o->nu1, o->nu2);
+        if (e) return e;
         HIPCALL(hipGetLastError());
         double rn;
         e = fine_norm(G, &rn);
@@ -578,6 +681,7 @@ int rs_bdf_step(rs_grid *G, double dt, int order, const rs_solve_opts *o, rs_ste
         st->res = r;
         st->n_hist = nh;
         memcpy(st->res_hist, hist, sizeof(double) * nh);
+        st->cell_updates = G->updates;
     }
     if (status != RS_OK) {
         return fail(status, status == RS_ENONFINITE ? "residual is not finite"
@@ -605,6 +709,30 @@ int rs_set_field(rs_grid *G, int level, int field, const double *src)
     if (!p) return fail(RS_EINVAL, "unknown field %d", field);
     HIPCALL(hipMemcpyAsync(p, src, sizeof(double) * (size_t)G->lev[level].geo.N,
                            hipMemcpyDeviceToDevice, G->stream));
+    return RS_OK;
+}
+
+int rs_profile_enable(rs_grid *G, int on)
+{
+    if (!G) return fail(RS_EINVAL, "null grid");
+    G->prof_on = on != 0;
+    return RS_OK;
+}
+
+int rs_profile_read(rs_grid *G, double *sweep_ms, long long *launches, double *cells, int reset)
+{
+    if (!G) return fail(RS_EINVAL, "null grid");
+    HIPCALL(hipStreamSynchronize(G->stream));
+    int e = harvest_profile(G);
+    if (e) return e;
+    if (sweep_ms) *sweep_ms = G->prof_ms;
+    if (launches) *launches = G->prof_launches;
+    if (cells) *cells = G->prof_cells;
+    if (reset) {
+        G->prof_ms = 0.0;
+        G->prof_launches = 0;
+        G->prof_cells = 0.0;
+    }
     return RS_OK;
 }
 
