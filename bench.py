@@ -37,6 +37,14 @@ def gpu_run(args):
     from paper_2606_04292_amd import workloads as W
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        # a plain device copy of known size, for scaling HBM byte counters
+        src = torch.empty(64 << 20, dtype=torch.float64, device="cuda:0").fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: %d bytes read, %d bytes written" % (src.numel() * 8, src.numel() * 8))
+        del src, dst
     w = W.config3(args.n)
     G = rsl.Grid(w, device="cuda:0")
     opts = rsl.solve_opts(w.nu1, w.nu2, w.nu_coarse, max_cycles=args.max_cycles,
@@ -115,6 +123,8 @@ def main():
     ap.add_argument("--max-cycles", type=int, default=40)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one 512 MiB device copy first (counter calibration)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

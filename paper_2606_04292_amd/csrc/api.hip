@@ -137,7 +137,7 @@ Geo make_geo(const rs_grid_desc *d, int lev)
 // density table; fine-level history psi^n, psi^{n-1}, the Ks field; scratch.
 struct Layout {
     int nlev;
-    size_t lev_off[kMaxLevels][5];
+    size_t lev_off[kMaxLevels][6];   // psi, K, g, d, psibar, psi_alt (fused levels)
     size_t beta_off[kMaxLevels];
     size_t psi_n, psi_nm1, ks, scratch;
     size_t total;
@@ -156,6 +156,11 @@ void plan(const rs_grid_desc *d, int precision, Layout *L)
             L->lev_off[l][a] = off;
             off = align_up(off + sizeof(double) * (size_t)g.N);
         }
+        L->lev_off[l][5] = 0;
+        if (fused_sweep_level(g)) {
+            L->lev_off[l][5] = off;
+            off = align_up(off + sizeof(double) * (size_t)g.N);
+        }
         L->beta_off[l] = off;
         off = align_up(off + sizeof(double) * (size_t)g.n[g.vert]);
     }
@@ -170,6 +175,7 @@ void plan(const rs_grid_desc *d, int precision, Layout *L)
 struct LevelData {
     Geo geo;
     double *psi, *K, *g, *d, *psibar, *beta;
+    double *psi_alt;   // second psi buffer of the fused sweep (or null)
     double lambdaU;
     long long unknowns;
 };
@@ -237,6 +243,7 @@ struct rs_grid {
     bool prof_on;
     std::vector<hipEvent_t> prof_ev;  // start/stop pairs of finest-level sweeps
     std::vector<int> prof_sweeps;
+    std::vector<int> prof_launch;
     size_t prof_used;
     double prof_ms;
     long long prof_launches;
@@ -314,7 +321,7 @@ int harvest_profile(rs_grid *G)
         float ms = 0.f;
         HIPCALL(hipEventElapsedTime(&ms, G->prof_ev[2 * q], G->prof_ev[2 * q + 1]));
         G->prof_ms += ms;
-        G->prof_launches += 2LL * G->prof_sweeps[q];
+        G->prof_launches += G->prof_launch[q];
         G->prof_cells += (double)G->prof_sweeps[q] * (double)G->lev[0].unknowns;
     }
     G->prof_used = 0;
@@ -335,13 +342,16 @@ int sweep_level(rs_grid *G, int l, int nsweeps)
                 G->prof_ev.push_back(ev);
             }
             G->prof_sweeps.push_back(0);
+            G->prof_launch.push_back(0);
         }
         HIPCALL(hipEventRecord(G->prof_ev[2 * G->prof_used], G->stream));
     }
-    launch_sweep_rb(f.geo, G->law, G->step, f.beta, f.lambdaU, f.K, f.g, f.psi, nsweeps, G->stream);
+    int launches = launch_sweep_rb(f.geo, G->law, G->step, f.beta, f.lambdaU, f.K, f.g, &f.psi,
+                                   &f.psi_alt, nsweeps, G->stream);
     if (timed) {
         HIPCALL(hipEventRecord(G->prof_ev[2 * G->prof_used + 1], G->stream));
         G->prof_sweeps[G->prof_used] = nsweeps;
+        G->prof_launch[G->prof_used] = launches;
         G->prof_used += 1;
     }
     G->updates += (double)nsweeps * (double)f.unknowns;
@@ -448,6 +458,7 @@ int rs_create_grid(const rs_grid_desc *d, int precision, void *ws_dev, size_t ws
         v.g = (double *)(base + L.lev_off[l][2]);
         v.d = (double *)(base + L.lev_off[l][3]);
         v.psibar = (double *)(base + L.lev_off[l][4]);
+        v.psi_alt = L.lev_off[l][5] ? (double *)(base + L.lev_off[l][5]) : nullptr;
         v.beta = (double *)(base + L.beta_off[l]);
         v.lambdaU = 0.0;
         v.unknowns = count_unknowns(v.geo);

@@ -8,6 +8,10 @@
 // (eq. discrete-strong with arithmetic face averages; the matrix M of
 // section 2).  Node kinds come from indices, so a sweep moves only psi, K*
 // and g (8 B each per node) plus the psi write.
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+
 #include "rs_internal.h"
 #include "soil_device.h"
 
@@ -188,22 +192,74 @@ __global__ __launch_bounds__(256) void k_lambda_u(Geo g, const double *K, unsign
 // Red-black NGS (eq. iterative / eq. point-update)
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ void ngs_update(const Geo &g, const Law &L, const Step &st,
-                                           const double *beta, double lambdaU, const double *K,
-                                           const double *gv, double *psi, int i, int j, int k,
-                                           int colour)
+// Work-groups are dispatched round-robin over the 8 XCDs; renumber them so that
+// XCD x runs the contiguous logical range [x per, (x+1) per) and its L2 sees a
+// compact slab of the grid (neighbouring rows and planes hit in L2).  The grid
+// is padded to a multiple of 8; padded groups fall past the last cell.
+__device__ __forceinline__ unsigned xcd_block(unsigned per)
 {
-    long long idx = i + (long long)j * g.stride[1] + (long long)k * g.stride[2];
-    int c[3] = {i, j, k};
-    double Ki = K[idx];
+    return (blockIdx.x % 8u) * per + blockIdx.x / 8u;
+}
+
+unsigned xcd_grid(unsigned long long blocks) { return (unsigned)((blocks + 7) / 8 * 8); }
+
+// Packed enumeration of the cells of one colour: rows (fixed j, k) of
+// H = (n0 + 1) / 2 slots, slot ih -> i = 2 ih + parity; every lane of a wave
+// holds a cell (only the last slot of odd-parity rows falls outside).
+struct ColourMap {
+    unsigned long long total;
+    unsigned H;
+    double invH;
+    unsigned n1;
+    double invN1;
+};
+
+ColourMap colour_map(const Geo &g)
+{
+    ColourMap m;
+    m.H = (unsigned)((g.n[0] + 1) / 2);
+    m.invH = 1.0 / m.H;
+    m.n1 = (unsigned)g.n[1];
+    m.invN1 = 1.0 / m.n1;
+    m.total = (unsigned long long)m.H * g.n[1] * g.n[2];
+    return m;
+}
+
+// Visit the neighbours of node (i, j, k) along the first DIM axes in the
+// order axis 0 low/high, axis 1 low/high, axis 2 low/high; fn(jdx, coef, axis,
+// side) with coef = 1/(2 w h^2).
+template <int DIM, typename Fn>
+__device__ __forceinline__ void for_nb(const Geo &g, int i, int j, int k, long long idx, Fn &&fn)
+{
+#pragma unroll
+    for (int l = 0; l < DIM; ++l) {
+        const int cl = (l == 0) ? i : (l == 1 ? j : k);
+        const double cf = ((cl == 0 || cl == g.n[l] - 1) ? 1.0 : 0.5) * g.ih2[l];
+        const long long s = g.stride[l];
+        if (cl > 0) fn(idx - s, cf, l, -1);
+        if (cl < g.n[l] - 1) fn(idx + s, cf, l, +1);
+    }
+}
+
+// New value of unknown (i, j, k) from eq. point-update: f_i = g_i +
+// sum_j m_ij psi_j + kappa_i psi_i, c_i = xi + kappa_i + m_ii, then the
+// safeguarded Newton solve.  nbv(jdx, axis, side) supplies the current value of
+// each neighbour (the previous colour's new values, the other colour's old).
+template <int MODEL, bool SINK, int DIM, typename NbVal>
+__device__ __forceinline__ double ngs_value(const Geo &g, const Law &L, double a,
+                                            const double *beta, double lambdaU, const double *K,
+                                            const double *gv, int i, int j, int k, long long idx,
+                                            int colour, double x0, NbVal &&nbv)
+{
+    const double Ki = K[idx];
     double f = gv[idx];
     double mii = 0.0, usum = 0.0;
-    const bool remark = (L.kappa_rule == kKappaRemark);
-    for_each_nb(g, c, idx, [&](long long jn, double cf, int l, int side) {
+    const bool remark = (L.kappa_rule == kKappaRemark) && colour == 0;
+    for_nb<DIM>(g, i, j, k, idx, [&](long long jn, double cf, int l, int side) {
         double m = cf * (Ki + K[jn]);
         mii += m;
-        f += m * psi[jn];
-        if (remark && colour == 0) {
+        f += m * nbv(jn, l, side);
+        if (remark) {
             int d[3] = {i, j, k};
             d[l] += side;
             if (!dirichlet_at(g, d[0], d[1], d[2], nullptr)) usum += m;
@@ -213,28 +269,155 @@ __device__ __forceinline__ void ngs_update(const Geo &g, const Law &L, const Ste
     if (L.kappa_rule == kKappaConst) kap = L.kappa;
     else if (L.kappa_rule == kKappaRel) kap = L.kappa * mii;
     else kap = (colour == 0) ? lambdaU - usum : lambdaU;
-    double x0 = psi[idx];
     f += kap * x0;
-    double cc = L.xi + kap + mii;
-    double b = sink_beta(L, beta, c, g.vert);
-    psi[idx] = local_solve(L, st.a, b, cc, f, x0);
+    const double cc = L.xi + kap + mii;
+    const int vk = (DIM == 1) ? i : (DIM == 2 ? j : k);
+    const double b = SINK ? beta[vk] : 0.0;
+    if (L.newton == 3) return local_solve_t<MODEL, SINK, 3>(L, a, b, cc, f, x0);
+    return local_solve_t<MODEL, SINK, 0>(L, a, b, cc, f, x0);
 }
 
-__global__ __launch_bounds__(256) void k_sweep_colour(Geo g, Law L, Step st, const double *beta,
-                                                      double lambdaU, const double *K,
-                                                      const double *gv, double *psi, int colour)
+template <int MODEL, bool SINK, int DIM>
+__device__ __forceinline__ void ngs_cell(const Geo &g, const Law &L, double a, const double *beta,
+                                         double lambdaU, const double *K, const double *gv,
+                                         double *psi, int i, int j, int k, int colour)
 {
-    int j = blockIdx.y * kBY + threadIdx.y;
-    int k = blockIdx.z;
-    if (j >= g.n[1]) return;
-    int i = 2 * (blockIdx.x * kBX + threadIdx.x) + ((j + k + colour) & 1);
-    if (i >= g.n[0]) return;
-    if (dirichlet_at(g, i, j, k, nullptr)) return;
-    ngs_update(g, L, st, beta, lambdaU, K, gv, psi, i, j, k, colour);
+    const long long idx = i + (long long)j * g.stride[1] + (long long)k * g.stride[2];
+    psi[idx] = ngs_value<MODEL, SINK, DIM>(g, L, a, beta, lambdaU, K, gv, i, j, k, idx, colour,
+                                           psi[idx],
+                                           [&](long long jn, int, int) { return psi[jn]; });
 }
 
-// Whole sweeps of a small level in one work-group (coarse levels, where
+// ---------------------------------------------------------------------------
+// Fused red-black sweep for 3-D levels.  A work-group owns a tile
+// [X0,X1) x [Y0,Y1) of a z-chunk [Z0,Z1) and marches up it: at plane k it
+// computes the red values of plane k on the tile and a one-node ring around
+// it (the ring is recomputed by the neighbouring tiles too), keeping them in a
+// three-plane LDS ring, then the black values of plane k-1 on the tile from
+// those red values.  Red updates read the old values from pin, the new values
+// go to pout; every node of the level is written exactly once by its owner, so
+// there is no inter-group ordering and a sweep reads psi, K* and g once.
+// Work-groups are numbered so that each XCD gets a contiguous z-slab.
+// ---------------------------------------------------------------------------
+
+struct FusedMap {
+    int TX, TY, ZC;      // base tile extent (the last tile on an axis takes the remainder)
+    int ntx, nty, ntz;
+    int nwg, per;        // work-groups, logical groups per XCD
+    int P, Hs;           // LDS plane pitch and rows
+};
+
+template <int MODEL, bool SINK>
+__global__ __launch_bounds__(256) void k_sweep_fused(Geo g, Law L, Step st, const double *beta,
+                                                     double lambdaU, const double *K,
+                                                     const double *gv, const double *pin,
+                                                     double *pout, FusedMap fm)
+{
+    extern __shared__ double red[];
+    const unsigned b = (blockIdx.x % 8u) * (unsigned)fm.per + blockIdx.x / 8u;
+    if ((int)b >= fm.nwg) return;
+    const int bx = (int)b % fm.ntx;
+    const int rest = (int)b / fm.ntx;
+    const int by = rest % fm.nty;
+    const int bz = rest / fm.nty;
+    const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
+    const int X0 = bx * fm.TX, X1 = (bx == fm.ntx - 1) ? n0 : X0 + fm.TX;
+    const int Y0 = by * fm.TY, Y1 = (by == fm.nty - 1) ? n1 : Y0 + fm.TY;
+    const int Z0 = bz * fm.ZC, Z1 = (bz == fm.ntz - 1) ? n2 : Z0 + fm.ZC;
+    const int EX0 = X0 > 0 ? X0 - 1 : 0, EX1 = X1 < n0 ? X1 + 1 : n0;
+    const int EY0 = Y0 > 0 ? Y0 - 1 : 0, EY1 = Y1 < n1 ? Y1 + 1 : n1;
+    const int slot_sz = fm.P * fm.Hs;
+    const long long s1 = g.stride[1], s2 = g.stride[2];
+    const int tid = threadIdx.x;
+    const int kfirst = Z0 > 0 ? Z0 - 1 : 0;
+    const int klast = Z1 < n2 ? Z1 : n2 - 1;
+
+    for (int k = kfirst; k <= Z1; ++k) {
+        if (k <= klast) {
+            // red nodes of plane k: tile plus ring inside the chunk, tile only
+            // on the extra planes below and above it
+            const bool inner = (k >= Z0 && k < Z1);
+            const int rx0 = inner ? EX0 : X0, rx1 = inner ? EX1 : X1;
+            const int ry0 = inner ? EY0 : Y0, ry1 = inner ? EY1 : Y1;
+            const int ps = (rx1 - rx0 + 1) >> 1;
+            const int nq = ps * (ry1 - ry0);
+            double *slot = red + (k % 3) * slot_sz;
+            for (int q = tid; q < nq; q += blockDim.x) {
+                const int r = q / ps;
+                const int y = ry0 + r;
+                const int x = rx0 + ((rx0 + y + k) & 1) + 2 * (q - r * ps);
+                if (x >= rx1) continue;
+                const long long idx = x + y * s1 + k * s2;
+                const double old = pin[idx];
+                double v = old;
+                if (!dirichlet_at(g, x, y, k, nullptr))
+                    v = ngs_value<MODEL, SINK, 3>(g, L, st.a, beta, lambdaU, K, gv, x, y, k, idx, 0,
+                                                  old,
+                                                  [&](long long jn, int, int) { return pin[jn]; });
+                slot[(y - EY0) * fm.P + (x - EX0)] = v;
+                if (inner && x >= X0 && x < X1 && y >= Y0 && y < Y1) pout[idx] = v;
+            }
+        }
+        __syncthreads();
+        const int kb = k - 1;
+        if (kb >= Z0 && kb < Z1) {
+            // black nodes of plane kb on the tile, red neighbours from LDS
+            const double *sl_m = red + ((kb + 2) % 3) * slot_sz;   // plane kb-1
+            const double *sl_0 = red + (kb % 3) * slot_sz;         // plane kb
+            const double *sl_p = red + ((kb + 1) % 3) * slot_sz;   // plane kb+1
+            const int ps = (X1 - X0 + 1) >> 1;
+            const int nq = ps * (Y1 - Y0);
+            for (int q = tid; q < nq; q += blockDim.x) {
+                const int r = q / ps;
+                const int y = Y0 + r;
+                const int x = X0 + ((X0 + y + kb + 1) & 1) + 2 * (q - r * ps);
+                if (x >= X1) continue;
+                const long long idx = x + y * s1 + kb * s2;
+                const double old = pin[idx];
+                double v = old;
+                if (!dirichlet_at(g, x, y, kb, nullptr)) {
+                    const int c = (y - EY0) * fm.P + (x - EX0);
+                    v = ngs_value<MODEL, SINK, 3>(
+                        g, L, st.a, beta, lambdaU, K, gv, x, y, kb, idx, 1, old,
+                        [&](long long, int l, int side) {
+                            if (l == 0) return sl_0[c + side];
+                            if (l == 1) return sl_0[c + side * fm.P];
+                            return side < 0 ? sl_m[c] : sl_p[c];
+                        });
+                }
+                pout[idx] = v;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <int MODEL, bool SINK, int DIM>
+__global__ __launch_bounds__(256) void k_sweep(Geo g, Law L, Step st, const double *beta,
+                                               double lambdaU, const double *K, const double *gv,
+                                               double *psi, int colour, ColourMap cm)
+{
+    const unsigned long long t =
+        (unsigned long long)xcd_block(gridDim.x / 8u) * blockDim.x + threadIdx.x;
+    if (t >= cm.total) return;
+    const unsigned row = udiv(t, cm.H, cm.invH);
+    const unsigned ih = (unsigned)(t - (unsigned long long)row * cm.H);
+    unsigned j = 0, k = 0;
+    if (DIM == 3) {
+        k = udiv(row, cm.n1, cm.invN1);
+        j = row - k * cm.n1;
+    } else if (DIM == 2) {
+        j = row;
+    }
+    const int i = 2 * (int)ih + (int)((j + k + colour) & 1);
+    if (i >= g.n[0]) return;
+    if (dirichlet_at(g, i, (int)j, (int)k, nullptr)) return;
+    ngs_cell<MODEL, SINK, DIM>(g, L, st.a, beta, lambdaU, K, gv, psi, i, (int)j, (int)k, colour);
+}
+
+// Whole sweeps of a tiny level in one work-group (the coarsest levels, where
 // launch latency, not work, dominates).
+template <int MODEL, bool SINK, int DIM>
 __global__ __launch_bounds__(256) void k_sweep_small(Geo g, Law L, Step st, const double *beta,
                                                      double lambdaU, const double *K,
                                                      const double *gv, double *psi, int nsweeps)
@@ -249,7 +432,7 @@ __global__ __launch_bounds__(256) void k_sweep_small(Geo g, Law L, Step st, cons
                 int k = r / g.n[1];
                 if (((i + j + k) & 1) != colour) continue;
                 if (dirichlet_at(g, i, j, k, nullptr)) continue;
-                ngs_update(g, L, st, beta, lambdaU, K, gv, psi, i, j, k, colour);
+                ngs_cell<MODEL, SINK, DIM>(g, L, st.a, beta, lambdaU, K, gv, psi, i, j, k, colour);
             }
             __syncthreads();
         }
@@ -260,29 +443,76 @@ __global__ __launch_bounds__(256) void k_sweep_small(Geo g, Law L, Step st, cons
 // Defect d = g - N(psi) and its max-norm (step 2 of the FAS algorithm)
 // ---------------------------------------------------------------------------
 
+struct NodeMap {
+    unsigned n0, n1;
+    double inv0, inv1;
+};
+
+NodeMap node_map(const Geo &g)
+{
+    NodeMap m;
+    m.n0 = (unsigned)g.n[0];
+    m.n1 = (unsigned)g.n[1];
+    m.inv0 = 1.0 / m.n0;
+    m.inv1 = 1.0 / m.n1;
+    return m;
+}
+
+template <int MODEL, bool SINK, int DIM>
+__device__ __forceinline__ double apply_N_t(const Geo &g, const Law &L, double a,
+                                            const double *beta, const double *K,
+                                            const double *psi, int i, int j, int k, long long idx)
+{
+    const double x = psi[idx];
+    const double Ki = K[idx];
+    double s = a * theta_only_t<MODEL>(L, x);
+    if (SINK) {
+        double fa, dfa;
+        feddes(L, x, fa, dfa);
+        const int vk = (DIM == 1) ? i : (DIM == 2 ? j : k);
+        s += beta[vk] * fa;
+    }
+    double mpsi = 0.0;
+    for_nb<DIM>(g, i, j, k, idx, [&](long long jn, double cf, int, int) {
+        mpsi += cf * (Ki + K[jn]) * (x - psi[jn]);
+    });
+    return s + (L.xi * x + mpsi);
+}
+
+// Grid-stride over the nodes; one block maximum and one atomic per block.
+template <int MODEL, bool SINK, int DIM>
 __global__ __launch_bounds__(256) void k_residual(Geo g, Law L, Step st, const double *beta,
                                                   const double *K, const double *gv,
                                                   const double *psi, double *d,
-                                                  unsigned long long *norm_bits)
+                                                  unsigned long long *norm_bits, NodeMap nm)
 {
-    int i = blockIdx.x * kBX + threadIdx.x;
-    int j = blockIdx.y * kBY + threadIdx.y;
-    int k = blockIdx.z;
     double v = 0.0;
-    if (i < g.n[0] && j < g.n[1]) {
-        long long idx = i + (long long)j * g.stride[1] + (long long)k * g.stride[2];
-        double r = 0.0;
-        if (!dirichlet_at(g, i, j, k, nullptr)) {
-            int c[3] = {i, j, k};
-            r = gv[idx] - apply_N(g, L, st, beta, K, psi, c, idx);
+    const unsigned long long N = (unsigned long long)g.N;
+    // each group walks a contiguous chunk of nodes (XCD-aware numbering)
+    const unsigned long long chunk =
+        ((N + gridDim.x - 1) / gridDim.x + blockDim.x - 1) / blockDim.x * blockDim.x;
+    const unsigned long long t0 = (unsigned long long)xcd_block(gridDim.x / 8u) * chunk;
+    const unsigned long long t1 = t0 + chunk < N ? t0 + chunk : N;
+    for (unsigned long long t = t0 + threadIdx.x; t < t1; t += blockDim.x) {
+        const unsigned row = udiv(t, nm.n0, nm.inv0);
+        const int i = (int)(t - (unsigned long long)row * nm.n0);
+        int j = 0, k = 0;
+        if (DIM == 3) {
+            k = (int)udiv(row, nm.n1, nm.inv1);
+            j = (int)row - k * (int)nm.n1;
+        } else if (DIM == 2) {
+            j = (int)row;
         }
-        if (d) d[idx] = r;
-        v = fabs(r);
+        double r = 0.0;
+        if (!dirichlet_at(g, i, j, k, nullptr))
+            r = gv[t] - apply_N_t<MODEL, SINK, DIM>(g, L, st.a, beta, K, psi, i, j, k, (long long)t);
+        if (d) d[t] = r;
+        const double ar = fabs(r);
+        v = (ar > v || ar != ar) ? ar : v;
     }
     if (norm_bits) {
         v = block_max(v);
-        if (threadIdx.x == 0 && threadIdx.y == 0)
-            atomicMax(norm_bits, (unsigned long long)__double_as_longlong(v));
+        if (threadIdx.x == 0) atomicMax(norm_bits, (unsigned long long)__double_as_longlong(v));
     }
 }
 
@@ -482,29 +712,129 @@ void launch_lambda_u(const Geo &g, const double *K, unsigned long long *out, hip
     hipLaunchKernelGGL(k_lambda_u, node_grid(g), dim3(kBX, kBY), 0, s, g, K, out);
 }
 
-void launch_sweep_rb(const Geo &g, const Law &law, const Step &st, const double *beta,
-                     double lambdaU, const double *K, const double *gvec, double *psi,
-                     int nsweeps, hipStream_t s)
+// Call fn.template operator()<MODEL, SINK, DIM>() for the law and level.
+template <typename Fn>
+void dispatch(const Law &law, int dim, Fn &&fn)
 {
-    if (g.N <= 8192) {
-        hipLaunchKernelGGL(k_sweep_small, dim3(1), dim3(256), 0, s, g, law, st, beta, lambdaU, K,
-                           gvec, psi, nsweeps);
-        return;
+    const bool s = law.sink == kSinkFeddes;
+#define RS_DIMS(M, S)                                   \
+    do {                                                \
+        if (dim == 1) fn.template go<M, S, 1>();        \
+        else if (dim == 2) fn.template go<M, S, 2>();   \
+        else fn.template go<M, S, 3>();                 \
+    } while (0)
+    if (law.model == kHaverkamp) {
+        if (s) RS_DIMS(kHaverkamp, true); else RS_DIMS(kHaverkamp, false);
+    } else if (law.model == kVgm) {
+        if (s) RS_DIMS(kVgm, true); else RS_DIMS(kVgm, false);
+    } else {
+        if (s) RS_DIMS(kLinear, true); else RS_DIMS(kLinear, false);
     }
-    int half = (g.n[0] + 1) / 2;
-    dim3 grid((half + kBX - 1) / kBX, (g.n[1] + kBY - 1) / kBY, g.n[2]);
-    for (int sw = 0; sw < nsweeps; ++sw)
-        for (int colour = 0; colour < 2; ++colour)
-            hipLaunchKernelGGL(k_sweep_colour, grid, dim3(kBX, kBY), 0, s, g, law, st, beta,
-                               lambdaU, K, gvec, psi, colour);
+#undef RS_DIMS
+}
+
+// Tile extents of the fused sweep (x, y, z-chunk); RS_FUSED_TILE="tx,ty,zc"
+// overrides them for tuning.
+void fused_tile(int *tx, int *ty, int *zc)
+{
+    *tx = 64; *ty = 16; *zc = 16;
+    if (const char *e = getenv("RS_FUSED_TILE")) {
+        int a, b, c;
+        if (sscanf(e, "%d,%d,%d", &a, &b, &c) == 3 && a >= 1 && b >= 1 && c >= 1) {
+            *tx = a; *ty = b; *zc = c;
+        }
+    }
+}
+
+// The fused sweep is opt-in (RS_SWEEP=fused) until it beats the two-pass one.
+bool fused_enabled()
+{
+    const char *e = getenv("RS_SWEEP");
+    return e && strcmp(e, "fused") == 0;
+}
+
+FusedMap fused_map(const Geo &g)
+{
+    FusedMap m;
+    fused_tile(&m.TX, &m.TY, &m.ZC);
+    m.TX = m.TX < g.n[0] ? m.TX : g.n[0];
+    m.TY = m.TY < g.n[1] ? m.TY : g.n[1];
+    m.ZC = m.ZC < g.n[2] ? m.ZC : g.n[2];
+    m.ntx = g.n[0] / m.TX;
+    m.nty = g.n[1] / m.TY;
+    m.ntz = g.n[2] / m.ZC;
+    m.nwg = m.ntx * m.nty * m.ntz;
+    m.per = (m.nwg + 7) / 8;
+    m.P = m.TX + (g.n[0] - m.ntx * m.TX) + 2;
+    m.Hs = m.TY + (g.n[1] - m.nty * m.TY) + 2;
+    return m;
+}
+
+struct SweepLaunch {
+    const Geo &g; const Law &law; const Step &st; const double *beta; double lambdaU;
+    const double *K; const double *gvec; double **psi; double **psi_alt; int nsweeps; hipStream_t s;
+    template <int M, bool S, int D>
+    void go()
+    {
+        if (g.N <= 1024) {
+            hipLaunchKernelGGL((k_sweep_small<M, S, D>), dim3(1), dim3(256), 0, s, g, law, st,
+                               beta, lambdaU, K, gvec, *psi, nsweeps);
+            return;
+        }
+        if (D == 3 && psi_alt && *psi_alt && fused_enabled()) {
+            FusedMap fm = fused_map(g);
+            size_t lds = sizeof(double) * 3 * (size_t)fm.P * fm.Hs;
+            for (int sw = 0; sw < nsweeps; ++sw) {
+                hipLaunchKernelGGL((k_sweep_fused<M, S>), dim3(8 * fm.per), dim3(256), lds, s, g,
+                                   law, st, beta, lambdaU, K, gvec, *psi, *psi_alt, fm);
+                double *t = *psi;
+                *psi = *psi_alt;
+                *psi_alt = t;
+            }
+            return;
+        }
+        ColourMap cm = colour_map(g);
+        dim3 grid(xcd_grid((cm.total + 255) / 256));
+        for (int sw = 0; sw < nsweeps; ++sw)
+            for (int colour = 0; colour < 2; ++colour)
+                hipLaunchKernelGGL((k_sweep<M, S, D>), grid, dim3(256), 0, s, g, law, st, beta,
+                                   lambdaU, K, gvec, *psi, colour, cm);
+    }
+};
+
+struct ResidualLaunch {
+    const Geo &g; const Law &law; const Step &st; const double *beta; const double *K;
+    const double *gvec; const double *psi; double *d; unsigned long long *norm_bits; hipStream_t s;
+    template <int M, bool S, int D>
+    void go()
+    {
+        unsigned long long blocks = ((unsigned long long)g.N + 255) / 256;
+        if (blocks > 2048) blocks = 2048;
+        hipLaunchKernelGGL((k_residual<M, S, D>), dim3(xcd_grid(blocks)), dim3(256), 0, s, g,
+                           law, st, beta, K, gvec, psi, d, norm_bits, node_map(g));
+    }
+};
+
+int launch_sweep_rb(const Geo &g, const Law &law, const Step &st, const double *beta,
+                    double lambdaU, const double *K, const double *gvec, double **psi,
+                    double **psi_alt, int nsweeps, hipStream_t s)
+{
+    if (nsweeps <= 0) return 0;
+    dispatch(law, g.dim, SweepLaunch{g, law, st, beta, lambdaU, K, gvec, psi, psi_alt, nsweeps, s});
+    if (g.N <= 1024) return 1;
+    return (g.dim == 3 && psi_alt && *psi_alt && fused_enabled()) ? nsweeps : 2 * nsweeps;
+}
+
+bool fused_sweep_level(const Geo &g)
+{
+    return g.dim == 3 && g.N >= kFusedMinNodes;
 }
 
 void launch_residual(const Geo &g, const Law &law, const Step &st, const double *beta,
                      const double *K, const double *gvec, const double *psi, double *d,
                      unsigned long long *norm_bits, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_residual, node_grid(g), dim3(kBX, kBY), 0, s, g, law, st, beta, K, gvec,
-                       psi, d, norm_bits);
+    dispatch(law, g.dim, ResidualLaunch{g, law, st, beta, K, gvec, psi, d, norm_bits, s});
 }
 
 void launch_restrict(const Geo &gc, const Geo &gf, const double *psi_f, const double *d_f,

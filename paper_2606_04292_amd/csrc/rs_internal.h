@@ -70,9 +70,14 @@ void launch_setup_g(const Geo &g, const Law &law, const Step &st, const double *
                     const double *psi_nm1, const double *K, double *gvec, hipStream_t s);
 void launch_inject(const Geo &gc, const Geo &gf, const double *Kf, double *Kc, hipStream_t s);
 void launch_lambda_u(const Geo &g, const double *K, unsigned long long *out, hipStream_t s);
-void launch_sweep_rb(const Geo &g, const Law &law, const Step &st, const double *beta,
-                     double lambdaU, const double *K, const double *gvec, double *psi,
-                     int nsweeps, hipStream_t s);
+// Red-black sweeps; 3-D levels with a second psi buffer use the fused kernel
+// and swap *psi / *psi_alt after every sweep.  Returns the kernel launches made.
+int launch_sweep_rb(const Geo &g, const Law &law, const Step &st, const double *beta,
+                    double lambdaU, const double *K, const double *gvec, double **psi,
+                    double **psi_alt, int nsweeps, hipStream_t s);
+// Levels that get a second psi buffer for the fused sweep.
+constexpr long long kFusedMinNodes = 33LL * 33 * 33;
+bool fused_sweep_level(const Geo &g);
 void launch_residual(const Geo &g, const Law &law, const Step &st, const double *beta,
                      const double *K, const double *gvec, const double *psi, double *d,
                      unsigned long long *norm_bits, hipStream_t s);

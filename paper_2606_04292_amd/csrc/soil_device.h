@@ -8,21 +8,107 @@
 //   1 - (P/(1+P))^m = -expm1(m (n log(alpha|psi|) - log1p(P))).
 // Haverkamp uses Q = |u psi|^beta = exp(beta log|u psi|) and
 //   theta' = u beta (theta - theta_r) (Q / (alpha + Q)) / |u psi|.
+// The sweep and residual evaluate ln, ln(1+p) and exp with the short
+// series below (a few ulp); the once-per-step K(psi) uses the library ones.
+// Each law is a template specialisation so the sweep kernels carry no model
+// switch; the generic entry points dispatch on Law::model.
 #pragma once
 
 #include "rs_internal.h"
 
 namespace rs {
 
+// 1/x from the hardware estimate refined by two Newton-Raphson steps
+// (error of a few ulp; used where a correctly rounded quotient is not needed).
+__device__ __forceinline__ double rcp_nr(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+// Natural logarithm of a positive normal double.  x = m 2^e with m in
+// [sqrt(1/2), sqrt(2)), ln x = e ln2 + 2 atanh(s), s = (m-1)/(m+1), |s| <= 0.1716,
+// with the atanh series 2 s (1 + s^2/3 + ... + s^18/19) (truncation < 3e-17)
+// and ln2 split Cody-Waite style so that e ln2_hi is exact.
+constexpr double kLn2Hi = 6.93147180369123816490e-01;
+constexpr double kLn2Lo = 1.90821492927058770002e-10;
+constexpr double kInvLn2 = 1.44269504088896338700e+00;
+
+__device__ __forceinline__ double atanh2_series(double s)
+{
+    const double s2 = s * s;
+    double p = 1.0 / 19.0;
+    p = fma(p, s2, 1.0 / 17.0);
+    p = fma(p, s2, 1.0 / 15.0);
+    p = fma(p, s2, 1.0 / 13.0);
+    p = fma(p, s2, 1.0 / 11.0);
+    p = fma(p, s2, 1.0 / 9.0);
+    p = fma(p, s2, 1.0 / 7.0);
+    p = fma(p, s2, 1.0 / 5.0);
+    p = fma(p, s2, 1.0 / 3.0);
+    return fma(2.0 * s * s2, p, 2.0 * s);   // 2 atanh(s)
+}
+
+__device__ __forceinline__ double rs_log(double x)
+{
+    int e = __builtin_amdgcn_frexp_exp(x);
+    double m = __builtin_amdgcn_frexp_mant(x);      // [0.5, 1)
+    if (m < 0.70710678118654752440) {
+        m += m;
+        e -= 1;
+    }
+    const double s = (m - 1.0) * rcp_nr(m + 1.0);
+    const double de = (double)e;
+    return fma(de, kLn2Hi, fma(de, kLn2Lo, atanh2_series(s)));
+}
+
+// ln(1 + p) for p >= 0: the atanh series with s = p/(2+p) while p < sqrt(2)-1
+// (no cancellation for small p), else ln of the rounded sum.
+__device__ __forceinline__ double rs_log1p(double p)
+{
+    if (p < 0.41421356237309504880) return atanh2_series(p * rcp_nr(2.0 + p));
+    return rs_log(1.0 + p);
+}
+
+// e^y: y = n ln2 + r (Cody-Waite, |r| <= ln2/2), e^r by its Taylor series to
+// r^13/13! (truncation < 5e-18), scaled by 2^n (overflows to inf, underflows
+// to 0 past the double range).
+__device__ __forceinline__ double rs_exp(double y)
+{
+    double n = rint(y * kInvLn2);
+    n = fmin(fmax(n, -2100.0), 2100.0);
+    double r = fma(-n, kLn2Hi, y);
+    r = fma(-n, kLn2Lo, r);
+    double p = 1.0 / 6227020800.0;                   // 1/13!
+    p = fma(p, r, 1.0 / 479001600.0);
+    p = fma(p, r, 1.0 / 39916800.0);
+    p = fma(p, r, 1.0 / 3628800.0);
+    p = fma(p, r, 1.0 / 362880.0);
+    p = fma(p, r, 1.0 / 40320.0);
+    p = fma(p, r, 1.0 / 5040.0);
+    p = fma(p, r, 1.0 / 720.0);
+    p = fma(p, r, 1.0 / 120.0);
+    p = fma(p, r, 1.0 / 24.0);
+    p = fma(p, r, 1.0 / 6.0);
+    p = fma(p, r, 0.5);
+    p = fma(p, r, 1.0);
+    p = fma(p, r, 1.0);
+    return __builtin_amdgcn_ldexp(p, (int)n);
+}
+
 struct ThetaEval {
     double th;
     double dth;
 };
 
-__device__ __forceinline__ ThetaEval theta_eval(const Law &L, double x)
+template <int MODEL>
+__device__ __forceinline__ ThetaEval theta_t(const Law &L, double x)
 {
     ThetaEval r;
-    if (L.model == kLinear) {
+    if (MODEL == kLinear) {
         r.th = L.tr + L.lin_c * x;
         r.dth = L.lin_c;
         return r;
@@ -32,27 +118,49 @@ __device__ __forceinline__ ThetaEval theta_eval(const Law &L, double x)
         r.dth = 0.0;
         return r;
     }
-    if (L.model == kHaverkamp) {
+    if (MODEL == kHaverkamp) {
+        // one reciprocal serves 1/(alpha + Q) = hu w and 1/hu = (alpha + Q) w
         double hu = -L.unit * x;
-        double Q = exp(L.hk_beta * log(hu));
-        double rden = 1.0 / (L.hk_alpha + Q);
-        double tmr = L.hk_alpha * L.dT * rden;          // theta - theta_r
+        double Q = rs_exp(L.hk_beta * rs_log(hu));
+        double den = L.hk_alpha + Q;
+        double w = rcp_nr(hu * den);
+        double tmr = L.hk_alpha * L.dT * (hu * w);      // theta - theta_r
         r.th = L.tr + tmr;
-        r.dth = L.unit * L.hk_beta * tmr * (Q * rden) / hu;
+        r.dth = L.unit * L.hk_beta * tmr * Q * w;
         return r;
     }
     // van Genuchten - Mualem
     double ax = -L.vg_alpha * x;
-    double P = exp(L.vg_n * log(ax));
-    double Se = exp(-L.vg_m * log1p(P));
+    double P = rs_exp(L.vg_n * rs_log(ax));
+    double Se = rs_exp(-L.vg_m * rs_log1p(P));
     r.th = L.tr + L.dT * Se;
-    r.dth = L.dT * L.vg_m * L.vg_n * P * Se / ((1.0 + P) * (-x));
+    r.dth = L.dT * L.vg_m * L.vg_n * P * Se * rcp_nr((1.0 + P) * (-x));
     return r;
+}
+
+template <int MODEL>
+__device__ __forceinline__ double theta_only_t(const Law &L, double x)
+{
+    if (MODEL == kLinear) return L.tr + L.lin_c * x;
+    if (!(x < 0.0)) return L.ts;
+    if (MODEL == kHaverkamp) {
+        double hu = -L.unit * x;
+        double Q = rs_exp(L.hk_beta * rs_log(hu));
+        double den = L.hk_alpha + Q;
+        double w = rcp_nr(hu * den);
+        return L.tr + L.hk_alpha * L.dT * (hu * w);
+    }
+    double P = rs_exp(L.vg_n * rs_log(-L.vg_alpha * x));
+    return L.tr + L.dT * rs_exp(-L.vg_m * rs_log1p(P));
 }
 
 __device__ __forceinline__ double theta_only(const Law &L, double x)
 {
-    return theta_eval(L, x).th;
+    switch (L.model) {
+    case kHaverkamp: return theta_only_t<kHaverkamp>(L, x);
+    case kVgm: return theta_only_t<kVgm>(L, x);
+    default: return theta_only_t<kLinear>(L, x);
+    }
 }
 
 // K(psi) / Ks.
@@ -83,33 +191,37 @@ __device__ __forceinline__ void feddes(const Law &L, double x, double &a, double
 
 // Pointwise equation of the NGS update (eq. point-update with the BDF
 // coefficient a and sink beta * a_F):  a theta(x) + beta a_F(x) + c x = f.
-// Exactly L.newton safeguarded Newton steps from x0: the root stays inside
-// [lo, hi] (initially [(f - a theta_s - beta)/c, (f - a theta_r)/c] widened by
-// 1e-12 of the ends' magnitudes, so that the root of a saturated cell -- the
-// lower end, F being linear there -- lies strictly inside; narrowed by the
-// sign of F at each iterate); a step that does not land strictly
-// inside, or a non-positive F', becomes a bisection, unless the step leaves
-// the iterate unchanged.
-__device__ __forceinline__ double local_solve(const Law &L, double a, double beta, double c,
-                                              double f, double x0)
+// NEWTON (or L.newton when NEWTON == 0) safeguarded Newton steps from x0: the
+// root stays inside [lo, hi] (initially [(f - a theta_s - beta)/c,
+// (f - a theta_r)/c] widened by 1e-12 of the ends' magnitudes, so that the
+// root of a saturated cell -- the lower end, F being linear there -- lies
+// strictly inside; narrowed by the sign of F at each iterate); a step that does
+// not land strictly inside, or a non-positive F', becomes a bisection, unless
+// the step leaves the iterate unchanged.
+template <int MODEL, bool SINK, int NEWTON>
+__device__ __forceinline__ double local_solve_t(const Law &L, double a, double beta, double c,
+                                                double f, double x0)
 {
     double lo, hi;
-    if (L.model == kLinear) {
+    if (MODEL == kLinear) {
         lo = -INFINITY;
         hi = INFINITY;
     } else {
-        lo = (f - a * L.ts - beta) / c;
-        hi = (f - a * L.tr) / c;
+        double ic = rcp_nr(c);
+        lo = (f - a * L.ts - beta) * ic;
+        hi = (f - a * L.tr) * ic;
         double pad = 1e-12 * (fabs(lo) + fabs(hi));
         lo -= pad;
         hi += pad;
     }
     double x = x0;
-    for (int k = 0; k < L.newton; ++k) {
-        ThetaEval t = theta_eval(L, x);
+    const int iters = NEWTON > 0 ? NEWTON : L.newton;
+#pragma unroll
+    for (int k = 0; k < iters; ++k) {
+        ThetaEval t = theta_t<MODEL>(L, x);
         double F = a * t.th + c * x - f;
         double dF = a * t.dth + c;
-        if (L.sink == kSinkFeddes) {
+        if (SINK) {
             double fa, dfa;
             feddes(L, x, fa, dfa);
             F += beta * fa;
@@ -123,11 +235,28 @@ __device__ __forceinline__ double local_solve(const Law &L, double a, double bet
             lo = x;
             hi = x;
         }
-        double xn = x - F / dF;
+        double xn = x - F * rcp_nr(dF);
         bool bisect = !(dF > 0.0) || (xn != x && !(xn > lo && xn < hi));
         x = bisect ? 0.5 * (lo + hi) : xn;
     }
     return x;
+}
+
+__device__ __forceinline__ double local_solve(const Law &L, double a, double beta, double c,
+                                              double f, double x0)
+{
+    const bool s = L.sink == kSinkFeddes;
+    switch (L.model) {
+    case kHaverkamp:
+        return s ? local_solve_t<kHaverkamp, true, 0>(L, a, beta, c, f, x0)
+                 : local_solve_t<kHaverkamp, false, 0>(L, a, beta, c, f, x0);
+    case kVgm:
+        return s ? local_solve_t<kVgm, true, 0>(L, a, beta, c, f, x0)
+                 : local_solve_t<kVgm, false, 0>(L, a, beta, c, f, x0);
+    default:
+        return s ? local_solve_t<kLinear, true, 0>(L, a, beta, c, f, x0)
+                 : local_solve_t<kLinear, false, 0>(L, a, beta, c, f, x0);
+    }
 }
 
 // Node kinds from indices (no node-type array): Dirichlet if on a Dirichlet
@@ -162,6 +291,16 @@ __device__ __forceinline__ bool dirichlet_at(const Geo &g, int i, int j, int k, 
     }
     if (val) *val = v;
     return dir;
+}
+
+// Quotient and remainder of t by d using a double reciprocal and one
+// correction step (exact for t < 2^40).
+__device__ __forceinline__ unsigned udiv(unsigned long long t, unsigned d, double invd)
+{
+    unsigned long long q = (unsigned long long)((double)t * invd);
+    if (q * d > t) --q;
+    else if ((q + 1) * d <= t) ++q;
+    return (unsigned)q;
 }
 
 }  // namespace rs
