@@ -72,11 +72,39 @@ def gpu_run(args):
     elapsed = time.perf_counter() - t0
     sweep_ms, launches, sweep_cells = G.profile_read(reset=True)
     G.profile_enable(False)
+    psi_fp64 = G.get_state()[0]
     avg_launch_s = sweep_ms * 1e-3 / max(launches, 1)
     bytes_per_launch = BYTES_PER_UPDATE * sweep_cells / max(launches, 1)
     achieved = bytes_per_launch / avg_launch_s / 1e9
+    mixed = None
+    if not args.no_mixed:
+        # the same steps with FP32 correction cycles inside FP64 defect correction
+        H = rsl.Grid(w, precision=rsl.RS_MIXED, device="cuda:0")
+        for s in range(args.warmup):
+            H.bdf_step(opts=opts)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        mup, outer = 0.0, []
+        for s in range(args.steps):
+            code, st = H.bdf_step(opts=opts)
+            if code != rsl.RS_OK:
+                raise SystemExit("mixed step failed: " + rsl.lib().rs_last_error().decode())
+            mup += st.cell_updates
+            outer.append(st.cycles)
+        torch.cuda.synchronize()
+        el2 = time.perf_counter() - t1
+        psi_mp = H.get_state()[0]
+        err = float((psi_mp - psi_fp64).abs().max() / psi_fp64.abs().max())
+        mixed = {"ms_per_step": round(el2 * 1e3 / args.steps, 3),
+                 "speedup_vs_fp64": round(elapsed / el2, 3),
+                 "fp32_cell_updates_per_s": mup / el2,
+                 "outer_corrections_per_step": outer,
+                 "rel_err_vs_fp64": err,
+                 "note": "same steps and tolerance; FP64 path is parity-tested against the oracle"}
+        log("mixed: %.2f ms/step, rel diff vs FP64 %.2e" % (el2 * 1e3 / args.steps, err))
+        H.close()
     res = dict(
-        w=w, elapsed=elapsed, updates=updates, cycles=cycles,
+        w=w, elapsed=elapsed, updates=updates, cycles=cycles, mixed=mixed,
         roofline={"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                   "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                   "kernel": "k_sweep_colour (finest level, one colour per launch)",
@@ -123,6 +151,7 @@ def main():
     ap.add_argument("--max-cycles", type=int, default=40)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 512 MiB device copy first (counter calibration)")
     args = ap.parse_args()
@@ -149,6 +178,8 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": r["roofline"],
     }
+    if r["mixed"] is not None:
+        out["mixed_precision"] = r["mixed"]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, args.n)
     print(json.dumps(out), flush=True)

@@ -126,7 +126,8 @@ typedef struct rs_solve_opts {
     size_t struct_size;   /* sizeof(rs_solve_opts) */
     int nu1, nu2, nu_coarse, max_cycles;
     double tol_abs;       /* stop when ||g - N(psi)||_inf <= tol_abs */
-    int stagnation;       /* also stop when the norm fails to halve twice in a row */
+    int stagnation;       /* also stop, with RS_OK, at the rounding floor: two cycles
+                             in a row that set no new minimum of the norm */
     int mp_inner_cycles;  /* RS_MIXED: FP32 V-cycles per FP64 defect correction */
 } rs_solve_opts;
 
@@ -182,6 +183,16 @@ int rs_sweep(rs_grid *g, int level, int nsweeps);
  * not NULL the fine residual max-norm after the cycle is written there and the
  * call synchronises the stream.  Errors: RS_ESTATE without begin_step. */
 int rs_vcycle(rs_grid *g, int nu1, int nu2, double *res_linf);
+
+/* RS_MIXED grids: one FP64 defect correction (spec precision pattern,
+ * not in the paper).  The FP64 defect r = g_h - N_h(psi) is formed, then
+ * inner_cycles FP32 FAS V(nu1, nu2) cycles solve the correction equation
+ * N_h(psi_b + delta) - N_h(psi_b) = fl32(r) about the base state
+ * psi_b = fl32(psi), with the increments of theta and S evaluated without
+ * cancellation, and psi += delta in FP64.  res (nullable) receives the FP64
+ * residual norm afterwards (synchronises).  Errors: RS_ESTATE on an FP64 grid
+ * or without begin_step. */
+int rs_correction_cycle(rs_grid *g, int inner_cycles, int nu1, int nu2, double *res_linf);
 
 /* ||g_h - N_h(psi)||_inf over the fine unknowns in FP64 (the stopping quantity
  * of section 3.2).  Synchronises.  RS_ENONFINITE if it is not finite. */

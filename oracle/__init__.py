@@ -276,20 +276,24 @@ def run_steps(w, steps=None, ordering=ORDER_RB, max_cycles=60, tol=0.0, stagnati
 
 
 def solve_to_floor(S, max_cycles=60, tol=0.0, stagnation=True):
-    """V-cycles until ||r|| <= tol, or (stagnation) the norm fails to drop
-    below 0.5x its previous value twice in a row, or max_cycles."""
+    """V-cycles until ||r|| <= tol, or (stagnation) the rounding floor is
+    reached: two cycles in a row set no new minimum of the norm; or
+    max_cycles.  A slow but steady contraction keeps iterating."""
     r = S.residual()
     hist = [r]
+    best = r
     slow = 0
     for _ in range(max_cycles):
         if r <= tol:
             break
         S.vcycle()
-        rn = S.residual()
-        hist.append(rn)
+        r = S.residual()
+        hist.append(r)
         if stagnation:
-            slow = slow + 1 if rn > 0.5 * r else 0
-            if slow >= 2:
-                break
-        r = rn
+            if r < best:
+                best, slow = r, 0
+            else:
+                slow += 1
+                if slow >= 2:
+                    break
     return hist

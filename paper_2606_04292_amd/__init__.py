@@ -27,7 +27,7 @@ EXPORTS = [
     "rs_get_state", "rs_begin_step", "rs_sweep", "rs_vcycle", "rs_residual_norm",
     "rs_residual", "rs_end_step", "rs_bdf_step", "rs_copy_field", "rs_set_field",
     "rs_num_levels", "rs_level_shape", "rs_destroy_grid", "rs_last_error",
-    "rs_profile_enable", "rs_profile_read",
+    "rs_profile_enable", "rs_profile_read", "rs_correction_cycle",
 ]
 
 
@@ -101,6 +101,7 @@ def lib():
         L.rs_destroy_grid.argtypes = [vp]
         L.rs_profile_enable.argtypes = [vp, C.c_int]
         L.rs_profile_read.argtypes = [vp, D, C.POINTER(C.c_longlong), D, C.c_int]
+        L.rs_correction_cycle.argtypes = [vp, C.c_int, C.c_int, C.c_int, D]
         _lib = L
     return _lib
 
@@ -291,3 +292,11 @@ class Grid:
         check(lib().rs_profile_read(self.h, C.byref(ms), C.byref(n), C.byref(cells),
                                     1 if reset else 0))
         return ms.value, n.value, cells.value
+
+    def correction_cycle(self, inner=1, nu1=None, nu2=None, want_norm=False):
+        """One FP64 defect correction with FP32 V-cycles (RS_MIXED grids)."""
+        r = C.c_double()
+        check(lib().rs_correction_cycle(self.h, inner, self.w.nu1 if nu1 is None else nu1,
+                                        self.w.nu2 if nu2 is None else nu2,
+                                        C.byref(r) if want_norm else None))
+        return r.value if want_norm else None

@@ -13,6 +13,7 @@
 
 #include "../../include/richards.h"
 #include "rs_internal.h"
+#include "mp_internal.h"
 
 namespace rs {
 void launch_root_beta(int nlev, const int *nvert, const double *hvert, double *const *beta,
@@ -138,6 +139,7 @@ Geo make_geo(const rs_grid_desc *d, int lev)
 struct Layout {
     int nlev;
     size_t lev_off[kMaxLevels][6];   // psi, K, g, d, psibar, psi_alt (fused levels)
+    size_t mp_off[kMaxLevels][6];    // RS_MIXED: delta, K32, rhs, r, dbar, psi_b (FP32)
     size_t beta_off[kMaxLevels];
     size_t psi_n, psi_nm1, ks, scratch;
     size_t total;
@@ -147,7 +149,6 @@ constexpr int kScratchWords = 64;
 
 void plan(const rs_grid_desc *d, int precision, Layout *L)
 {
-    (void)precision;
     size_t off = 0;
     L->nlev = level_count(d);
     for (int l = 0; l < L->nlev; ++l) {
@@ -163,6 +164,13 @@ void plan(const rs_grid_desc *d, int precision, Layout *L)
         }
         L->beta_off[l] = off;
         off = align_up(off + sizeof(double) * (size_t)g.n[g.vert]);
+        for (int a = 0; a < 6; ++a) {
+            L->mp_off[l][a] = 0;
+            if (precision == RS_MIXED) {
+                L->mp_off[l][a] = off;
+                off = align_up(off + sizeof(float) * (size_t)g.N);
+            }
+        }
     }
     size_t N0 = (size_t)make_geo(d, 0).N;
     L->psi_n = off;   off = align_up(off + sizeof(double) * N0);
@@ -176,6 +184,7 @@ struct LevelData {
     Geo geo;
     double *psi, *K, *g, *d, *psibar, *beta;
     double *psi_alt;   // second psi buffer of the fused sweep (or null)
+    float *dl, *K32, *rhs32, *r32, *dbar32, *pb32;   // RS_MIXED correction cycles
     double lambdaU;
     long long unknowns;
 };
@@ -233,6 +242,7 @@ struct rs_grid {
     unsigned long long *scratch;
     unsigned long long *host_bits;   // pinned readback
     Law law;
+    Law32 law32;
     bool law_set;
     Step step;
     bool in_step;
@@ -374,13 +384,71 @@ int read_norm(rs_grid *G, double *out)
     return RS_OK;
 }
 
-int fine_norm(rs_grid *G, double *out)
+// FP64 defect max-norm of the finest level (and the defect vector into d).
+int fine_norm(rs_grid *G, double *out, double *d = nullptr)
 {
     LevelData &f = G->lev[0];
     launch_fill_u64(G->scratch, 1, 0ull, G->stream);
-    launch_residual(f.geo, G->law, G->step, f.beta, f.K, f.g, f.psi, nullptr, G->scratch, G->stream);
+    launch_residual(f.geo, G->law, G->step, f.beta, f.K, f.g, f.psi, d, G->scratch, G->stream);
     HIPCALL(hipGetLastError());
     return read_norm(G, out);
+}
+
+// FP32 red-black sweeps of the correction equation on level l.
+void sweep32_level(rs_grid *G, int l, int nsweeps)
+{
+    LevelData &f = G->lev[l];
+    bool timed = G->prof_on && l == 0 && nsweeps > 0;
+    if (timed && 2 * (G->prof_used + 1) > G->prof_ev.size()) {
+        for (int e = 0; e < 2; ++e) {
+            hipEvent_t ev;
+            if (hipEventCreate(&ev) != hipSuccess) { timed = false; break; }
+            G->prof_ev.push_back(ev);
+        }
+        G->prof_sweeps.push_back(0);
+        G->prof_launch.push_back(0);
+    }
+    if (timed) timed = hipEventRecord(G->prof_ev[2 * G->prof_used], G->stream) == hipSuccess;
+    launch_sweep32(f.geo, G->law32, (float)G->step.a, f.beta, (float)f.lambdaU, f.K32, f.rhs32,
+                   f.pb32, f.dl, nsweeps, G->stream);
+    if (timed && hipEventRecord(G->prof_ev[2 * G->prof_used + 1], G->stream) == hipSuccess) {
+        G->prof_sweeps[G->prof_used] = nsweeps;
+        G->prof_launch[G->prof_used] = f.geo.N <= 1024 ? 1 : 2 * nsweeps;
+        G->prof_used += 1;
+    }
+    G->updates += (double)nsweeps * (double)f.unknowns;
+}
+
+// FP32 FAS V-cycle on the correction equation (same structure as the FP64 one).
+void vcycle32_level(rs_grid *G, int l, int nu1, int nu2)
+{
+    LevelData &f = G->lev[l];
+    const float a = (float)G->step.a;
+    if (l == G->nlev - 1) {
+        sweep32_level(G, l, G->nu_coarse);
+        return;
+    }
+    LevelData &c = G->lev[l + 1];
+    sweep32_level(G, l, nu1);
+    launch_residual32(f.geo, G->law32, a, f.beta, f.K32, f.rhs32, f.pb32, f.dl, f.r32, G->stream);
+    launch_restrict32(c.geo, f.geo, f.dl, f.r32, c.dbar32, c.rhs32, G->stream);
+    launch_coarse_rhs32(c.geo, G->law32, a, c.beta, c.K32, c.pb32, c.dbar32, c.rhs32, c.dl, G->stream);
+    vcycle32_level(G, l + 1, nu1, nu2);
+    launch_prolong32(f.geo, c.geo, c.dl, c.dbar32, f.dl, G->stream);
+    sweep32_level(G, l, nu2);
+}
+
+// One outer defect correction: the FP64 defect is in lev[0].d; FP32 cycles
+// solve the correction equation and psi += delta in FP64.
+void mp_correction(rs_grid *G, int inner, int nu1, int nu2)
+{
+    LevelData &f = G->lev[0];
+    launch_mp_prep(f.geo.N, f.d, f.psi, f.rhs32, f.dl, f.pb32, G->stream);
+    for (int l = 1; l < G->nlev; ++l)
+        launch_inject32(G->lev[l].geo, G->lev[l - 1].geo, G->lev[l - 1].pb32, G->lev[l].pb32,
+                        G->stream);
+    for (int c = 0; c < inner; ++c) vcycle32_level(G, 0, nu1, nu2);
+    launch_apply_delta(f.geo.N, f.dl, f.psi, G->stream);
 }
 
 int vcycle_level(rs_grid *G, int l, int nu1, int nu2)
@@ -459,6 +527,9 @@ int rs_create_grid(const rs_grid_desc *d, int precision, void *ws_dev, size_t ws
         v.d = (double *)(base + L.lev_off[l][3]);
         v.psibar = (double *)(base + L.lev_off[l][4]);
         v.psi_alt = L.lev_off[l][5] ? (double *)(base + L.lev_off[l][5]) : nullptr;
+        float **mp[6] = {&v.dl, &v.K32, &v.rhs32, &v.r32, &v.dbar32, &v.pb32};
+        for (int a = 0; a < 6; ++a)
+            *mp[a] = L.mp_off[l][a] ? (float *)(base + L.mp_off[l][a]) : nullptr;
         v.beta = (double *)(base + L.beta_off[l]);
         v.lambdaU = 0.0;
         v.unknowns = count_unknowns(v.geo);
@@ -503,6 +574,7 @@ int rs_set_constitutive(rs_grid *G, const rs_constitutive *c)
     int e = validate_law(c);
     if (e) return e;
     G->law = make_law(c);
+    G->law32 = make_law32(G->law);
     G->step.lag_extrap = c->lag_extrap ? 1 : 0;
     if (c->Ks_field) {
         size_t bytes = sizeof(double) * (size_t)G->lev[0].geo.N;
@@ -570,6 +642,9 @@ int rs_begin_step(rs_grid *G, double dt, int order)
     launch_setup_g(f.geo, G->law, G->step, G->psi_n, G->psi_nm1, f.K, f.g, G->stream);
     for (int l = 1; l < G->nlev; ++l)
         launch_inject(G->lev[l].geo, G->lev[l - 1].geo, G->lev[l - 1].K, G->lev[l].K, G->stream);
+    if (G->precision == RS_MIXED)
+        for (int l = 0; l < G->nlev; ++l)
+            launch_to_f32(G->lev[l].geo.N, G->lev[l].K, G->lev[l].K32, G->stream);
     HIPCALL(hipGetLastError());
     if (G->law.kappa_rule == kKappaRemark) {
         launch_fill_u64(G->scratch + 1, G->nlev, 0ull, G->stream);
@@ -608,6 +683,21 @@ int rs_vcycle(rs_grid *G, int nu1, int nu2, double *res)
     if (nu1 < 0 || nu2 < 0) return fail(RS_EINVAL, "negative smoothing count");
     int e = vcycle_level(G, 0, nu1, nu2);
     if (e) return e;
+    HIPCALL(hipGetLastError());
+    if (res) return fine_norm(G, res);
+    return RS_OK;
+}
+
+int rs_correction_cycle(rs_grid *G, int inner_cycles, int nu1, int nu2, double *res)
+{
+    if (!G) return fail(RS_EINVAL, "null grid");
+    if (G->precision != RS_MIXED) return fail(RS_ESTATE, "grid was not created with RS_MIXED");
+    if (!G->in_step) return fail(RS_ESTATE, "no active step (call rs_begin_step)");
+    if (inner_cycles < 1 || nu1 < 0 || nu2 < 0) return fail(RS_EINVAL, "bad cycle counts");
+    double r;
+    int e = fine_norm(G, &r, G->lev[0].d);
+    if (e) return e;
+    mp_correction(G, inner_cycles, nu1, nu2);
     HIPCALL(hipGetLastError());
     if (res) return fine_norm(G, res);
     return RS_OK;
@@ -663,24 +753,39 @@ int rs_bdf_step(rs_grid *G, double dt, int order, const rs_solve_opts *o, rs_ste
     if (e) return e;
     double r0 = r;
     int cycles = 0, slow = 0, nh = 0;
+    double best = r;
     double hist[64];
     hist[nh++] = r;
     bool stagnated = false;
     G->updates = 0.0;
-    while (std::isfinite(r) && r > o->tol_abs && cycles < o->max_cycles) {
-        e = vcycle_level(G, 0, o->nu1, o->nu2);
+    const bool mixed = G->precision == RS_MIXED;
+    if (mixed) {
+        e = fine_norm(G, &r, G->lev[0].d);   // defect vector for the first correction
         if (e) return e;
+    }
+    while (std::isfinite(r) && r > o->tol_abs && cycles < o->max_cycles) {
+        if (mixed) {
+            mp_correction(G, o->mp_inner_cycles > 0 ? o->mp_inner_cycles : 1, o->nu1, o->nu2);
+        } else {
+            e = vcycle_level(G, 0, o->nu1, o->nu2);
+            if (e) return e;
+        }
         HIPCALL(hipGetLastError());
         double rn;
-        e = fine_norm(G, &rn);
+        e = fine_norm(G, &rn, mixed ? G->lev[0].d : nullptr);
         if (e) return e;
         ++cycles;
         if (nh < 64) hist[nh++] = rn;
-        if (o->stagnation) {
-            slow = (rn > 0.5 * r) ? slow + 1 : 0;
-            if (slow >= 2) { r = rn; stagnated = true; break; }
-        }
         r = rn;
+        if (o->stagnation) {
+            if (rn < best) {
+                best = rn;
+                slow = 0;
+            } else if (++slow >= 2) {
+                stagnated = true;
+                break;
+            }
+        }
     }
     int status = RS_OK;
     if (!std::isfinite(r)) status = RS_ENONFINITE;

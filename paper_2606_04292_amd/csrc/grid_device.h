@@ -1,0 +1,125 @@
+// Index and launch-shape helpers shared by the FP64 and FP32 kernels.
+#pragma once
+
+#include "rs_internal.h"
+#include "soil_device.h"
+
+namespace rs {
+
+constexpr int kBX = 64;
+constexpr int kBY = 4;
+
+// Maximum over a work-group (NaN wins); the result is valid in thread 0.
+__device__ __forceinline__ double block_max(double v)
+{
+    __shared__ double red[8];
+    int lane = threadIdx.x + threadIdx.y * blockDim.x;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        double o = __shfl_xor(v, off);
+        v = (o > v || o != o) ? o : v;
+    }
+    int wave = lane >> 6;
+    if ((lane & 63) == 0) red[wave] = v;
+    __syncthreads();
+    int nw = (blockDim.x * blockDim.y + 63) >> 6;
+    if (lane == 0) {
+        double m = red[0];
+        for (int w = 1; w < nw; ++w) m = (red[w] > m || red[w] != red[w]) ? red[w] : m;
+        v = m;
+    }
+    return v;
+}
+
+// Work-groups are dispatched round-robin over the 8 XCDs; renumber them so that
+// XCD x runs the contiguous logical range [x per, (x+1) per) and its L2 sees a
+// compact slab of the grid (neighbouring rows and planes hit in L2).  The grid
+// is padded to a multiple of 8; padded groups fall past the last cell.
+__device__ __forceinline__ unsigned xcd_block(unsigned per)
+{
+    return (blockIdx.x % 8u) * per + blockIdx.x / 8u;
+}
+
+inline unsigned xcd_grid(unsigned long long blocks) { return (unsigned)((blocks + 7) / 8 * 8); }
+
+// Packed enumeration of the cells of one colour: rows (fixed j, k) of
+// H = (n0 + 1) / 2 slots, slot ih -> i = 2 ih + parity; every lane of a wave
+// holds a cell (only the last slot of odd-parity rows falls outside).
+struct ColourMap {
+    unsigned long long total;
+    unsigned H;
+    double invH;
+    unsigned n1;
+    double invN1;
+};
+
+inline ColourMap colour_map(const Geo &g)
+{
+    ColourMap m;
+    m.H = (unsigned)((g.n[0] + 1) / 2);
+    m.invH = 1.0 / m.H;
+    m.n1 = (unsigned)g.n[1];
+    m.invN1 = 1.0 / m.n1;
+    m.total = (unsigned long long)m.H * g.n[1] * g.n[2];
+    return m;
+}
+
+// Visit the neighbours of node (i, j, k) along the first DIM axes in the
+// order axis 0 low/high, axis 1 low/high, axis 2 low/high; fn(jdx, coef, axis,
+// side) with coef = 1/(2 w h^2).
+template <int DIM, typename Fn>
+__device__ __forceinline__ void for_nb(const Geo &g, int i, int j, int k, long long idx, Fn &&fn)
+{
+#pragma unroll
+    for (int l = 0; l < DIM; ++l) {
+        const int cl = (l == 0) ? i : (l == 1 ? j : k);
+        const double cf = ((cl == 0 || cl == g.n[l] - 1) ? 1.0 : 0.5) * g.ih2[l];
+        const long long s = g.stride[l];
+        if (cl > 0) fn(idx - s, cf, l, -1);
+        if (cl < g.n[l] - 1) fn(idx + s, cf, l, +1);
+    }
+}
+
+struct NodeMap {
+    unsigned n0, n1;
+    double inv0, inv1;
+};
+
+inline NodeMap node_map(const Geo &g)
+{
+    NodeMap m;
+    m.n0 = (unsigned)g.n[0];
+    m.n1 = (unsigned)g.n[1];
+    m.inv0 = 1.0 / m.n0;
+    m.inv1 = 1.0 / m.n1;
+    return m;
+}
+
+inline dim3 node_grid(const Geo &g)
+{
+    return dim3((g.n[0] + kBX - 1) / kBX, (g.n[1] + kBY - 1) / kBY, g.n[2]);
+}
+
+
+// Call fn.template operator()<MODEL, SINK, DIM>() for the law and level.
+template <typename Fn>
+inline void dispatch(const Law &law, int dim, Fn &&fn)
+{
+    const bool s = law.sink == kSinkFeddes;
+#define RS_DIMS(M, S)                                   \
+    do {                                                \
+        if (dim == 1) fn.template go<M, S, 1>();        \
+        else if (dim == 2) fn.template go<M, S, 2>();   \
+        else fn.template go<M, S, 3>();                 \
+    } while (0)
+    if (law.model == kHaverkamp) {
+        if (s) RS_DIMS(kHaverkamp, true); else RS_DIMS(kHaverkamp, false);
+    } else if (law.model == kVgm) {
+        if (s) RS_DIMS(kVgm, true); else RS_DIMS(kVgm, false);
+    } else {
+        if (s) RS_DIMS(kLinear, true); else RS_DIMS(kLinear, false);
+    }
+#undef RS_DIMS
+}
+
+}  // namespace rs

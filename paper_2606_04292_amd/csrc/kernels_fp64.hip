@@ -14,13 +14,12 @@
 
 #include "rs_internal.h"
 #include "soil_device.h"
+#include "grid_device.h"
+#include "transfer.h"
 
 namespace rs {
 
 namespace {
-
-constexpr int kBX = 64;
-constexpr int kBY = 4;
 
 // Visit the existing neighbours of node c (order: axis 0 low/high, axis 1,
 // axis 2), calling fn(jdx, coef, axis, side) with coef = 1/(2 w h^2).
@@ -60,27 +59,6 @@ __device__ __forceinline__ double apply_N(const Geo &g, const Law &L, const Step
         mpsi += cf * (Ki + K[j]) * (x - psi[j]);
     });
     return s + (L.xi * x + mpsi);
-}
-
-__device__ __forceinline__ double block_max(double v)
-{
-    __shared__ double red[8];
-    int lane = threadIdx.x + threadIdx.y * blockDim.x;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        double o = __shfl_xor(v, off);
-        v = (o > v || o != o) ? o : v;
-    }
-    int wave = lane >> 6;
-    if ((lane & 63) == 0) red[wave] = v;
-    __syncthreads();
-    int nw = (blockDim.x * blockDim.y + 63) >> 6;
-    if (lane == 0) {
-        double m = red[0];
-        for (int w = 1; w < nw; ++w) m = (red[w] > m || red[w] != red[w]) ? red[w] : m;
-        v = m;
-    }
-    return v;
 }
 
 __global__ void k_fill_u64(unsigned long long *p, int n, unsigned long long v)
@@ -191,55 +169,6 @@ __global__ __launch_bounds__(256) void k_lambda_u(Geo g, const double *K, unsign
 // ---------------------------------------------------------------------------
 // Red-black NGS (eq. iterative / eq. point-update)
 // ---------------------------------------------------------------------------
-
-// Work-groups are dispatched round-robin over the 8 XCDs; renumber them so that
-// XCD x runs the contiguous logical range [x per, (x+1) per) and its L2 sees a
-// compact slab of the grid (neighbouring rows and planes hit in L2).  The grid
-// is padded to a multiple of 8; padded groups fall past the last cell.
-__device__ __forceinline__ unsigned xcd_block(unsigned per)
-{
-    return (blockIdx.x % 8u) * per + blockIdx.x / 8u;
-}
-
-unsigned xcd_grid(unsigned long long blocks) { return (unsigned)((blocks + 7) / 8 * 8); }
-
-// Packed enumeration of the cells of one colour: rows (fixed j, k) of
-// H = (n0 + 1) / 2 slots, slot ih -> i = 2 ih + parity; every lane of a wave
-// holds a cell (only the last slot of odd-parity rows falls outside).
-struct ColourMap {
-    unsigned long long total;
-    unsigned H;
-    double invH;
-    unsigned n1;
-    double invN1;
-};
-
-ColourMap colour_map(const Geo &g)
-{
-    ColourMap m;
-    m.H = (unsigned)((g.n[0] + 1) / 2);
-    m.invH = 1.0 / m.H;
-    m.n1 = (unsigned)g.n[1];
-    m.invN1 = 1.0 / m.n1;
-    m.total = (unsigned long long)m.H * g.n[1] * g.n[2];
-    return m;
-}
-
-// Visit the neighbours of node (i, j, k) along the first DIM axes in the
-// order axis 0 low/high, axis 1 low/high, axis 2 low/high; fn(jdx, coef, axis,
-// side) with coef = 1/(2 w h^2).
-template <int DIM, typename Fn>
-__device__ __forceinline__ void for_nb(const Geo &g, int i, int j, int k, long long idx, Fn &&fn)
-{
-#pragma unroll
-    for (int l = 0; l < DIM; ++l) {
-        const int cl = (l == 0) ? i : (l == 1 ? j : k);
-        const double cf = ((cl == 0 || cl == g.n[l] - 1) ? 1.0 : 0.5) * g.ih2[l];
-        const long long s = g.stride[l];
-        if (cl > 0) fn(idx - s, cf, l, -1);
-        if (cl < g.n[l] - 1) fn(idx + s, cf, l, +1);
-    }
-}
 
 // New value of unknown (i, j, k) from eq. point-update: f_i = g_i +
 // sum_j m_ij psi_j + kappa_i psi_i, c_i = xi + kappa_i + m_ii, then the
@@ -443,21 +372,6 @@ __global__ __launch_bounds__(256) void k_sweep_small(Geo g, Law L, Step st, cons
 // Defect d = g - N(psi) and its max-norm (step 2 of the FAS algorithm)
 // ---------------------------------------------------------------------------
 
-struct NodeMap {
-    unsigned n0, n1;
-    double inv0, inv1;
-};
-
-NodeMap node_map(const Geo &g)
-{
-    NodeMap m;
-    m.n0 = (unsigned)g.n[0];
-    m.n1 = (unsigned)g.n[1];
-    m.inv0 = 1.0 / m.n0;
-    m.inv1 = 1.0 / m.n1;
-    return m;
-}
-
 template <int MODEL, bool SINK, int DIM>
 __device__ __forceinline__ double apply_N_t(const Geo &g, const Law &L, double a,
                                             const double *beta, const double *K,
@@ -520,53 +434,6 @@ __global__ __launch_bounds__(256) void k_residual(Geo g, Law L, Step st, const d
 // Transfers (section 3.2 steps 3, 4 and 6)
 // ---------------------------------------------------------------------------
 
-// psibar_H = FW(psi_h), d_H = FW(d_h) stored in g_H (Dirichlet coarse nodes:
-// injection of psi, zero defect).  FW: tensor (1/4, 1/2, 1/4) around fine node
-// 2I, missing neighbours mirrored at the domain boundary.
-__global__ __launch_bounds__(256) void k_restrict(Geo gc, Geo gf, const double *psi_f,
-                                                  const double *d_f, double *psibar_c,
-                                                  double *g_c)
-{
-    int I0 = blockIdx.x * kBX + threadIdx.x;
-    int I1 = blockIdx.y * kBY + threadIdx.y;
-    int I2 = blockIdx.z;
-    if (I0 >= gc.n[0] || I1 >= gc.n[1]) return;
-    long long I = I0 + (long long)I1 * gc.stride[1] + (long long)I2 * gc.stride[2];
-    int F[3] = {2 * I0, 2 * I1, 2 * I2};
-    if (dirichlet_at(gc, I0, I1, I2, nullptr)) {
-        psibar_c[I] = psi_f[F[0] + (long long)F[1] * gf.stride[1] + (long long)F[2] * gf.stride[2]];
-        g_c[I] = 0.0;
-        return;
-    }
-    int lo[3], hi[3];
-#pragma unroll
-    for (int l = 0; l < 3; ++l) {
-        lo[l] = (l < gf.dim) ? -1 : 0;
-        hi[l] = (l < gf.dim) ? 1 : 0;
-    }
-    double sp = 0.0, sd = 0.0;
-    for (int o2 = lo[2]; o2 <= hi[2]; ++o2) {
-        int f2 = F[2] + o2;
-        f2 = f2 < 0 ? -f2 : (f2 > gf.n[2] - 1 ? 2 * (gf.n[2] - 1) - f2 : f2);
-        double w2 = (gf.dim > 2) ? (o2 == 0 ? 0.5 : 0.25) : 1.0;
-        for (int o1 = lo[1]; o1 <= hi[1]; ++o1) {
-            int f1 = F[1] + o1;
-            f1 = f1 < 0 ? -f1 : (f1 > gf.n[1] - 1 ? 2 * (gf.n[1] - 1) - f1 : f1);
-            double w1 = (gf.dim > 1) ? (o1 == 0 ? 0.5 : 0.25) : 1.0;
-            for (int o0 = -1; o0 <= 1; ++o0) {
-                int f0 = F[0] + o0;
-                f0 = f0 < 0 ? -f0 : (f0 > gf.n[0] - 1 ? 2 * (gf.n[0] - 1) - f0 : f0);
-                double w = (o0 == 0 ? 0.5 : 0.25) * w1 * w2;
-                long long fi = f0 + (long long)f1 * gf.stride[1] + (long long)f2 * gf.stride[2];
-                sp += w * psi_f[fi];
-                sd += w * d_f[fi];
-            }
-        }
-    }
-    psibar_c[I] = sp;
-    g_c[I] = sd;
-}
-
 // g_H = N_H(psibar_H) + d_H (g_H holds d_H on entry), psi_H = psibar_H.
 __global__ __launch_bounds__(256) void k_coarse_rhs(Geo g, Law L, Step st, const double *beta,
                                                     const double *K, const double *psibar,
@@ -582,44 +449,6 @@ __global__ __launch_bounds__(256) void k_coarse_rhs(Geo g, Law L, Step st, const
         gv[idx] = apply_N(g, L, st, beta, K, psibar, c, idx) + gv[idx];
     }
     psi[idx] = psibar[idx];
-}
-
-// psi_h += I_h^H (psi_H - psibar_H) at fine unknowns (tensor linear
-// interpolation: even index -> coarse node, odd -> mean of the two).
-__global__ __launch_bounds__(256) void k_prolong(Geo gf, Geo gc, const double *psi_c,
-                                                 const double *psibar_c, double *psi_f)
-{
-    int i = blockIdx.x * kBX + threadIdx.x;
-    int j = blockIdx.y * kBY + threadIdx.y;
-    int k = blockIdx.z;
-    if (i >= gf.n[0] || j >= gf.n[1]) return;
-    if (dirichlet_at(gf, i, j, k, nullptr)) return;
-    int c[3] = {i, j, k};
-    int a0[3], a1[3], cnt[3];
-    double wt[3];
-#pragma unroll
-    for (int l = 0; l < 3; ++l) {
-        if (c[l] & 1) {
-            a0[l] = (c[l] - 1) >> 1;
-            a1[l] = (c[l] + 1) >> 1;
-            cnt[l] = 2;
-            wt[l] = 0.5;
-        } else {
-            a0[l] = a1[l] = c[l] >> 1;
-            cnt[l] = 1;
-            wt[l] = 1.0;
-        }
-    }
-    double e = 0.0;
-    for (int q2 = 0; q2 < cnt[2]; ++q2)
-        for (int q1 = 0; q1 < cnt[1]; ++q1)
-            for (int q0 = 0; q0 < cnt[0]; ++q0) {
-                long long J = (q0 ? a1[0] : a0[0]) + (long long)(q1 ? a1[1] : a0[1]) * gc.stride[1] +
-                              (long long)(q2 ? a1[2] : a0[2]) * gc.stride[2];
-                e += wt[0] * wt[1] * wt[2] * (psi_c[J] - psibar_c[J]);
-            }
-    long long idx = i + (long long)j * gf.stride[1] + (long long)k * gf.stride[2];
-    psi_f[idx] += e;
 }
 
 // Root density of the Feddes-exponential sink on every level:
@@ -653,11 +482,6 @@ __global__ __launch_bounds__(256) void k_root_beta(BetaArgs a)
     for (int l = 0; l < a.nlev; ++l)
         for (int k = threadIdx.x; k < a.nvert[l]; k += blockDim.x)
             a.beta[l][k] = a.Tp * exp(-(a.Lz - k * a.hvert[l]) / a.rl) / Z;
-}
-
-dim3 node_grid(const Geo &g)
-{
-    return dim3((g.n[0] + kBX - 1) / kBX, (g.n[1] + kBY - 1) / kBY, g.n[2]);
 }
 
 }  // namespace
@@ -710,27 +534,6 @@ void launch_inject(const Geo &gc, const Geo &gf, const double *Kf, double *Kc, h
 void launch_lambda_u(const Geo &g, const double *K, unsigned long long *out, hipStream_t s)
 {
     hipLaunchKernelGGL(k_lambda_u, node_grid(g), dim3(kBX, kBY), 0, s, g, K, out);
-}
-
-// Call fn.template operator()<MODEL, SINK, DIM>() for the law and level.
-template <typename Fn>
-void dispatch(const Law &law, int dim, Fn &&fn)
-{
-    const bool s = law.sink == kSinkFeddes;
-#define RS_DIMS(M, S)                                   \
-    do {                                                \
-        if (dim == 1) fn.template go<M, S, 1>();        \
-        else if (dim == 2) fn.template go<M, S, 2>();   \
-        else fn.template go<M, S, 3>();                 \
-    } while (0)
-    if (law.model == kHaverkamp) {
-        if (s) RS_DIMS(kHaverkamp, true); else RS_DIMS(kHaverkamp, false);
-    } else if (law.model == kVgm) {
-        if (s) RS_DIMS(kVgm, true); else RS_DIMS(kVgm, false);
-    } else {
-        if (s) RS_DIMS(kLinear, true); else RS_DIMS(kLinear, false);
-    }
-#undef RS_DIMS
 }
 
 // Tile extents of the fused sweep (x, y, z-chunk); RS_FUSED_TILE="tx,ty,zc"
@@ -840,7 +643,7 @@ void launch_residual(const Geo &g, const Law &law, const Step &st, const double 
 void launch_restrict(const Geo &gc, const Geo &gf, const double *psi_f, const double *d_f,
                      double *psibar_c, double *g_c, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_restrict, node_grid(gc), dim3(kBX, kBY), 0, s, gc, gf, psi_f, d_f,
+    hipLaunchKernelGGL((k_restrict<double>), node_grid(gc), dim3(kBX, kBY), 0, s, gc, gf, psi_f, d_f,
                        psibar_c, g_c);
 }
 
@@ -855,7 +658,7 @@ void launch_coarse_rhs(const Geo &gc, const Law &law, const Step &st, const doub
 void launch_prolong(const Geo &gf, const Geo &gc, const double *psi_c, const double *psibar_c,
                     double *psi_f, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_prolong, node_grid(gf), dim3(kBX, kBY), 0, s, gf, gc, psi_c, psibar_c,
+    hipLaunchKernelGGL((k_prolong<double>), node_grid(gf), dim3(kBX, kBY), 0, s, gf, gc, psi_c, psibar_c,
                        psi_f);
 }
 

@@ -1,0 +1,329 @@
+// FP32 kernels of the mixed-precision solve: FAS V-cycles in FP32 on the
+// correction equation N(psi_b + delta) - N(psi_b) = r (see soil_mp.h), inside
+// an FP64 defect-correction loop whose residual, history and stopping test stay
+// in FP64 (kernels_fp64.hip).  Per level the FP32 cycles keep delta, K*, the
+// right-hand side, the inner defect, the restricted delta and the base state
+// psi_b, 4 B each; a sweep moves delta, K*, rhs and psi_b (20 B per update).
+#include <cstdio>
+
+#include "rs_internal.h"
+#include "soil_device.h"
+#include "grid_device.h"
+#include "transfer.h"
+#include "soil_mp.h"
+
+namespace rs {
+
+namespace {
+
+template <int DIM>
+__device__ __forceinline__ int vert_index(int i, int j, int k)
+{
+    return (DIM == 1) ? i : (DIM == 2 ? j : k);
+}
+
+// New delta at unknown (i, j, k): f = rhs + sum_j m_ij delta_j + kappa delta_i,
+// c = xi + kappa + m_ii, then the scalar correction solve.
+template <int MODEL, bool SINK, int DIM>
+__device__ __forceinline__ void ngs_cell32(const Geo &g, const Law32 &L, float a,
+                                           const double *beta, float lambdaU, const float *K,
+                                           const float *rhs, const float *pb, float *dl, int i,
+                                           int j, int k, int colour)
+{
+    const long long idx = i + (long long)j * g.stride[1] + (long long)k * g.stride[2];
+    const float Ki = K[idx];
+    float f = rhs[idx];
+    float mii = 0.0f, usum = 0.0f;
+    const bool remark = (L.kappa_rule == kKappaRemark) && colour == 0;
+    for_nb<DIM>(g, i, j, k, idx, [&](long long jn, double cf, int l, int side) {
+        const float m = (float)cf * (Ki + K[jn]);
+        mii += m;
+        f += m * dl[jn];
+        if (remark) {
+            int d[3] = {i, j, k};
+            d[l] += side;
+            if (!dirichlet_at(g, d[0], d[1], d[2], nullptr)) usum += m;
+        }
+    });
+    float kap;
+    if (L.kappa_rule == kKappaConst) kap = L.kappa;
+    else if (L.kappa_rule == kKappaRel) kap = L.kappa * mii;
+    else kap = (colour == 0) ? lambdaU - usum : lambdaU;
+    const float d0 = dl[idx];
+    f += kap * d0;
+    const float c = L.xi + kap + mii;
+    const float bz = SINK ? (float)beta[vert_index<DIM>(i, j, k)] : 0.0f;
+    const Base b = base_of<MODEL>(L, pb[idx]);
+    dl[idx] = local_solve32<MODEL, SINK>(L, a, bz, c, f, b, d0);
+}
+
+template <int MODEL, bool SINK, int DIM>
+__global__ __launch_bounds__(256) void k_sweep32(Geo g, Law32 L, float a, const double *beta,
+                                                 float lambdaU, const float *K, const float *rhs,
+                                                 const float *pb, float *dl, int colour,
+                                                 ColourMap cm)
+{
+    const unsigned long long t =
+        (unsigned long long)xcd_block(gridDim.x / 8u) * blockDim.x + threadIdx.x;
+    if (t >= cm.total) return;
+    const unsigned row = udiv(t, cm.H, cm.invH);
+    const unsigned ih = (unsigned)(t - (unsigned long long)row * cm.H);
+    unsigned j = 0, k = 0;
+    if (DIM == 3) {
+        k = udiv(row, cm.n1, cm.invN1);
+        j = row - k * cm.n1;
+    } else if (DIM == 2) {
+        j = row;
+    }
+    const int i = 2 * (int)ih + (int)((j + k + colour) & 1);
+    if (i >= g.n[0]) return;
+    if (dirichlet_at(g, i, (int)j, (int)k, nullptr)) return;
+    ngs_cell32<MODEL, SINK, DIM>(g, L, a, beta, lambdaU, K, rhs, pb, dl, i, (int)j, (int)k, colour);
+}
+
+template <int MODEL, bool SINK, int DIM>
+__global__ __launch_bounds__(256) void k_sweep32_small(Geo g, Law32 L, float a, const double *beta,
+                                                       float lambdaU, const float *K,
+                                                       const float *rhs, const float *pb,
+                                                       float *dl, int nsweeps)
+{
+    const int N = (int)g.N;
+    for (int s = 0; s < nsweeps; ++s) {
+        for (int colour = 0; colour < 2; ++colour) {
+            for (int t = threadIdx.x; t < N; t += blockDim.x) {
+                int i = t % g.n[0];
+                int r = t / g.n[0];
+                int j = r % g.n[1];
+                int k = r / g.n[1];
+                if (((i + j + k) & 1) != colour) continue;
+                if (dirichlet_at(g, i, j, k, nullptr)) continue;
+                ngs_cell32<MODEL, SINK, DIM>(g, L, a, beta, lambdaU, K, rhs, pb, dl, i, j, k, colour);
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// N_delta(delta)_i = a dtheta + beta da + xi delta_i + sum_j m_ij (delta_i - delta_j)
+template <int MODEL, bool SINK, int DIM>
+__device__ __forceinline__ float apply_Nd(const Geo &g, const Law32 &L, float a,
+                                          const double *beta, const float *K, const float *pb,
+                                          const float *dl, int i, int j, int k, long long idx)
+{
+    const float x = dl[idx];
+    const float Ki = K[idx];
+    const Base b = base_of<MODEL>(L, pb[idx]);
+    float dth, slope;
+    dtheta32<MODEL>(L, b, x, dth, slope);
+    float s = a * dth;
+    if (SINK) {
+        float da, ds;
+        dfeddes32(L, b.psi, x, da, ds);
+        s += (float)beta[vert_index<DIM>(i, j, k)] * da;
+    }
+    float md = 0.0f;
+    for_nb<DIM>(g, i, j, k, idx, [&](long long jn, double cf, int, int) {
+        md += (float)cf * (Ki + K[jn]) * (x - dl[jn]);
+    });
+    return s + (L.xi * x + md);
+}
+
+// Inner defect r32 = rhs - N_delta(delta) (0 at Dirichlet nodes).
+template <int MODEL, bool SINK, int DIM>
+__global__ __launch_bounds__(256) void k_residual32(Geo g, Law32 L, float a, const double *beta,
+                                                    const float *K, const float *rhs,
+                                                    const float *pb, const float *dl, float *r)
+{
+    int i = blockIdx.x * kBX + threadIdx.x;
+    int j = blockIdx.y * kBY + threadIdx.y;
+    int k = blockIdx.z;
+    if (i >= g.n[0] || j >= g.n[1]) return;
+    long long idx = i + (long long)j * g.stride[1] + (long long)k * g.stride[2];
+    float v = 0.0f;
+    if (!dirichlet_at(g, i, j, k, nullptr))
+        v = rhs[idx] - apply_Nd<MODEL, SINK, DIM>(g, L, a, beta, K, pb, dl, i, j, k, idx);
+    r[idx] = v;
+}
+
+// FAS coarse right-hand side of the correction equation:
+// rhs_H = N_delta,H(dbar_H) + r_H (rhs_H holds r_H on entry), delta_H = dbar_H.
+template <int MODEL, bool SINK, int DIM>
+__global__ __launch_bounds__(256) void k_coarse_rhs32(Geo g, Law32 L, float a, const double *beta,
+                                                      const float *K, const float *pb,
+                                                      const float *dbar, float *rhs, float *dl)
+{
+    int i = blockIdx.x * kBX + threadIdx.x;
+    int j = blockIdx.y * kBY + threadIdx.y;
+    int k = blockIdx.z;
+    if (i >= g.n[0] || j >= g.n[1]) return;
+    long long idx = i + (long long)j * g.stride[1] + (long long)k * g.stride[2];
+    if (!dirichlet_at(g, i, j, k, nullptr))
+        rhs[idx] = apply_Nd<MODEL, SINK, DIM>(g, L, a, beta, K, pb, dbar, i, j, k, idx) + rhs[idx];
+    dl[idx] = dbar[idx];
+}
+
+// Start of an outer correction on the finest level: rhs = fl32(FP64 defect),
+// delta = 0, psi_b = fl32(psi).
+__global__ __launch_bounds__(256) void k_mp_prep(long long N, const double *d64,
+                                                 const double *psi64, float *rhs, float *dl,
+                                                 float *pb)
+{
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N) return;
+    rhs[t] = (float)d64[t];
+    dl[t] = 0.0f;
+    pb[t] = (float)psi64[t];
+}
+
+__global__ __launch_bounds__(256) void k_to_f32(long long N, const double *src, float *dst)
+{
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < N) dst[t] = (float)src[t];
+}
+
+// psi += delta in FP64 (delta is 0 at Dirichlet nodes).
+__global__ __launch_bounds__(256) void k_apply_delta(long long N, const float *dl, double *psi64)
+{
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < N) psi64[t] += (double)dl[t];
+}
+
+unsigned blocks_for(long long N) { return (unsigned)((N + 255) / 256); }
+
+struct Sweep32Launch {
+    const Geo &g; const Law32 &law; float a; const double *beta; float lambdaU; const float *K;
+    const float *rhs; const float *pb; float *dl; int nsweeps; hipStream_t s;
+    template <int M, bool S, int D>
+    void go()
+    {
+        if (g.N <= 1024) {
+            hipLaunchKernelGGL((k_sweep32_small<M, S, D>), dim3(1), dim3(256), 0, s, g, law, a, beta,
+                               lambdaU, K, rhs, pb, dl, nsweeps);
+            return;
+        }
+        ColourMap cm = colour_map(g);
+        dim3 grid(xcd_grid((cm.total + 255) / 256));
+        for (int sw = 0; sw < nsweeps; ++sw)
+            for (int colour = 0; colour < 2; ++colour)
+                hipLaunchKernelGGL((k_sweep32<M, S, D>), grid, dim3(256), 0, s, g, law, a, beta,
+                                   lambdaU, K, rhs, pb, dl, colour, cm);
+    }
+};
+
+struct Residual32Launch {
+    const Geo &g; const Law32 &law; float a; const double *beta; const float *K; const float *rhs;
+    const float *pb; const float *dl; float *r; hipStream_t s;
+    template <int M, bool S, int D>
+    void go()
+    {
+        hipLaunchKernelGGL((k_residual32<M, S, D>), node_grid(g), dim3(kBX, kBY), 0, s, g, law, a,
+                           beta, K, rhs, pb, dl, r);
+    }
+};
+
+struct CoarseRhs32Launch {
+    const Geo &g; const Law32 &law; float a; const double *beta; const float *K; const float *pb;
+    const float *dbar; float *rhs; float *dl; hipStream_t s;
+    template <int M, bool S, int D>
+    void go()
+    {
+        hipLaunchKernelGGL((k_coarse_rhs32<M, S, D>), node_grid(g), dim3(kBX, kBY), 0, s, g, law, a,
+                           beta, K, pb, dbar, rhs, dl);
+    }
+};
+
+// dispatch() keys on Law::model / Law::sink; build a Law carrying those two.
+Law dispatch_key(const Law32 &l)
+{
+    Law k{};
+    k.model = l.model;
+    k.sink = l.sink;
+    return k;
+}
+
+}  // namespace
+
+Law32 make_law32(const Law &L)
+{
+    Law32 f;
+    f.model = L.model;
+    f.ts = (float)L.ts;
+    f.tr = (float)L.tr;
+    f.dT = (float)L.dT;
+    f.vg_alpha = (float)L.vg_alpha;
+    f.vg_n = (float)L.vg_n;
+    f.vg_m = (float)L.vg_m;
+    f.hk_alpha = (float)L.hk_alpha;
+    f.hk_beta = (float)L.hk_beta;
+    f.unit = (float)L.unit;
+    f.lin_c = (float)L.lin_c;
+    f.sink = L.sink;
+    f.h1 = (float)L.h1;
+    f.h2 = (float)L.h2;
+    f.h3 = (float)L.h3;
+    f.h4 = (float)L.h4;
+    f.xi = (float)L.xi;
+    f.kappa = (float)L.kappa;
+    f.kappa_rule = L.kappa_rule;
+    f.newton = L.newton;
+    return f;
+}
+
+void launch_sweep32(const Geo &g, const Law32 &law, float a, const double *beta, float lambdaU,
+                    const float *K, const float *rhs, const float *pb, float *dl, int nsweeps,
+                    hipStream_t s)
+{
+    if (nsweeps <= 0) return;
+    dispatch(dispatch_key(law), g.dim,
+             Sweep32Launch{g, law, a, beta, lambdaU, K, rhs, pb, dl, nsweeps, s});
+}
+
+void launch_residual32(const Geo &g, const Law32 &law, float a, const double *beta, const float *K,
+                       const float *rhs, const float *pb, const float *dl, float *r, hipStream_t s)
+{
+    dispatch(dispatch_key(law), g.dim, Residual32Launch{g, law, a, beta, K, rhs, pb, dl, r, s});
+}
+
+void launch_coarse_rhs32(const Geo &g, const Law32 &law, float a, const double *beta,
+                         const float *K, const float *pb, const float *dbar, float *rhs, float *dl,
+                         hipStream_t s)
+{
+    dispatch(dispatch_key(law), g.dim, CoarseRhs32Launch{g, law, a, beta, K, pb, dbar, rhs, dl, s});
+}
+
+void launch_restrict32(const Geo &gc, const Geo &gf, const float *dl_f, const float *r_f,
+                       float *dbar_c, float *rhs_c, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_restrict<float>), node_grid(gc), dim3(kBX, kBY), 0, s, gc, gf, dl_f, r_f,
+                       dbar_c, rhs_c);
+}
+
+void launch_prolong32(const Geo &gf, const Geo &gc, const float *dl_c, const float *dbar_c,
+                      float *dl_f, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_prolong<float>), node_grid(gf), dim3(kBX, kBY), 0, s, gf, gc, dl_c,
+                       dbar_c, dl_f);
+}
+
+void launch_inject32(const Geo &gc, const Geo &gf, const float *vf, float *vc, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_inject_t<float>), node_grid(gc), dim3(kBX, kBY), 0, s, gc, gf, vf, vc);
+}
+
+void launch_mp_prep(long long N, const double *d64, const double *psi64, float *rhs, float *dl,
+                    float *pb, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mp_prep, dim3(blocks_for(N)), dim3(256), 0, s, N, d64, psi64, rhs, dl, pb);
+}
+
+void launch_to_f32(long long N, const double *src, float *dst, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_to_f32, dim3(blocks_for(N)), dim3(256), 0, s, N, src, dst);
+}
+
+void launch_apply_delta(long long N, const float *dl, double *psi64, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_apply_delta, dim3(blocks_for(N)), dim3(256), 0, s, N, dl, psi64);
+}
+
+}  // namespace rs

@@ -1,0 +1,28 @@
+// Launchers of the FP32 correction cycles (kernels_mp.hip).
+#pragma once
+
+#include "rs_internal.h"
+#include "soil_mp.h"
+
+namespace rs {
+
+Law32 make_law32(const Law &L);
+void launch_sweep32(const Geo &g, const Law32 &law, float a, const double *beta, float lambdaU,
+                    const float *K, const float *rhs, const float *pb, float *dl, int nsweeps,
+                    hipStream_t s);
+void launch_residual32(const Geo &g, const Law32 &law, float a, const double *beta, const float *K,
+                       const float *rhs, const float *pb, const float *dl, float *r, hipStream_t s);
+void launch_coarse_rhs32(const Geo &g, const Law32 &law, float a, const double *beta,
+                         const float *K, const float *pb, const float *dbar, float *rhs, float *dl,
+                         hipStream_t s);
+void launch_restrict32(const Geo &gc, const Geo &gf, const float *dl_f, const float *r_f,
+                       float *dbar_c, float *rhs_c, hipStream_t s);
+void launch_prolong32(const Geo &gf, const Geo &gc, const float *dl_c, const float *dbar_c,
+                      float *dl_f, hipStream_t s);
+void launch_inject32(const Geo &gc, const Geo &gf, const float *vf, float *vc, hipStream_t s);
+void launch_mp_prep(long long N, const double *d64, const double *psi64, float *rhs, float *dl,
+                    float *pb, hipStream_t s);
+void launch_to_f32(long long N, const double *src, float *dst, hipStream_t s);
+void launch_apply_delta(long long N, const float *dl, double *psi64, hipStream_t s);
+
+}  // namespace rs

@@ -216,7 +216,6 @@ __device__ __forceinline__ double local_solve_t(const Law &L, double a, double b
     }
     double x = x0;
     const int iters = NEWTON > 0 ? NEWTON : L.newton;
-#pragma unroll
     for (int k = 0; k < iters; ++k) {
         ThetaEval t = theta_t<MODEL>(L, x);
         double F = a * t.th + c * x - f;

@@ -21,6 +21,11 @@ pytestmark = pytest.mark.gpu
 
 TOL_SWEEP = 1e-12
 TOL_CONV = 1e-10
+# Cycle budget for iterating to the rounding floor.  The REMARK shift gives
+# black rows kappa = max row sum of U over the whole grid, which on a drying
+# Haverkamp block (K* over many decades) contracts at 0.93-0.99 per cycle:
+# thousands of cycles on 17^3.
+FLOOR_CYCLES = 8000
 
 
 def say(*a):
@@ -68,7 +73,7 @@ def advance(w, steps):
     S = oracle.Solver(w, oracle.ORDER_RB)
     for _ in range(steps):
         S.begin_step()
-        oracle.solve_to_floor(S, 60, 0.0)
+        oracle.solve_to_floor(S, FLOOR_CYCLES, 0.0)
         S.end_step()
     return S.get(oracle.FIELD_PSI_N), S.get(oracle.FIELD_PSI_NM1)
 
@@ -154,10 +159,10 @@ def test_converged_steps_parity(torch_cuda, name):
     say("converged parity", name)
     S = oracle.Solver(w, oracle.ORDER_RB)
     G = rsl.Grid(w)
-    opts = rsl.solve_opts(w.nu1, w.nu2, w.nu_coarse, max_cycles=60, tol_abs=0.0, stagnation=1)
+    opts = rsl.solve_opts(w.nu1, w.nu2, w.nu_coarse, max_cycles=FLOOR_CYCLES, tol_abs=0.0, stagnation=1)
     for step in range(3):
         S.begin_step()
-        oracle.solve_to_floor(S, 60, 0.0)
+        oracle.solve_to_floor(S, FLOOR_CYCLES, 0.0)
         S.end_step()
         code, st = G.bdf_step(opts=opts)
         assert code == rsl.RS_OK, rsl.lib().rs_last_error()
