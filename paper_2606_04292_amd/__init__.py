@@ -18,7 +18,7 @@ from . import workloads
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_lib", "librichards.so")
 
-RS_OK, RS_EINVAL, RS_ENOMEM, RS_EHIP, RS_ESTATE, RS_ENONFINITE, RS_ENOTCONV = range(7)
+RS_OK, RS_EINVAL, RS_ENOMEM, RS_EHIP, RS_ESTATE, RS_ENONFINITE, RS_ENOTCONV, RS_EBUSY = range(8)
 RS_FP64, RS_MIXED = 0, 1
 FIELD_PSI, FIELD_KSTAR, FIELD_G, FIELD_PSIBAR = 0, 1, 2, 3
 
@@ -28,6 +28,10 @@ EXPORTS = [
     "rs_residual", "rs_end_step", "rs_bdf_step", "rs_copy_field", "rs_set_field",
     "rs_num_levels", "rs_level_shape", "rs_destroy_grid", "rs_last_error",
     "rs_profile_enable", "rs_profile_read", "rs_correction_cycle",
+    # include/richards_serve.h
+    "rs_engine_default_opts", "rs_engine_control_bytes", "rs_engine_request_bytes",
+    "rs_engine_create", "rs_engine_submit", "rs_engine_tick", "rs_engine_fetch",
+    "rs_engine_capacity", "rs_engine_destroy",
 ]
 
 

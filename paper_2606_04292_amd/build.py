@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "librichards.so")
-SOURCES = ["api.hip", "kernels_fp64.hip", "kernels_mp.hip"]
+SOURCES = ["api.hip", "kernels_fp64.hip", "kernels_mp.hip", "engine.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

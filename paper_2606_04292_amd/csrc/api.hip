@@ -14,6 +14,7 @@
 #include "../../include/richards.h"
 #include "rs_internal.h"
 #include "mp_internal.h"
+#include "host_common.h"
 
 namespace rs {
 void launch_root_beta(int nlev, const int *nvert, const double *hvert, double *const *beta,
@@ -22,11 +23,10 @@ void launch_root_beta(int nlev, const int *nvert, const double *hvert, double *c
 
 using namespace rs;
 
-namespace {
+namespace rs {
 
 thread_local std::string g_err;
 
-int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 int fail(int code, const char *fmt, ...)
 {
     char buf[512];
@@ -38,17 +38,7 @@ int fail(int code, const char *fmt, ...)
     return code;
 }
 
-#define HIPCALL(x)                                                                     \
-    do {                                                                               \
-        hipError_t e_ = (x);                                                           \
-        if (e_ != hipSuccess) return fail(RS_EHIP, "%s: %s", #x, hipGetErrorString(e_)); \
-    } while (0)
-
-constexpr size_t kAlign = 256;
-
-size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
-
-bool pow2p1(int n)
+static bool pow2p1(int n)
 {
     if (n < 3) return false;
     int m = n - 1;
@@ -134,6 +124,10 @@ Geo make_geo(const rs_grid_desc *d, int lev)
     return g;
 }
 
+}  // namespace rs
+
+namespace {
+
 // Workspace layout: per level psi, K, g, d, psibar (FP64) and the root
 // density table; fine-level history psi^n, psi^{n-1}, the Ks field; scratch.
 struct Layout {
@@ -189,6 +183,10 @@ struct LevelData {
     long long unknowns;
 };
 
+}  // namespace
+
+namespace rs {
+
 // Unknown (non-Dirichlet) nodes of a level, counted on the host from the same
 // index rules the kernels use.
 long long count_unknowns(const Geo &g)
@@ -228,7 +226,7 @@ long long count_unknowns(const Geo &g)
     return g.N - dirichlet;
 }
 
-}  // namespace
+}  // namespace rs
 
 struct rs_grid {
     rs_grid_desc desc;
@@ -260,7 +258,7 @@ struct rs_grid {
     double prof_cells;
 };
 
-namespace {
+namespace rs {
 
 Law make_law(const rs_constitutive *c)
 {
@@ -324,6 +322,10 @@ int validate_law(const rs_constitutive *c)
         return fail(RS_EINVAL, "newton_iters must be in 1..64");
     return RS_OK;
 }
+
+}  // namespace rs
+
+namespace {
 
 int harvest_profile(rs_grid *G)
 {

@@ -1,0 +1,78 @@
+// Per-node FP32 operations of the correction equation
+// N(psi_b + delta) - N(psi_b) = r (see soil_mp.h), shared by the single-grid
+// mixed-precision kernels and the batched serving kernels.
+#pragma once
+
+#include "rs_internal.h"
+#include "soil_device.h"
+#include "grid_device.h"
+#include "soil_mp.h"
+
+namespace rs {
+
+template <int DIM>
+__device__ __forceinline__ int vert_index(int i, int j, int k)
+{
+    return (DIM == 1) ? i : (DIM == 2 ? j : k);
+}
+
+// New delta at unknown (i, j, k): f = rhs + sum_j m_ij delta_j + kappa delta_i,
+// c = xi + kappa + m_ii, then the scalar correction solve.
+template <int MODEL, bool SINK, int DIM>
+__device__ __forceinline__ void ngs_cell32(const Geo &g, const Law32 &L, float a,
+                                           const double *beta, float lambdaU, const float *K,
+                                           const float *rhs, const float *pb, float *dl, int i,
+                                           int j, int k, int colour)
+{
+    const long long idx = i + (long long)j * g.stride[1] + (long long)k * g.stride[2];
+    const float Ki = K[idx];
+    float f = rhs[idx];
+    float mii = 0.0f, usum = 0.0f;
+    const bool remark = (L.kappa_rule == kKappaRemark) && colour == 0;
+    for_nb<DIM>(g, i, j, k, idx, [&](long long jn, double cf, int l, int side) {
+        const float m = (float)cf * (Ki + K[jn]);
+        mii += m;
+        f += m * dl[jn];
+        if (remark) {
+            int d[3] = {i, j, k};
+            d[l] += side;
+            if (!dirichlet_at(g, d[0], d[1], d[2], nullptr)) usum += m;
+        }
+    });
+    float kap;
+    if (L.kappa_rule == kKappaConst) kap = L.kappa;
+    else if (L.kappa_rule == kKappaRel) kap = L.kappa * mii;
+    else kap = (colour == 0) ? lambdaU - usum : lambdaU;
+    const float d0 = dl[idx];
+    f += kap * d0;
+    const float c = L.xi + kap + mii;
+    const float bz = SINK ? (float)beta[vert_index<DIM>(i, j, k)] : 0.0f;
+    const Base b = base_of<MODEL>(L, pb[idx]);
+    dl[idx] = local_solve32<MODEL, SINK>(L, a, bz, c, f, b, d0);
+}
+
+// N_delta(delta)_i = a dtheta + beta da + xi delta_i + sum_j m_ij (delta_i - delta_j)
+template <int MODEL, bool SINK, int DIM>
+__device__ __forceinline__ float apply_Nd(const Geo &g, const Law32 &L, float a,
+                                          const double *beta, const float *K, const float *pb,
+                                          const float *dl, int i, int j, int k, long long idx)
+{
+    const float x = dl[idx];
+    const float Ki = K[idx];
+    const Base b = base_of<MODEL>(L, pb[idx]);
+    float dth, slope;
+    dtheta32<MODEL>(L, b, x, dth, slope);
+    float s = a * dth;
+    if (SINK) {
+        float da, ds;
+        dfeddes32(L, b.psi, x, da, ds);
+        s += (float)beta[vert_index<DIM>(i, j, k)] * da;
+    }
+    float md = 0.0f;
+    for_nb<DIM>(g, i, j, k, idx, [&](long long jn, double cf, int, int) {
+        md += (float)cf * (Ki + K[jn]) * (x - dl[jn]);
+    });
+    return s + (L.xi * x + md);
+}
+
+}  // namespace rs

@@ -80,6 +80,21 @@ __device__ __forceinline__ void for_nb(const Geo &g, int i, int j, int k, long l
     }
 }
 
+// Visit the existing neighbours of node c, runtime dimension (order: axis 0 low/high, axis 1,
+// axis 2), calling fn(jdx, coef, axis, side) with coef = 1/(2 w h^2).
+template <typename Fn>
+__device__ __forceinline__ void for_each_nb(const Geo &g, const int c[3], long long idx, Fn &&fn)
+{
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        if (l >= g.dim) break;
+        double iw = (c[l] == 0 || c[l] == g.n[l] - 1) ? 2.0 : 1.0;
+        double cf = 0.5 * iw * g.ih2[l];
+        if (c[l] > 0) fn(idx - g.stride[l], cf, l, -1);
+        if (c[l] < g.n[l] - 1) fn(idx + g.stride[l], cf, l, +1);
+    }
+}
+
 struct NodeMap {
     unsigned n0, n1;
     double inv0, inv1;

@@ -16,25 +16,11 @@
 #include "soil_device.h"
 #include "grid_device.h"
 #include "transfer.h"
+#include "cell64.h"
 
 namespace rs {
 
 namespace {
-
-// Visit the existing neighbours of node c (order: axis 0 low/high, axis 1,
-// axis 2), calling fn(jdx, coef, axis, side) with coef = 1/(2 w h^2).
-template <typename Fn>
-__device__ __forceinline__ void for_each_nb(const Geo &g, const int c[3], long long idx, Fn &&fn)
-{
-#pragma unroll
-    for (int l = 0; l < 3; ++l) {
-        if (l >= g.dim) break;
-        double iw = (c[l] == 0 || c[l] == g.n[l] - 1) ? 2.0 : 1.0;
-        double cf = 0.5 * iw * g.ih2[l];
-        if (c[l] > 0) fn(idx - g.stride[l], cf, l, -1);
-        if (c[l] < g.n[l] - 1) fn(idx + g.stride[l], cf, l, +1);
-    }
-}
 
 __device__ __forceinline__ double sink_beta(const Law &L, const double *beta, const int c[3], int vert)
 {
@@ -80,18 +66,9 @@ __global__ __launch_bounds__(256) void k_setup_kstar(Geo g, Law L, Step st, cons
     int k = blockIdx.z;
     if (i >= g.n[0] || j >= g.n[1]) return;
     long long idx = i + (long long)j * g.stride[1] + (long long)k * g.stride[2];
-    double bv;
-    double ps;
-    if (dirichlet_at(g, i, j, k, &bv)) {
-        ps = bv;
-        psi[idx] = bv;
-    } else {
-        double pn = psi_n[idx];
-        ps = (st.order == 2 && st.lag_extrap) ? 2.0 * pn - psi_nm1[idx] : pn;
-        psi[idx] = pn;
-    }
-    double ks = Ks ? Ks[idx] : L.Ks;
-    K[idx] = ks * krel(L, ps);
+    double p0;
+    K[idx] = kstar_at(g, L, st, psi_n, psi_nm1, Ks ? Ks[idx] : L.Ks, i, j, k, idx, &p0);
+    psi[idx] = p0;
 }
 
 __global__ __launch_bounds__(256) void k_setup_g(Geo g, Law L, Step st, const double *psi_n,
@@ -103,34 +80,7 @@ __global__ __launch_bounds__(256) void k_setup_g(Geo g, Law L, Step st, const do
     int k = blockIdx.z;
     if (i >= g.n[0] || j >= g.n[1]) return;
     long long idx = i + (long long)j * g.stride[1] + (long long)k * g.stride[2];
-    if (dirichlet_at(g, i, j, k, nullptr)) {
-        gv[idx] = 0.0;
-        return;
-    }
-    int c[3] = {i, j, k};
-    double pn = psi_n[idx];
-    double H, ps;
-    if (st.order == 1) {
-        H = theta_only(L, pn) / st.dt;
-        ps = pn;
-    } else {
-        double pm = psi_nm1[idx];
-        H = (4.0 * theta_only(L, pn) - theta_only(L, pm)) / (2.0 * st.dt);
-        ps = st.lag_extrap ? 2.0 * pn - pm : pn;
-    }
-    // gravity (M z)_i: only faces along the vertical axis, z_i - z_j = -side h
-    double Ki = K[idx];
-    double mz = 0.0;
-    const int v = g.vert;
-    for_each_nb(g, c, idx, [&](long long jn, double cf, int l, int side) {
-        if (l == v) mz += cf * (Ki + K[jn]) * (-side * g.h[v]);
-    });
-    double gi = H + L.xi * ps - mz;
-    if (c[v] == 0 && g.bc[2 * v] == kBcFreedrain) {
-        double iw = 2.0;   // bottom node: half control volume
-        gi -= Ki * iw / g.h[v];
-    }
-    gv[idx] = gi;
+    gv[idx] = g_at(g, L, st, psi_n, psi_nm1, K, i, j, k, idx);
 }
 
 __global__ __launch_bounds__(256) void k_inject(Geo gc, Geo gf, const double *Kf, double *Kc)
@@ -371,27 +321,6 @@ __global__ __launch_bounds__(256) void k_sweep_small(Geo g, Law L, Step st, cons
 // ---------------------------------------------------------------------------
 // Defect d = g - N(psi) and its max-norm (step 2 of the FAS algorithm)
 // ---------------------------------------------------------------------------
-
-template <int MODEL, bool SINK, int DIM>
-__device__ __forceinline__ double apply_N_t(const Geo &g, const Law &L, double a,
-                                            const double *beta, const double *K,
-                                            const double *psi, int i, int j, int k, long long idx)
-{
-    const double x = psi[idx];
-    const double Ki = K[idx];
-    double s = a * theta_only_t<MODEL>(L, x);
-    if (SINK) {
-        double fa, dfa;
-        feddes(L, x, fa, dfa);
-        const int vk = (DIM == 1) ? i : (DIM == 2 ? j : k);
-        s += beta[vk] * fa;
-    }
-    double mpsi = 0.0;
-    for_nb<DIM>(g, i, j, k, idx, [&](long long jn, double cf, int, int) {
-        mpsi += cf * (Ki + K[jn]) * (x - psi[jn]);
-    });
-    return s + (L.xi * x + mpsi);
-}
 
 // Grid-stride over the nodes; one block maximum and one atomic per block.
 template <int MODEL, bool SINK, int DIM>

@@ -12,13 +12,10 @@ namespace rs {
 // injection of psi, zero defect).  FW: tensor (1/4, 1/2, 1/4) around fine node
 // 2I, missing neighbours mirrored at the domain boundary.
 template <typename T>
-__global__ __launch_bounds__(256) void k_restrict(Geo gc, Geo gf, const T *psi_f, const T *d_f,
-                                                  T *psibar_c, T *g_c)
+__device__ __forceinline__ void restrict_at(const Geo &gc, const Geo &gf, const T *psi_f,
+                                            const T *d_f, T *psibar_c, T *g_c, int I0, int I1,
+                                            int I2)
 {
-    int I0 = blockIdx.x * kBX + threadIdx.x;
-    int I1 = blockIdx.y * kBY + threadIdx.y;
-    int I2 = blockIdx.z;
-    if (I0 >= gc.n[0] || I1 >= gc.n[1]) return;
     long long I = I0 + (long long)I1 * gc.stride[1] + (long long)I2 * gc.stride[2];
     int F[3] = {2 * I0, 2 * I1, 2 * I2};
     if (dirichlet_at(gc, I0, I1, I2, nullptr)) {
@@ -55,16 +52,23 @@ __global__ __launch_bounds__(256) void k_restrict(Geo gc, Geo gf, const T *psi_f
     g_c[I] = sd;
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_restrict(Geo gc, Geo gf, const T *psi_f, const T *d_f,
+                                                  T *psibar_c, T *g_c)
+{
+    int I0 = blockIdx.x * kBX + threadIdx.x;
+    int I1 = blockIdx.y * kBY + threadIdx.y;
+    int I2 = blockIdx.z;
+    if (I0 >= gc.n[0] || I1 >= gc.n[1]) return;
+    restrict_at<T>(gc, gf, psi_f, d_f, psibar_c, g_c, I0, I1, I2);
+}
+
 // psi_h += I_h^H (psi_H - psibar_H) at fine unknowns (tensor linear
 // interpolation: even index -> coarse node, odd -> mean of the two).
 template <typename T>
-__global__ __launch_bounds__(256) void k_prolong(Geo gf, Geo gc, const T *psi_c, const T *psibar_c,
-                                                 T *psi_f)
+__device__ __forceinline__ void prolong_at(const Geo &gf, const Geo &gc, const T *psi_c,
+                                           const T *psibar_c, T *psi_f, int i, int j, int k)
 {
-    int i = blockIdx.x * kBX + threadIdx.x;
-    int j = blockIdx.y * kBY + threadIdx.y;
-    int k = blockIdx.z;
-    if (i >= gf.n[0] || j >= gf.n[1]) return;
     if (dirichlet_at(gf, i, j, k, nullptr)) return;
     int c[3] = {i, j, k};
     int a0[3], a1[3], cnt[3];
@@ -92,6 +96,17 @@ __global__ __launch_bounds__(256) void k_prolong(Geo gf, Geo gc, const T *psi_c,
             }
     long long idx = i + (long long)j * gf.stride[1] + (long long)k * gf.stride[2];
     psi_f[idx] += e;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_prolong(Geo gf, Geo gc, const T *psi_c, const T *psibar_c,
+                                                 T *psi_f)
+{
+    int i = blockIdx.x * kBX + threadIdx.x;
+    int j = blockIdx.y * kBY + threadIdx.y;
+    int k = blockIdx.z;
+    if (i >= gf.n[0] || j >= gf.n[1]) return;
+    prolong_at<T>(gf, gc, psi_c, psibar_c, psi_f, i, j, k);
 }
 
 // Injection to a coarse level: v_H[I] = v_h[2I].

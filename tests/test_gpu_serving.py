@@ -1,0 +1,147 @@
+"""Continuous-batching engine on the GPU: every served result matches the FP64
+oracle's converged steps (1e-10 normwise relative), a request's result is
+bit-identical alone and in a mix that changes while it runs, graph replay
+equals plain launches, and admission follows the arena footprint."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2606_04292_amd as rsl
+from paper_2606_04292_amd import serve
+from paper_2606_04292_amd import workloads as W
+from tests.test_gpu_parity import FLOOR_CYCLES, rel, say
+
+pytestmark = pytest.mark.gpu
+
+TOL_CONV = 1e-10
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def small_requests(k, max1d=513, max2d=129, seed_path=(7,)):
+    """k requests of the serving stream's recipe, sizes capped so that the
+    oracle finishes in seconds."""
+    out = []
+    for w in W.serving_requests(400, seed_path=seed_path):
+        lim = max1d if w.grid.dim == 1 else max2d
+        if max(w.grid.n) <= lim:
+            out.append(w)
+        if len(out) == k:
+            break
+    return out
+
+
+def oracle_solution(w):
+    S = oracle.run_steps(w, steps=w.steps, max_cycles=FLOOR_CYCLES)
+    return S.get(oracle.FIELD_PSI_N)
+
+
+def arena_for(reqs, opts):
+    return serve.control_bytes(opts) + sum(serve.request_bytes(opts, w.grid) for w in reqs)
+
+
+def serve_all(reqs, opts, schedule=None, arena=None, max_ticks=5000):
+    """Submit request q at tick schedule[q] (all at tick 0 by default; a
+    request that does not fit waits, FCFS); tick until all are fetched.
+    Returns {index: (psi numpy, stats)}."""
+    schedule = schedule or [0] * len(reqs)
+    E = serve.Engine(arena if arena is not None else arena_for(reqs, opts), opts)
+    out, ticket_of, waiting = {}, {}, list(range(len(reqs)))
+    tick = 0
+    while len(out) < len(reqs):
+        assert tick < max_ticks, "engine did not finish"
+        while waiting and schedule[waiting[0]] <= tick:
+            q = waiting[0]
+            t = E.submit(reqs[q])
+            if t is None:
+                break
+            ticket_of[t] = q
+            waiting.pop(0)
+        done, _ = E.tick()
+        for t in done:
+            psi, st = E.fetch(t)
+            E.synchronize()
+            out[ticket_of[t]] = (psi.cpu().numpy(), st)
+        tick += 1
+    E.close()
+    return out
+
+
+def test_served_results_match_the_fp64_oracle(torch_cuda):
+    reqs = small_requests(6)
+    for tail in (8192, 300):   # default split, and one with several wide levels
+        opts = serve.engine_opts(tail_nodes=tail)
+        res = serve_all(reqs, opts)
+        for q, w in enumerate(reqs):
+            psi, st = res[q]
+            assert st.state == serve.RS_REQ_FINISHED and st.status == rsl.RS_OK
+            assert st.steps == w.steps
+            e = rel(psi, oracle_solution(w))
+            say("tail", tail, w.grid.dim, "D n", w.grid.n[0], "corrections", st.corrections,
+                "max/step", st.max_step_corrections, "rel", e)
+            assert e <= TOL_CONV
+
+
+def test_each_result_is_the_same_alone_and_in_the_mix(torch_cuda):
+    reqs = small_requests(8, max1d=1025, max2d=129, seed_path=(8,))
+    opts = serve.engine_opts(tail_nodes=300, rounds_per_tick=2)
+    alone = {}
+    for q, w in enumerate(reqs):
+        alone[q] = serve_all([w], opts)[0][0]
+    # staggered arrivals: requests join while others are part-way through
+    mix = serve_all(reqs, opts, schedule=[0, 0, 1, 3, 3, 5, 8, 13])
+    for q in range(len(reqs)):
+        say("request", q, reqs[q].grid.dim, "D n", reqs[q].grid.n[0],
+            "max |alone - mix|", float(np.abs(alone[q] - mix[q][0]).max()))
+        assert np.array_equal(alone[q], mix[q][0])
+
+
+def test_graph_replay_equals_plain_launches(torch_cuda):
+    reqs = small_requests(4, seed_path=(9,))
+    a = serve_all(reqs, serve.engine_opts(tail_nodes=300, use_graph=1))
+    b = serve_all(reqs, serve.engine_opts(tail_nodes=300, use_graph=0))
+    for q in range(len(reqs)):
+        assert np.array_equal(a[q][0], b[q][0])
+        assert a[q][1].corrections == b[q][1].corrections
+
+
+def test_admission_follows_the_arena_footprint(torch_cuda):
+    reqs = small_requests(3, max1d=257, max2d=65, seed_path=(10,))
+    opts = serve.engine_opts(max_slots=8)
+    big = max(serve.request_bytes(opts, w.grid) for w in reqs)
+    arena = serve.control_bytes(opts) + 2 * big
+    E = serve.Engine(arena, opts)
+    t0, t1 = E.submit(reqs[0]), E.submit(reqs[1])
+    assert t0 is not None and t1 is not None
+    fb, fs = E.capacity()
+    assert fs == 6
+    if fb < serve.request_bytes(opts, reqs[2].grid):
+        assert E.submit(reqs[2]) is None          # waits for memory
+    E.close()
+    res = serve_all(reqs, opts, arena=arena)      # FCFS with the same arena
+    for q, w in enumerate(reqs):
+        assert res[q][1].state == serve.RS_REQ_FINISHED
+        assert rel(res[q][0], oracle_solution(w)) <= TOL_CONV
+
+
+def test_unsupported_requests_are_rejected(torch_cuda):
+    opts = serve.engine_opts(max_slots=4)
+    E = serve.Engine(serve.control_bytes(opts) + (64 << 20), opts)
+    w = small_requests(1)[0]
+    import dataclasses
+    for law in (dataclasses.replace(w.law, kappa_rule=W.KAPPA_REMARK),
+                dataclasses.replace(w.law, sink=W.SINK_FEDDES_EXP, Tp=1e-8, root_len=0.2,
+                                    h1=-0.1, h2=-0.25, h3=-4.0, h4=-80.0)):
+        with pytest.raises(rsl.RsError) as ei:
+            E.submit(dataclasses.replace(w, law=law))
+        assert ei.value.code == rsl.RS_EINVAL
+    with pytest.raises(rsl.RsError) as ei:
+        E.submit(dataclasses.replace(w, steps=0))
+    assert ei.value.code == rsl.RS_EINVAL
+    assert E.capacity()[1] == 4
+    E.close()
