@@ -116,6 +116,92 @@ def gpu_run(args):
     return res
 
 
+def serving_leg(args):
+    """Continuous batching of the serving stream against one-at-a-time FP64.
+
+    1. closed loop: all requests present at t = 0; capacity C = requests / makespan;
+    2. open loop: Poisson arrivals at 0.7 C; per-request latency = completion -
+       arrival, step-solves/s = steps served / (last completion - first arrival);
+    3. baseline: the first --serve-baseline requests of the same trace solved one
+       at a time on an FP64 grid (rs_bdf_step to the rounding floor), each
+       timed alone; its FCFS latencies follow from those service times and the
+       same arrival times.  The engine's final states of these requests are
+       compared with the FP64 results.
+    """
+    import numpy as np
+    import torch
+    import paper_2606_04292_amd as rsl
+    from paper_2606_04292_amd import serve
+    from paper_2606_04292_amd import workloads as W
+
+    reqs = W.serving_requests(args.serve_requests)
+    steps = sum(w.steps for w in reqs)
+    opts = serve.engine_opts()
+    arena = int(args.serve_arena_gib * (1 << 30))
+    E = serve.Engine(arena, opts, device="cuda:0")
+    # warm-up: a few requests through the engine (graph, kernels, allocator)
+    serve.run_stream(E, reqs[:16])
+    _, comp, st, _ = serve.run_stream(E, reqs)
+    makespan = float(np.nanmax(comp))
+    cap = len(reqs) / makespan
+    bad = [q for q, s in enumerate(st) if s[0] != rsl.RS_OK]
+    log("serving closed loop: %d requests in %.3f s (%.1f req/s), %d failed" % (
+        len(reqs), makespan, cap, len(bad)))
+    rate = 0.7 * cap
+    arr = W.poisson_arrivals(len(reqs), rate)
+    M = min(args.serve_baseline, len(reqs))
+    arr2, comp2, st2, kept = serve.run_stream(E, reqs, arrivals=arr, keep=range(M))
+    lat = comp2 - arr2
+    span = float(np.nanmax(comp2) - arr2[0])
+    log("serving open loop at %.1f req/s: p50 %.1f ms p99 %.1f ms" % (
+        rate, 1e3 * np.percentile(lat, 50), 1e3 * np.percentile(lat, 99)))
+    E.close()
+    del E
+    torch.cuda.empty_cache()
+    # one-at-a-time FP64 on the same requests
+    fp_opts = rsl.solve_opts(max_cycles=100, tol_abs=0.0, stagnation=1)
+    service, errs = [], []
+    for q in range(M):
+        w = reqs[q]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        G = rsl.Grid(w, device="cuda:0")
+        for _ in range(w.steps):
+            code, s = G.bdf_step(opts=fp_opts)
+            if code != rsl.RS_OK:
+                raise SystemExit("FP64 baseline step failed: " + rsl.lib().rs_last_error().decode())
+        psi = G.get_state()[0]
+        torch.cuda.synchronize()
+        service.append(time.perf_counter() - t0)
+        G.close()
+        errs.append(float((kept[q] - psi).abs().max() / psi.abs().max()))
+    service = np.array(service)
+    blat = serve.fcfs_latencies(arr[:M], service)
+    pct = lambda x, p: round(1e3 * float(np.percentile(x, p)), 2)
+    return {
+        "requests": len(reqs), "steps_per_request": reqs[0].steps,
+        "step_solves_per_s": steps / span,
+        "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99)},
+        "arrival_rate_req_per_s": round(rate, 2),
+        "closed_loop_capacity_req_per_s": round(cap, 2),
+        "failed": len(bad) + sum(1 for s in st2 if s[0] != rsl.RS_OK),
+        "corrections_per_step": round(sum(s[2] for s in st2) / steps, 2),
+        "engine": {"precision": "FP32 correction cycles, FP64 defect/history",
+                   "max_slots": opts.max_slots, "tail_nodes": opts.tail_nodes,
+                   "rounds_per_tick": opts.rounds_per_tick, "graph": bool(opts.use_graph),
+                   "arena_gib": args.serve_arena_gib},
+        "baseline_one_at_a_time_fp64": {
+            "requests": M,
+            "step_solves_per_s": M * reqs[0].steps / float(service.sum()),
+            "latency_ms_same_trace": {"p50": pct(blat, 50), "p99": pct(blat, 99)},
+            "engine_latency_ms_same_requests": {"p50": pct(lat[:M], 50), "p99": pct(lat[:M], 99)},
+            "mean_service_ms": round(1e3 * float(service.mean()), 2),
+            "kind": "each request timed alone (grid set-up + steps + result); FCFS queue "
+                    "from those service times on the same arrival times"},
+        "rel_err_vs_fp64_max": max(errs) if errs else None,
+    }
+
+
 def cpu_baseline(args, n):
     import numpy as np
     import oracle
@@ -152,6 +238,12 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-requests", type=int, default=4096)
+    ap.add_argument("--serve-baseline", type=int, default=64,
+                    help="requests of the trace solved one at a time in FP64")
+    ap.add_argument("--serve-arena-gib", type=float, default=16.0)
+    ap.add_argument("--serve-only", action="store_true", help="run only the serving leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 512 MiB device copy first (counter calibration)")
     args = ap.parse_args()
@@ -160,6 +252,9 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.serve_only:
+        print(json.dumps({"serving": serving_leg(args)}), flush=True)
+        return
     r = gpu_run(args)
     w = r["w"]
     ms = r["elapsed"] * 1e3 / args.steps
@@ -180,6 +275,8 @@ def main():
     }
     if r["mixed"] is not None:
         out["mixed_precision"] = r["mixed"]
+    if not args.no_serving:
+        out["serving"] = serving_leg(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, args.n)
     print(json.dumps(out), flush=True)

@@ -167,3 +167,63 @@ class Engine:
 
     def synchronize(self):
         self.stream.synchronize()
+
+
+def run_stream(E: Engine, reqs, arrivals=None, keep=()):
+    """Serve ``reqs`` in arrival order (FCFS admission) against the wall clock.
+
+    ``arrivals``: seconds after the start at which request q arrives (all at 0
+    when None).  A request is submitted once it has arrived and the requests
+    before it are admitted; it waits while the engine has no room.  Returns
+    (arrival, completion, stats, kept): completion times in seconds after the
+    start (taken when the tick that reports the request returns), per-request
+    (status, steps, corrections, max corrections in a step), and the final
+    states of the requests listed in ``keep`` as device tensors."""
+    import time
+    n = len(reqs)
+    arr = np.zeros(n) if arrivals is None else np.asarray(arrivals, dtype=np.float64)
+    comp = np.full(n, np.nan)
+    stats = [None] * n
+    kept = {}
+    keep = set(keep)
+    ticket_of = {}
+    nxt = 0
+    finished = 0
+    t0 = time.perf_counter()
+    while finished < n:
+        now = time.perf_counter() - t0
+        while nxt < n and arr[nxt] <= now:
+            t = E.submit(reqs[nxt])
+            if t is None:
+                if not ticket_of:
+                    raise RuntimeError("request %d does not fit an empty engine" % nxt)
+                break
+            ticket_of[t] = nxt
+            nxt += 1
+        if not ticket_of:
+            time.sleep(max(0.0, arr[nxt] - (time.perf_counter() - t0)))
+            continue
+        done, _ = E.tick()
+        tdone = time.perf_counter() - t0
+        for t in done:
+            q = ticket_of.pop(t)
+            psi, st = E.fetch(t, want_psi=q in keep)
+            if psi is not None:
+                kept[q] = psi
+            comp[q] = tdone
+            stats[q] = (st.status, st.steps, st.corrections, st.max_step_corrections)
+            finished += 1
+    E.synchronize()
+    return arr, comp, stats, kept
+
+
+def fcfs_latencies(arrivals, service):
+    """Latencies of a single first-come-first-served server with the given
+    arrival and service times (Lindley's recursion)."""
+    lat = np.empty(len(arrivals))
+    free = -np.inf
+    for q, (a, s) in enumerate(zip(arrivals, service)):
+        start = max(a, free)
+        free = start + s
+        lat[q] = free - a
+    return lat
