@@ -25,25 +25,41 @@ __device__ __forceinline__ void ngs_cell32(const Geo &g, const Law32 &L, float a
                                            int j, int k, int colour)
 {
     const long long idx = i + (long long)j * g.stride[1] + (long long)k * g.stride[2];
+    const Stencil<DIM> st = stencil<DIM>(g, i, j, k, idx);
     const float Ki = K[idx];
-    float f = rhs[idx];
-    float mii = 0.0f, usum = 0.0f;
-    const bool remark = (L.kappa_rule == kKappaRemark) && colour == 0;
-    for_nb<DIM>(g, i, j, k, idx, [&](long long jn, double cf, int l, int side) {
-        const float m = (float)cf * (Ki + K[jn]);
-        mii += m;
-        f += m * dl[jn];
-        if (remark) {
-            int d[3] = {i, j, k};
-            d[l] += side;
-            if (!dirichlet_at(g, d[0], d[1], d[2], nullptr)) usum += m;
-        }
-    });
-    float kap;
-    if (L.kappa_rule == kKappaConst) kap = L.kappa;
-    else if (L.kappa_rule == kKappaRel) kap = L.kappa * mii;
-    else kap = (colour == 0) ? lambdaU - usum : lambdaU;
     const float d0 = dl[idx];
+    float f = rhs[idx];
+    float Kn[2 * DIM], dn[2 * DIM];
+#pragma unroll
+    for (int q = 0; q < 2 * DIM; ++q) {
+        Kn[q] = K[st.jn[q]];
+        dn[q] = dl[st.jn[q]];
+    }
+    float mii = 0.0f;
+#pragma unroll
+    for (int q = 0; q < 2 * DIM; ++q) {
+        const float m = (float)st.cf[q] * (Ki + Kn[q]);
+        mii += m;
+        f += m * dn[q];
+    }
+    float kap;
+    if (L.kappa_rule == kKappaConst) {
+        kap = L.kappa;
+    } else if (L.kappa_rule == kKappaRel) {
+        kap = L.kappa * mii;
+    } else if (colour == 0) {
+        float usum = 0.0f;
+#pragma unroll
+        for (int q = 0; q < 2 * DIM; ++q) {
+            int d[3] = {i, j, k};
+            d[q >> 1] += (q & 1) ? 1 : -1;
+            if (st.cf[q] != 0.0 && !dirichlet_at(g, d[0], d[1], d[2], nullptr))
+                usum += (float)st.cf[q] * (Ki + Kn[q]);
+        }
+        kap = lambdaU - usum;
+    } else {
+        kap = lambdaU;
+    }
     f += kap * d0;
     const float c = L.xi + kap + mii;
     const float bz = SINK ? (float)beta[vert_index<DIM>(i, j, k)] : 0.0f;
@@ -68,10 +84,16 @@ __device__ __forceinline__ float apply_Nd(const Geo &g, const Law32 &L, float a,
         dfeddes32(L, b.psi, x, da, ds);
         s += (float)beta[vert_index<DIM>(i, j, k)] * da;
     }
+    const Stencil<DIM> st = stencil<DIM>(g, i, j, k, idx);
+    float Kn[2 * DIM], dn[2 * DIM];
+#pragma unroll
+    for (int q = 0; q < 2 * DIM; ++q) {
+        Kn[q] = K[st.jn[q]];
+        dn[q] = dl[st.jn[q]];
+    }
     float md = 0.0f;
-    for_nb<DIM>(g, i, j, k, idx, [&](long long jn, double cf, int, int) {
-        md += (float)cf * (Ki + K[jn]) * (x - dl[jn]);
-    });
+#pragma unroll
+    for (int q = 0; q < 2 * DIM; ++q) md += (float)st.cf[q] * (Ki + Kn[q]) * (x - dn[q]);
     return s + (L.xi * x + md);
 }
 

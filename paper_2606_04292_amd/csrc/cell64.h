@@ -78,10 +78,16 @@ __device__ __forceinline__ double apply_N_t(const Geo &g, const Law &L, double a
         const int vk = (DIM == 1) ? i : (DIM == 2 ? j : k);
         s += beta[vk] * fa;
     }
+    const Stencil<DIM> st = stencil<DIM>(g, i, j, k, idx);
+    double Kn[2 * DIM], pn[2 * DIM];
+#pragma unroll
+    for (int q = 0; q < 2 * DIM; ++q) {
+        Kn[q] = K[st.jn[q]];
+        pn[q] = psi[st.jn[q]];
+    }
     double mpsi = 0.0;
-    for_nb<DIM>(g, i, j, k, idx, [&](long long jn, double cf, int, int) {
-        mpsi += cf * (Ki + K[jn]) * (x - psi[jn]);
-    });
+#pragma unroll
+    for (int q = 0; q < 2 * DIM; ++q) mpsi += st.cf[q] * (Ki + Kn[q]) * (x - pn[q]);
     return s + (L.xi * x + mpsi);
 }
 

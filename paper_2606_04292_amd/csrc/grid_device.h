@@ -95,6 +95,35 @@ __device__ __forceinline__ void for_each_nb(const Geo &g, const int c[3], long l
     }
 }
 
+// The 2 DIM neighbours of node (i, j, k) in the order of for_nb, as indices
+// and coefficients 1/(2 w h^2).  A neighbour outside the domain gets the node
+// itself as index and a zero coefficient, so every load of a stencil can be
+// issued before any arithmetic (no branch per neighbour) and the zero terms
+// leave the sums unchanged.
+template <int DIM>
+struct Stencil {
+    long long jn[2 * DIM];
+    double cf[2 * DIM];
+};
+
+template <int DIM>
+__device__ __forceinline__ Stencil<DIM> stencil(const Geo &g, int i, int j, int k, long long idx)
+{
+    Stencil<DIM> s;
+#pragma unroll
+    for (int l = 0; l < DIM; ++l) {
+        const int cl = (l == 0) ? i : (l == 1 ? j : k);
+        const double cf = ((cl == 0 || cl == g.n[l] - 1) ? 1.0 : 0.5) * g.ih2[l];
+        const long long st = g.stride[l];
+        const bool lo = cl > 0, hi = cl < g.n[l] - 1;
+        s.jn[2 * l] = lo ? idx - st : idx;
+        s.cf[2 * l] = lo ? cf : 0.0;
+        s.jn[2 * l + 1] = hi ? idx + st : idx;
+        s.cf[2 * l + 1] = hi ? cf : 0.0;
+    }
+    return s;
+}
+
 struct NodeMap {
     unsigned n0, n1;
     double inv0, inv1;

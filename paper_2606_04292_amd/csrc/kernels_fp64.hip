@@ -162,9 +162,47 @@ __device__ __forceinline__ void ngs_cell(const Geo &g, const Law &L, double a, c
                                          double *psi, int i, int j, int k, int colour)
 {
     const long long idx = i + (long long)j * g.stride[1] + (long long)k * g.stride[2];
-    psi[idx] = ngs_value<MODEL, SINK, DIM>(g, L, a, beta, lambdaU, K, gv, i, j, k, idx, colour,
-                                           psi[idx],
-                                           [&](long long jn, int, int) { return psi[jn]; });
+    const Stencil<DIM> st = stencil<DIM>(g, i, j, k, idx);
+    const double Ki = K[idx];
+    const double x0 = psi[idx];
+    double f = gv[idx];
+    double Kn[2 * DIM], pn[2 * DIM];
+#pragma unroll
+    for (int q = 0; q < 2 * DIM; ++q) {
+        Kn[q] = K[st.jn[q]];
+        pn[q] = psi[st.jn[q]];
+    }
+    double mii = 0.0;
+#pragma unroll
+    for (int q = 0; q < 2 * DIM; ++q) {
+        const double m = st.cf[q] * (Ki + Kn[q]);
+        mii += m;
+        f += m * pn[q];
+    }
+    double kap;
+    if (L.kappa_rule == kKappaConst) {
+        kap = L.kappa;
+    } else if (L.kappa_rule == kKappaRel) {
+        kap = L.kappa * mii;
+    } else if (colour == 0) {
+        double usum = 0.0;
+#pragma unroll
+        for (int q = 0; q < 2 * DIM; ++q) {
+            int d[3] = {i, j, k};
+            d[q >> 1] += (q & 1) ? 1 : -1;
+            if (st.cf[q] != 0.0 && !dirichlet_at(g, d[0], d[1], d[2], nullptr))
+                usum += st.cf[q] * (Ki + Kn[q]);
+        }
+        kap = lambdaU - usum;
+    } else {
+        kap = lambdaU;
+    }
+    f += kap * x0;
+    const double cc = L.xi + kap + mii;
+    const int vk = (DIM == 1) ? i : (DIM == 2 ? j : k);
+    const double b = SINK ? beta[vk] : 0.0;
+    psi[idx] = (L.newton == 3) ? local_solve_t<MODEL, SINK, 3>(L, a, b, cc, f, x0)
+                               : local_solve_t<MODEL, SINK, 0>(L, a, b, cc, f, x0);
 }
 
 // ---------------------------------------------------------------------------
