@@ -29,6 +29,16 @@ __device__ __forceinline__ double rcp_nr(double x)
     return fma(r, e, r);
 }
 
+// 1/x from the hardware estimate (about 2^-24) refined by one Newton-Raphson
+// step: within ~11 ulp, enough where the quotient only feeds a self-correcting
+// iteration or a term already carrying that much rounding.
+__device__ __forceinline__ double rcp_1nr(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
 // Natural logarithm of a positive normal double.  x = m 2^e with m in
 // [sqrt(1/2), sqrt(2)), ln x = e ln2 + 2 atanh(s), s = (m-1)/(m+1), |s| <= 0.1716,
 // with the atanh series 2 s (1 + s^2/3 + ... + s^18/19) (truncation < 3e-17)
@@ -37,18 +47,27 @@ constexpr double kLn2Hi = 6.93147180369123816490e-01;
 constexpr double kLn2Lo = 1.90821492927058770002e-10;
 constexpr double kInvLn2 = 1.44269504088896338700e+00;
 
+// p * r + c with the coefficient c in a scalar register pair (one VOP3 FMA;
+// no vector moves to materialise the constant).
+__device__ __forceinline__ double fma_sc(double p, double r, double c)
+{
+    double out;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(out) : "v"(p), "v"(r), "s"(c));
+    return out;
+}
+
 __device__ __forceinline__ double atanh2_series(double s)
 {
     const double s2 = s * s;
     double p = 1.0 / 19.0;
-    p = fma(p, s2, 1.0 / 17.0);
-    p = fma(p, s2, 1.0 / 15.0);
-    p = fma(p, s2, 1.0 / 13.0);
-    p = fma(p, s2, 1.0 / 11.0);
-    p = fma(p, s2, 1.0 / 9.0);
-    p = fma(p, s2, 1.0 / 7.0);
-    p = fma(p, s2, 1.0 / 5.0);
-    p = fma(p, s2, 1.0 / 3.0);
+    p = fma_sc(p, s2, 1.0 / 17.0);
+    p = fma_sc(p, s2, 1.0 / 15.0);
+    p = fma_sc(p, s2, 1.0 / 13.0);
+    p = fma_sc(p, s2, 1.0 / 11.0);
+    p = fma_sc(p, s2, 1.0 / 9.0);
+    p = fma_sc(p, s2, 1.0 / 7.0);
+    p = fma_sc(p, s2, 1.0 / 5.0);
+    p = fma_sc(p, s2, 1.0 / 3.0);
     return fma(2.0 * s * s2, p, 2.0 * s);   // 2 atanh(s)
 }
 
@@ -60,7 +79,7 @@ __device__ __forceinline__ double rs_log(double x)
         m += m;
         e -= 1;
     }
-    const double s = (m - 1.0) * rcp_nr(m + 1.0);
+    const double s = (m - 1.0) * rcp_1nr(m + 1.0);
     const double de = (double)e;
     return fma(de, kLn2Hi, fma(de, kLn2Lo, atanh2_series(s)));
 }
@@ -69,7 +88,7 @@ __device__ __forceinline__ double rs_log(double x)
 // (no cancellation for small p), else ln of the rounded sum.
 __device__ __forceinline__ double rs_log1p(double p)
 {
-    if (p < 0.41421356237309504880) return atanh2_series(p * rcp_nr(2.0 + p));
+    if (p < 0.41421356237309504880) return atanh2_series(p * rcp_1nr(2.0 + p));
     return rs_log(1.0 + p);
 }
 
@@ -83,16 +102,16 @@ __device__ __forceinline__ double rs_exp(double y)
     double r = fma(-n, kLn2Hi, y);
     r = fma(-n, kLn2Lo, r);
     double p = 1.0 / 6227020800.0;                   // 1/13!
-    p = fma(p, r, 1.0 / 479001600.0);
-    p = fma(p, r, 1.0 / 39916800.0);
-    p = fma(p, r, 1.0 / 3628800.0);
-    p = fma(p, r, 1.0 / 362880.0);
-    p = fma(p, r, 1.0 / 40320.0);
-    p = fma(p, r, 1.0 / 5040.0);
-    p = fma(p, r, 1.0 / 720.0);
-    p = fma(p, r, 1.0 / 120.0);
-    p = fma(p, r, 1.0 / 24.0);
-    p = fma(p, r, 1.0 / 6.0);
+    p = fma_sc(p, r, 1.0 / 479001600.0);
+    p = fma_sc(p, r, 1.0 / 39916800.0);
+    p = fma_sc(p, r, 1.0 / 3628800.0);
+    p = fma_sc(p, r, 1.0 / 362880.0);
+    p = fma_sc(p, r, 1.0 / 40320.0);
+    p = fma_sc(p, r, 1.0 / 5040.0);
+    p = fma_sc(p, r, 1.0 / 720.0);
+    p = fma_sc(p, r, 1.0 / 120.0);
+    p = fma_sc(p, r, 1.0 / 24.0);
+    p = fma_sc(p, r, 1.0 / 6.0);
     p = fma(p, r, 0.5);
     p = fma(p, r, 1.0);
     p = fma(p, r, 1.0);
@@ -123,7 +142,7 @@ __device__ __forceinline__ ThetaEval theta_t(const Law &L, double x)
         double hu = -L.unit * x;
         double Q = rs_exp(L.hk_beta * rs_log(hu));
         double den = L.hk_alpha + Q;
-        double w = rcp_nr(hu * den);
+        double w = rcp_1nr(hu * den);
         double tmr = L.hk_alpha * L.dT * (hu * w);      // theta - theta_r
         r.th = L.tr + tmr;
         r.dth = L.unit * L.hk_beta * tmr * Q * w;
@@ -134,7 +153,7 @@ __device__ __forceinline__ ThetaEval theta_t(const Law &L, double x)
     double P = rs_exp(L.vg_n * rs_log(ax));
     double Se = rs_exp(-L.vg_m * rs_log1p(P));
     r.th = L.tr + L.dT * Se;
-    r.dth = L.dT * L.vg_m * L.vg_n * P * Se * rcp_nr((1.0 + P) * (-x));
+    r.dth = L.dT * L.vg_m * L.vg_n * P * Se * rcp_1nr((1.0 + P) * (-x));
     return r;
 }
 
@@ -234,9 +253,14 @@ __device__ __forceinline__ double local_solve_t(const Law &L, double a, double b
             lo = x;
             hi = x;
         }
-        double xn = x - F * rcp_nr(dF);
+        double xn = x - F * rcp_1nr(dF);
         bool bisect = !(dF > 0.0) || (xn != x && !(xn > lo && xn < hi));
+        const double xo = x;
         x = bisect ? 0.5 * (lo + hi) : xn;
+        // An iterate that did not move stays put in every later iteration (same
+        // F, F', no bisection): once no lane of the wave moved, the remaining
+        // iterations are skipped with identical results.
+        if (!__any(x != xo)) break;
     }
     return x;
 }
