@@ -31,6 +31,36 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "sweep_fp64_block3d_haverkamp_257_traffic.md")
+
+
+def kernel_sources_sha256():
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2606_04292_amd", "csrc", "*"))):
+        if p.endswith((".hip", ".h")):
+            h.update(os.path.basename(p).encode())
+            with open(p, "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def profiled_traffic():
+    """Calibrated HBM bytes (read + write) per finest-level sweep launch from
+    the committed counter summary, or None once the kernel sources changed
+    since the counters were taken."""
+    import re
+    try:
+        with open(TRAFFIC_PROFILE) as f:
+            m = re.search(r"sweep_traffic_bytes=(\d+) kernel_sources_sha256=([0-9a-f]+)", f.read())
+    except OSError:
+        return None
+    if not m or m.group(2) != kernel_sources_sha256():
+        return None
+    return int(m.group(1))
+
+
 def gpu_run(args):
     import torch
     import paper_2606_04292_amd as rsl
@@ -103,10 +133,14 @@ def gpu_run(args):
                  "note": "same steps and tolerance; FP64 path is parity-tested against the oracle"}
         log("mixed: %.2f ms/step, rel diff vs FP64 %.2e" % (el2 * 1e3 / args.steps, err))
         H.close()
+    traffic = profiled_traffic()
     res = dict(
         w=w, elapsed=elapsed, updates=updates, cycles=cycles, mixed=mixed,
         roofline={"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                  "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                  "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                  "traffic_per_algorithmic": (round(traffic / bytes_per_launch, 3)
+                                              if traffic else None),
+                  "traffic_source": os.path.relpath(TRAFFIC_PROFILE, ROOT),
                   "kernel": "k_sweep_colour (finest level, one colour per launch)",
                   "avg_launch_us": round(avg_launch_s * 1e6, 2),
                   "bytes_per_launch": bytes_per_launch, "launches": launches,
