@@ -152,6 +152,15 @@ __device__ __forceinline__ void law_dim(int model, int dim, Fn &&fn)
 #undef RS_E_DIMS
 }
 
+template <typename Fn>
+__device__ __forceinline__ void dim_switch(int dim, Fn &&fn)
+{
+    using std::integral_constant;
+    if (dim == 1) fn(integral_constant<int, 1>{});
+    else if (dim == 2) fn(integral_constant<int, 2>{});
+    else fn(integral_constant<int, 3>{});
+}
+
 __device__ __forceinline__ void node_ijk(const NodeMap &nm, unsigned long long t, int &i, int &j,
                                          int &k)
 {
@@ -409,7 +418,9 @@ __device__ __forceinline__ void restrict32_node(const ELevel &F, const ELevel &C
 {
     int i, j, k;
     node_ijk(C.nm, t, i, j, k);
-    restrict_at<float>(C.geo, F.geo, F.dl, F.r, C.dbar, C.rhs, i, j, k);
+    dim_switch(C.geo.dim, [&](auto Dm) {
+        restrict_at<decltype(Dm)::value, float>(C.geo, F.geo, F.dl, F.r, C.dbar, C.rhs, i, j, k);
+    });
 }
 
 __device__ __forceinline__ void crhs32_node(const ESlot &S, float a, const ELevel &C,
@@ -432,7 +443,9 @@ __device__ __forceinline__ void prolong32_node(const ELevel &F, const ELevel &C,
 {
     int i, j, k;
     node_ijk(F.nm, t, i, j, k);
-    prolong_at<float>(F.geo, C.geo, C.dl, C.dbar, F.dl, i, j, k);
+    dim_switch(F.geo.dim, [&](auto Dm) {
+        prolong_at<decltype(Dm)::value, float>(F.geo, C.geo, C.dl, C.dbar, F.dl, i, j, k);
+    });
 }
 
 // op 0: inner defect on level d; 1: restriction d -> d+1; 2: FAS right-hand

@@ -610,8 +610,7 @@ void launch_residual(const Geo &g, const Law &law, const Step &st, const double 
 void launch_restrict(const Geo &gc, const Geo &gf, const double *psi_f, const double *d_f,
                      double *psibar_c, double *g_c, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_restrict<double>), node_grid(gc), dim3(kBX, kBY), 0, s, gc, gf, psi_f, d_f,
-                       psibar_c, g_c);
+    launch_restrict_t<double>(gc, gf, psi_f, d_f, psibar_c, g_c, s);
 }
 
 void launch_coarse_rhs(const Geo &gc, const Law &law, const Step &st, const double *beta,
@@ -625,8 +624,7 @@ void launch_coarse_rhs(const Geo &gc, const Law &law, const Step &st, const doub
 void launch_prolong(const Geo &gf, const Geo &gc, const double *psi_c, const double *psibar_c,
                     double *psi_f, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_prolong<double>), node_grid(gf), dim3(kBX, kBY), 0, s, gf, gc, psi_c, psibar_c,
-                       psi_f);
+    launch_prolong_t<double>(gf, gc, psi_c, psibar_c, psi_f, s);
 }
 
 }  // namespace rs

@@ -230,15 +230,13 @@ void launch_coarse_rhs32(const Geo &g, const Law32 &law, float a, const double *
 void launch_restrict32(const Geo &gc, const Geo &gf, const float *dl_f, const float *r_f,
                        float *dbar_c, float *rhs_c, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_restrict<float>), node_grid(gc), dim3(kBX, kBY), 0, s, gc, gf, dl_f, r_f,
-                       dbar_c, rhs_c);
+    launch_restrict_t<float>(gc, gf, dl_f, r_f, dbar_c, rhs_c, s);
 }
 
 void launch_prolong32(const Geo &gf, const Geo &gc, const float *dl_c, const float *dbar_c,
                       float *dl_f, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_prolong<float>), node_grid(gf), dim3(kBX, kBY), 0, s, gf, gc, dl_c,
-                       dbar_c, dl_f);
+    launch_prolong_t<float>(gf, gc, dl_c, dbar_c, dl_f, s);
 }
 
 void launch_inject32(const Geo &gc, const Geo &gf, const float *vf, float *vc, hipStream_t s)

@@ -10,39 +10,46 @@ namespace rs {
 
 // psibar_H = FW(psi_h), d_H = FW(d_h) stored in g_H (Dirichlet coarse nodes:
 // injection of psi, zero defect).  FW: tensor (1/4, 1/2, 1/4) around fine node
-// 2I, missing neighbours mirrored at the domain boundary.
-template <typename T>
+// 2I, missing neighbours mirrored at the domain boundary.  The taps are summed
+// axis 2 outermost, axis 0 innermost, with weight (w0 w1) w2.
+template <int DIM, typename T>
 __device__ __forceinline__ void restrict_at(const Geo &gc, const Geo &gf, const T *psi_f,
                                             const T *d_f, T *psibar_c, T *g_c, int I0, int I1,
                                             int I2)
 {
-    long long I = I0 + (long long)I1 * gc.stride[1] + (long long)I2 * gc.stride[2];
-    int F[3] = {2 * I0, 2 * I1, 2 * I2};
+    const long long I = I0 + (long long)I1 * gc.stride[1] + (long long)I2 * gc.stride[2];
+    const int F[3] = {2 * I0, 2 * I1, 2 * I2};
     if (dirichlet_at(gc, I0, I1, I2, nullptr)) {
         psibar_c[I] = psi_f[F[0] + (long long)F[1] * gf.stride[1] + (long long)F[2] * gf.stride[2]];
         g_c[I] = T(0);
         return;
     }
-    int lo[3], hi[3];
+    // fine offsets of the three taps per axis (mirrored at both ends)
+    long long off[3][3];
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
-        lo[l] = (l < gf.dim) ? -1 : 0;
-        hi[l] = (l < gf.dim) ? 1 : 0;
+        const int n = gf.n[l];
+        const long long st = gf.stride[l];
+        const int m = F[l] == 0 ? 1 : F[l] - 1;
+        const int p = F[l] == n - 1 ? n - 2 : F[l] + 1;
+        off[l][0] = (long long)m * st;
+        off[l][1] = (long long)F[l] * st;
+        off[l][2] = (long long)p * st;
     }
+    const T wt[3] = {T(0.25), T(0.5), T(0.25)};
     T sp = T(0), sd = T(0);
-    for (int o2 = lo[2]; o2 <= hi[2]; ++o2) {
-        int f2 = F[2] + o2;
-        f2 = f2 < 0 ? -f2 : (f2 > gf.n[2] - 1 ? 2 * (gf.n[2] - 1) - f2 : f2);
-        T w2 = (gf.dim > 2) ? (o2 == 0 ? T(0.5) : T(0.25)) : T(1);
-        for (int o1 = lo[1]; o1 <= hi[1]; ++o1) {
-            int f1 = F[1] + o1;
-            f1 = f1 < 0 ? -f1 : (f1 > gf.n[1] - 1 ? 2 * (gf.n[1] - 1) - f1 : f1);
-            T w1 = (gf.dim > 1) ? (o1 == 0 ? T(0.5) : T(0.25)) : T(1);
-            for (int o0 = -1; o0 <= 1; ++o0) {
-                int f0 = F[0] + o0;
-                f0 = f0 < 0 ? -f0 : (f0 > gf.n[0] - 1 ? 2 * (gf.n[0] - 1) - f0 : f0);
-                T w = (o0 == 0 ? T(0.5) : T(0.25)) * w1 * w2;
-                long long fi = f0 + (long long)f1 * gf.stride[1] + (long long)f2 * gf.stride[2];
+#pragma unroll
+    for (int o2 = 0; o2 < (DIM > 2 ? 3 : 1); ++o2) {
+        const T w2 = DIM > 2 ? wt[o2] : T(1);
+        const long long b2 = DIM > 2 ? off[2][o2] : 0;
+#pragma unroll
+        for (int o1 = 0; o1 < (DIM > 1 ? 3 : 1); ++o1) {
+            const T w1 = DIM > 1 ? wt[o1] : T(1);
+            const long long b1 = b2 + (DIM > 1 ? off[1][o1] : 0);
+#pragma unroll
+            for (int o0 = 0; o0 < 3; ++o0) {
+                const T w = wt[o0] * w1 * w2;
+                const long long fi = b1 + off[0][o0];
                 sp += w * psi_f[fi];
                 sd += w * d_f[fi];
             }
@@ -52,61 +59,156 @@ __device__ __forceinline__ void restrict_at(const Geo &gc, const Geo &gf, const 
     g_c[I] = sd;
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_restrict(Geo gc, Geo gf, const T *psi_f, const T *d_f,
-                                                  T *psibar_c, T *g_c)
-{
-    int I0 = blockIdx.x * kBX + threadIdx.x;
-    int I1 = blockIdx.y * kBY + threadIdx.y;
-    int I2 = blockIdx.z;
-    if (I0 >= gc.n[0] || I1 >= gc.n[1]) return;
-    restrict_at<T>(gc, gf, psi_f, d_f, psibar_c, g_c, I0, I1, I2);
-}
-
 // psi_h += I_h^H (psi_H - psibar_H) at fine unknowns (tensor linear
-// interpolation: even index -> coarse node, odd -> mean of the two).
-template <typename T>
+// interpolation: even index -> coarse node, odd -> mean of the two).  Two taps
+// per axis, the second with weight 0 at an even index, so the sum has no
+// branch and equals the sum over the contributing coarse nodes.
+template <int DIM, typename T>
 __device__ __forceinline__ void prolong_at(const Geo &gf, const Geo &gc, const T *psi_c,
                                            const T *psibar_c, T *psi_f, int i, int j, int k)
 {
     if (dirichlet_at(gf, i, j, k, nullptr)) return;
-    int c[3] = {i, j, k};
-    int a0[3], a1[3], cnt[3];
-    T wt[3];
+    const int c[3] = {i, j, k};
+    long long off[3][2];
+    T wt[3][2];
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
-        if (c[l] & 1) {
-            a0[l] = (c[l] - 1) >> 1;
-            a1[l] = (c[l] + 1) >> 1;
-            cnt[l] = 2;
-            wt[l] = T(0.5);
-        } else {
-            a0[l] = a1[l] = c[l] >> 1;
-            cnt[l] = 1;
-            wt[l] = T(1);
-        }
+        const bool odd = c[l] & 1;
+        off[l][0] = (long long)(c[l] >> 1) * gc.stride[l];
+        off[l][1] = (long long)((c[l] + 1) >> 1) * gc.stride[l];
+        wt[l][0] = odd ? T(0.5) : T(1);
+        wt[l][1] = odd ? T(0.5) : T(0);
     }
     T e = T(0);
-    for (int q2 = 0; q2 < cnt[2]; ++q2)
-        for (int q1 = 0; q1 < cnt[1]; ++q1)
-            for (int q0 = 0; q0 < cnt[0]; ++q0) {
-                long long J = (q0 ? a1[0] : a0[0]) + (long long)(q1 ? a1[1] : a0[1]) * gc.stride[1] +
-                              (long long)(q2 ? a1[2] : a0[2]) * gc.stride[2];
-                e += wt[0] * wt[1] * wt[2] * (psi_c[J] - psibar_c[J]);
+#pragma unroll
+    for (int q2 = 0; q2 < (DIM > 2 ? 2 : 1); ++q2) {
+        const T w2 = DIM > 2 ? wt[2][q2] : T(1);
+        const long long b2 = DIM > 2 ? off[2][q2] : 0;
+#pragma unroll
+        for (int q1 = 0; q1 < (DIM > 1 ? 2 : 1); ++q1) {
+            const T w1 = DIM > 1 ? wt[1][q1] : T(1);
+            const long long b1 = b2 + (DIM > 1 ? off[1][q1] : 0);
+#pragma unroll
+            for (int q0 = 0; q0 < 2; ++q0) {
+                const long long J = b1 + off[0][q0];
+                e += wt[0][q0] * w1 * w2 * (psi_c[J] - psibar_c[J]);
             }
-    long long idx = i + (long long)j * gf.stride[1] + (long long)k * gf.stride[2];
+        }
+    }
+    const long long idx = i + (long long)j * gf.stride[1] + (long long)k * gf.stride[2];
     psi_f[idx] += e;
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_prolong(Geo gf, Geo gc, const T *psi_c, const T *psibar_c,
-                                                 T *psi_f)
+// One coarse node per thread (restriction) / one fine node per thread
+// (prolongation), work-groups numbered per XCD.
+template <int DIM, typename T>
+__global__ __launch_bounds__(256) void k_restrict(Geo gc, Geo gf, const T *psi_f, const T *d_f,
+                                                  T *psibar_c, T *g_c, NodeMap nm)
 {
-    int i = blockIdx.x * kBX + threadIdx.x;
-    int j = blockIdx.y * kBY + threadIdx.y;
-    int k = blockIdx.z;
-    if (i >= gf.n[0] || j >= gf.n[1]) return;
-    prolong_at<T>(gf, gc, psi_c, psibar_c, psi_f, i, j, k);
+    const unsigned long long t =
+        (unsigned long long)xcd_block(gridDim.x / 8u) * blockDim.x + threadIdx.x;
+    if (t >= (unsigned long long)gc.N) return;
+    const unsigned row = udiv(t, nm.n0, nm.inv0);
+    const int i = (int)(t - (unsigned long long)row * nm.n0);
+    const int k = (int)udiv(row, nm.n1, nm.inv1);
+    const int j = (int)row - k * (int)nm.n1;
+    restrict_at<DIM, T>(gc, gf, psi_f, d_f, psibar_c, g_c, i, j, k);
+}
+
+// Prolongation by coarse cell: the thread of coarse node I loads psi_H - psibar_H
+// on the 2^DIM corners I + {0,1}^DIM once and updates the fine nodes 2I + {0,1}^DIM
+// (those inside the grid), each with the sum of prolong_at in the same order.
+template <int DIM, typename T>
+__global__ __launch_bounds__(256) void k_prolong(Geo gf, Geo gc, const T *psi_c, const T *psibar_c,
+                                                 T *psi_f, NodeMap nmc)
+{
+    const unsigned long long t =
+        (unsigned long long)xcd_block(gridDim.x / 8u) * blockDim.x + threadIdx.x;
+    if (t >= (unsigned long long)gc.N) return;
+    const unsigned row = udiv(t, nmc.n0, nmc.inv0);
+    int Ic[3] = {(int)(t - (unsigned long long)row * nmc.n0), 0, 0};
+    Ic[2] = (int)udiv(row, nmc.n1, nmc.inv1);
+    Ic[1] = (int)row - Ic[2] * (int)nmc.n1;
+    // corner offsets (the upper corner clamped at the last coarse node: its
+    // weight is 0 there or the fine node lies outside the grid)
+    long long co[3][2];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        const int lo = Ic[l];
+        const int hi = lo + 1 < gc.n[l] ? lo + 1 : lo;
+        co[l][0] = (long long)lo * gc.stride[l];
+        co[l][1] = (long long)hi * gc.stride[l];
+    }
+    constexpr int N2 = DIM > 2 ? 2 : 1, N1 = DIM > 1 ? 2 : 1;
+    T E[N2][N1][2];
+#pragma unroll
+    for (int q2 = 0; q2 < N2; ++q2)
+#pragma unroll
+        for (int q1 = 0; q1 < N1; ++q1)
+#pragma unroll
+            for (int q0 = 0; q0 < 2; ++q0) {
+                const long long J = (DIM > 2 ? co[2][q2] : 0) + (DIM > 1 ? co[1][q1] : 0) + co[0][q0];
+                E[q2][q1][q0] = psi_c[J] - psibar_c[J];
+            }
+#pragma unroll
+    for (int a2 = 0; a2 < N2; ++a2) {
+        const int f2 = 2 * Ic[2] + a2;
+        if (f2 >= gf.n[2]) continue;
+#pragma unroll
+        for (int a1 = 0; a1 < N1; ++a1) {
+            const int f1 = 2 * Ic[1] + a1;
+            if (f1 >= gf.n[1]) continue;
+#pragma unroll
+            for (int a0 = 0; a0 < 2; ++a0) {
+                const int f0 = 2 * Ic[0] + a0;
+                if (f0 >= gf.n[0]) continue;
+                if (dirichlet_at(gf, f0, f1, f2, nullptr)) continue;
+                // weights of the two taps along an axis: even fine index (1, 0),
+                // odd (1/2, 1/2)
+                const T w0[2] = {a0 ? T(0.5) : T(1), a0 ? T(0.5) : T(0)};
+                const T w1[2] = {a1 ? T(0.5) : T(1), a1 ? T(0.5) : T(0)};
+                const T w2[2] = {a2 ? T(0.5) : T(1), a2 ? T(0.5) : T(0)};
+                T e = T(0);
+#pragma unroll
+                for (int q2 = 0; q2 < N2; ++q2)
+#pragma unroll
+                    for (int q1 = 0; q1 < N1; ++q1)
+#pragma unroll
+                        for (int q0 = 0; q0 < 2; ++q0)
+                            e += w0[q0] * (DIM > 1 ? w1[q1] : T(1)) * (DIM > 2 ? w2[q2] : T(1)) *
+                                 E[q2][q1][q0];
+                psi_f[f0 + (long long)f1 * gf.stride[1] + (long long)f2 * gf.stride[2]] += e;
+            }
+        }
+    }
+}
+
+template <typename T>
+inline void launch_restrict_t(const Geo &gc, const Geo &gf, const T *psi_f, const T *d_f,
+                              T *psibar_c, T *g_c, hipStream_t s)
+{
+    const dim3 grid(xcd_grid(((unsigned long long)gc.N + 255) / 256));
+    const NodeMap nm = node_map(gc);
+    if (gc.dim == 1)
+        hipLaunchKernelGGL((k_restrict<1, T>), grid, dim3(256), 0, s, gc, gf, psi_f, d_f, psibar_c, g_c, nm);
+    else if (gc.dim == 2)
+        hipLaunchKernelGGL((k_restrict<2, T>), grid, dim3(256), 0, s, gc, gf, psi_f, d_f, psibar_c, g_c, nm);
+    else
+        hipLaunchKernelGGL((k_restrict<3, T>), grid, dim3(256), 0, s, gc, gf, psi_f, d_f, psibar_c, g_c, nm);
+}
+
+template <typename T>
+inline void launch_prolong_t(const Geo &gf, const Geo &gc, const T *psi_c, const T *psibar_c,
+                             T *psi_f, hipStream_t s)
+{
+    const dim3 grid(xcd_grid(((unsigned long long)gc.N + 255) / 256));
+    const NodeMap nm = node_map(gc);
+    if (gf.dim == 1)
+        hipLaunchKernelGGL((k_prolong<1, T>), grid, dim3(256), 0, s, gf, gc, psi_c, psibar_c, psi_f, nm);
+    else if (gf.dim == 2)
+        hipLaunchKernelGGL((k_prolong<2, T>), grid, dim3(256), 0, s, gf, gc, psi_c, psibar_c, psi_f, nm);
+    else
+        hipLaunchKernelGGL((k_prolong<3, T>), grid, dim3(256), 0, s, gf, gc, psi_c, psibar_c, psi_f, nm);
 }
 
 // Injection to a coarse level: v_H[I] = v_h[2I].
