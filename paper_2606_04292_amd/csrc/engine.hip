@@ -55,6 +55,8 @@ constexpr int kWideGroups = 2048;   // work-groups of every batched multi-group 
 constexpr int kEngMaxLevels = 12;   // up to 2^11 + 1 nodes on the shortest axis
 constexpr int kMaxSlots = 4096;
 constexpr int kMaxWide = 8;
+constexpr int kTailThreads = 512;         // work-group of the small-level cycle
+constexpr size_t kTailLdsMax = 152 * 1024;  // LDS the small-level cycle may use
 
 enum : int { kEmpty = 0, kBegin = 1, kActive = 2, kFinished = 3, kFailed = 4 };
 
@@ -65,6 +67,16 @@ struct ELevel {
     float *dl, *K32, *rhs, *r, *dbar, *pb;
 };
 
+// The six FP32 arrays of one level (in HBM, or in LDS for the small levels).
+struct Arrs {
+    float *dl, *K32, *rhs, *r, *dbar, *pb;
+};
+
+__device__ __forceinline__ Arrs arrs_of(const ELevel &L)
+{
+    return Arrs{L.dl, L.K32, L.rhs, L.r, L.dbar, L.pb};
+}
+
 struct ESlot {
     Law law;
     Law32 law32;
@@ -73,6 +85,7 @@ struct ESlot {
     double *psi, *psi_n, *psi_nm1, *K, *g;
     double tol_abs, tol_rel;
     int stagnation, max_corr;
+    int tail_lds;   // small levels fit in the tail's LDS
 };
 
 struct EDyn {
@@ -398,53 +411,55 @@ __global__ __launch_bounds__(256) void e_sweep32(const EList *DL, const ESlot *s
 }
 
 __device__ __forceinline__ void resid32_node(const ESlot &S, float a, const ELevel &Lv,
-                                             unsigned long long t)
+                                             const Arrs &A, unsigned long long t)
 {
     int i, j, k;
     node_ijk(Lv.nm, t, i, j, k);
     float v = 0.0f;
     if (!dirichlet_at(Lv.geo, i, j, k, nullptr)) {
         law_dim(S.law.model, Lv.geo.dim, [&](auto M, auto Dm) {
-            v = Lv.rhs[t] - apply_Nd<decltype(M)::value, false, decltype(Dm)::value>(
-                                Lv.geo, S.law32, a, nullptr, Lv.K32, Lv.pb, Lv.dl, i, j, k,
-                                (long long)t);
+            v = A.rhs[t] - apply_Nd<decltype(M)::value, false, decltype(Dm)::value>(
+                               Lv.geo, S.law32, a, nullptr, A.K32, A.pb, A.dl, i, j, k,
+                               (long long)t);
         });
     }
-    Lv.r[t] = v;
+    A.r[t] = v;
 }
 
-__device__ __forceinline__ void restrict32_node(const ELevel &F, const ELevel &C,
-                                                unsigned long long t)
+__device__ __forceinline__ void restrict32_node(const ELevel &F, const ELevel &C, const Arrs &AF,
+                                                const Arrs &AC, unsigned long long t)
 {
     int i, j, k;
     node_ijk(C.nm, t, i, j, k);
     dim_switch(C.geo.dim, [&](auto Dm) {
-        restrict_at<decltype(Dm)::value, float>(C.geo, F.geo, F.dl, F.r, C.dbar, C.rhs, i, j, k);
+        restrict_at<decltype(Dm)::value, float>(C.geo, F.geo, AF.dl, AF.r, AC.dbar, AC.rhs, i, j,
+                                                k);
     });
 }
 
 __device__ __forceinline__ void crhs32_node(const ESlot &S, float a, const ELevel &C,
-                                            unsigned long long t)
+                                            const Arrs &AC, unsigned long long t)
 {
     int i, j, k;
     node_ijk(C.nm, t, i, j, k);
     if (!dirichlet_at(C.geo, i, j, k, nullptr)) {
         law_dim(S.law.model, C.geo.dim, [&](auto M, auto Dm) {
-            C.rhs[t] = apply_Nd<decltype(M)::value, false, decltype(Dm)::value>(
-                           C.geo, S.law32, a, nullptr, C.K32, C.pb, C.dbar, i, j, k, (long long)t) +
-                       C.rhs[t];
+            AC.rhs[t] = apply_Nd<decltype(M)::value, false, decltype(Dm)::value>(
+                            C.geo, S.law32, a, nullptr, AC.K32, AC.pb, AC.dbar, i, j, k,
+                            (long long)t) +
+                        AC.rhs[t];
         });
     }
-    C.dl[t] = C.dbar[t];
+    AC.dl[t] = AC.dbar[t];
 }
 
-__device__ __forceinline__ void prolong32_node(const ELevel &F, const ELevel &C,
-                                               unsigned long long t)
+__device__ __forceinline__ void prolong32_node(const ELevel &F, const ELevel &C, const Arrs &AF,
+                                               const Arrs &AC, unsigned long long t)
 {
     int i, j, k;
     node_ijk(F.nm, t, i, j, k);
     dim_switch(F.geo.dim, [&](auto Dm) {
-        prolong_at<decltype(Dm)::value, float>(F.geo, C.geo, C.dl, C.dbar, F.dl, i, j, k);
+        prolong_at<decltype(Dm)::value, float>(F.geo, C.geo, AC.dl, AC.dbar, AF.dl, i, j, k);
     });
 }
 
@@ -463,14 +478,15 @@ __global__ __launch_bounds__(256) void e_transfer32(const EList *DL, const ESlot
         const ELevel &C = levels[s * kEngMaxLevels + L.lev[it] + 1];
         const unsigned long long t = (unsigned long long)tile * kTile + threadIdx.x;
         const float a = (float)dyn[s].a;
+        const Arrs AF = arrs_of(F), AC = arrs_of(C);
         if (kind == 1) {
             if (t >= (unsigned long long)F.geo.N) return;
-            if (op == 0) resid32_node(S, a, F, t);
-            else prolong32_node(F, C, t);
+            if (op == 0) resid32_node(S, a, F, AF, t);
+            else prolong32_node(F, C, AF, AC, t);
         } else {
             if (t >= (unsigned long long)C.geo.N) return;
-            if (op == 1) restrict32_node(F, C, t);
-            else crhs32_node(S, a, C, t);
+            if (op == 1) restrict32_node(F, C, AF, AC, t);
+            else crhs32_node(S, a, C, AC, t);
         }
     }, NoFlush{});
 }
@@ -480,7 +496,7 @@ __global__ __launch_bounds__(256) void e_transfer32(const EList *DL, const ESlot
 // to the coarsest and back, with work-group barriers between the steps.
 // ---------------------------------------------------------------------------
 
-__device__ void tail_sweeps(const ESlot &S, float a, const ELevel &Lv, int n)
+__device__ void tail_sweeps(const ESlot &S, float a, const ELevel &Lv, const Arrs &A, int n)
 {
     for (int sw = 0; sw < n; ++sw)
         for (int colour = 0; colour < 2; ++colour) {
@@ -490,7 +506,7 @@ __device__ void tail_sweeps(const ESlot &S, float a, const ELevel &Lv, int n)
                 if (dirichlet_at(Lv.geo, i, j, k, nullptr)) continue;
                 law_dim(S.law.model, Lv.geo.dim, [&](auto M, auto Dm) {
                     ngs_cell32<decltype(M)::value, false, decltype(Dm)::value>(
-                        Lv.geo, S.law32, a, nullptr, 0.0f, Lv.K32, Lv.rhs, Lv.pb, Lv.dl, i, j, k,
+                        Lv.geo, S.law32, a, nullptr, 0.0f, A.K32, A.rhs, A.pb, A.dl, i, j, k,
                         colour);
                 });
             }
@@ -498,10 +514,63 @@ __device__ void tail_sweeps(const ESlot &S, float a, const ELevel &Lv, int n)
         }
 }
 
-__global__ __launch_bounds__(256) void e_tail(const EList *TL, const ESlot *slots,
+// The V-cycle from level top down to the coarsest and back, one work-group;
+// arrs(l) gives the arrays of level l the cycle works on.
+template <typename Arr>
+__device__ void tail_cycle(const ESlot &S, float a, const ELevel *LV, int top, int last, int nu1,
+                           int nu2, int nuc, Arr &&arrs)
+{
+    for (int l = top; l < last; ++l) {
+        const ELevel &F = LV[l], &C = LV[l + 1];
+        const Arrs AF = arrs(l), AC = arrs(l + 1);
+        tail_sweeps(S, a, F, AF, nu1);
+        for (unsigned long long t = threadIdx.x; t < (unsigned long long)F.geo.N; t += blockDim.x)
+            resid32_node(S, a, F, AF, t);
+        __syncthreads();
+        for (unsigned long long t = threadIdx.x; t < (unsigned long long)C.geo.N; t += blockDim.x)
+            restrict32_node(F, C, AF, AC, t);
+        __syncthreads();
+        for (unsigned long long t = threadIdx.x; t < (unsigned long long)C.geo.N; t += blockDim.x)
+            crhs32_node(S, a, C, AC, t);
+        __syncthreads();
+    }
+    tail_sweeps(S, a, LV[last], arrs(last), nuc);
+    for (int l = last - 1; l >= top; --l) {
+        const ELevel &F = LV[l], &C = LV[l + 1];
+        const Arrs AF = arrs(l), AC = arrs(l + 1);
+        for (unsigned long long t = threadIdx.x; t < (unsigned long long)F.geo.N; t += blockDim.x)
+            prolong32_node(F, C, AF, AC, t);
+        __syncthreads();
+        tail_sweeps(S, a, F, AF, nu2);
+    }
+}
+
+// Arrays of level l of a request whose small levels live in LDS: levels
+// top..last one after another, each as dl, K32, rhs, r, dbar, pb (N_l floats).
+__device__ __forceinline__ Arrs lds_arrs(const ELevel *LV, int top, int l, float *smem)
+{
+    size_t off = 0;
+    for (int q = top; q < l; ++q) off += 6 * (size_t)LV[q].geo.N;
+    const size_t N = (size_t)LV[l].geo.N;
+    float *p = smem + off;
+    return Arrs{p, p + N, p + 2 * N, p + 3 * N, p + 4 * N, p + 5 * N};
+}
+
+__device__ __forceinline__ void block_copy(float *dst, const float *src, long long n)
+{
+    for (long long t = threadIdx.x; t < n; t += blockDim.x) dst[t] = src[t];
+}
+
+// One work-group per request runs its small levels.  A request whose small
+// levels fit in LDS (ESlot::tail_lds) works there: K32 and psi_b of every small
+// level and delta, rhs of the top one are staged in, the cycle runs on LDS,
+// and delta of the top level is written back (the wide levels' prolongation
+// reads it).
+__global__ __launch_bounds__(512) void e_tail(const EList *TL, const ESlot *slots,
                                               const EDyn *dyn, const ELevel *levels, int nu1,
                                               int nu2, int nuc)
 {
+    extern __shared__ float smem[];
     const int b = blockIdx.x;
     if (b >= TL->count) return;
     const int s = TL->slot[b];
@@ -510,27 +579,25 @@ __global__ __launch_bounds__(256) void e_tail(const EList *TL, const ESlot *slot
     const ELevel *LV = levels + s * kEngMaxLevels;
     const float a = (float)dyn[s].a;
     const int top = S.wide, last = S.nlev - 1;
-    for (int l = top; l < last; ++l) {
-        const ELevel &F = LV[l], &C = LV[l + 1];
-        tail_sweeps(S, a, F, nu1);
-        for (unsigned long long t = threadIdx.x; t < (unsigned long long)F.geo.N; t += blockDim.x)
-            resid32_node(S, a, F, t);
-        __syncthreads();
-        for (unsigned long long t = threadIdx.x; t < (unsigned long long)C.geo.N; t += blockDim.x)
-            restrict32_node(F, C, t);
-        __syncthreads();
-        for (unsigned long long t = threadIdx.x; t < (unsigned long long)C.geo.N; t += blockDim.x)
-            crhs32_node(S, a, C, t);
-        __syncthreads();
+    if (!S.tail_lds) {
+        tail_cycle(S, a, LV, top, last, nu1, nu2, nuc, [&](int l) { return arrs_of(LV[l]); });
+        return;
     }
-    tail_sweeps(S, a, LV[last], nuc);
-    for (int l = last - 1; l >= top; --l) {
-        const ELevel &F = LV[l], &C = LV[l + 1];
-        for (unsigned long long t = threadIdx.x; t < (unsigned long long)F.geo.N; t += blockDim.x)
-            prolong32_node(F, C, t);
-        __syncthreads();
-        tail_sweeps(S, a, F, nu2);
+    for (int l = top; l <= last; ++l) {
+        const Arrs A = lds_arrs(LV, top, l, smem);
+        const long long N = LV[l].geo.N;
+        block_copy(A.K32, LV[l].K32, N);
+        block_copy(A.pb, LV[l].pb, N);
+        if (l == top) {
+            block_copy(A.dl, LV[l].dl, N);
+            block_copy(A.rhs, LV[l].rhs, N);
+        }
     }
+    __syncthreads();
+    tail_cycle(S, a, LV, top, last, nu1, nu2, nuc,
+               [&](int l) { return lds_arrs(LV, top, l, smem); });
+    const Arrs T = lds_arrs(LV, top, top, smem);
+    block_copy(LV[top].dl, T.dl, LV[top].geo.N);
 }
 
 // psi += delta in FP64 on the finest level (delta is 0 at Dirichlet nodes).
@@ -712,6 +779,7 @@ struct rs_engine {
     hipGraph_t graph;
     hipGraphExec_t exec;
     bool graph_ready;
+    size_t tail_lds_bytes;            // dynamic LDS of the small-level cycle
 };
 
 namespace {
@@ -803,8 +871,8 @@ void enqueue_round(rs_engine *E)
             hipLaunchKernelGGL(e_transfer32, wg, blk, 0, s, dl, E->d_slots, E->d_dyn,
                                E->d_levels, op);
     }
-    hipLaunchKernelGGL(e_tail, dim3(o.max_slots), blk, 0, s, tail, E->d_slots, E->d_dyn,
-                       E->d_levels, o.nu1, o.nu2, o.nu_coarse);
+    hipLaunchKernelGGL(e_tail, dim3(o.max_slots), dim3(kTailThreads), E->tail_lds_bytes, s, tail,
+                       E->d_slots, E->d_dyn, E->d_levels, o.nu1, o.nu2, o.nu_coarse);
     for (int d = W - 1; d >= 0; --d) {
         const EList *dl = E->d_lists + 1 + d;
         hipLaunchKernelGGL(e_transfer32, wg, blk, 0, s, dl, E->d_slots, E->d_dyn, E->d_levels, 3);
@@ -899,12 +967,24 @@ int rs_engine_create(const rs_engine_opts *o, void *arena_dev, size_t arena_byte
     E->graph = nullptr;
     E->exec = nullptr;
     E->graph_ready = false;
+    E->tail_lds_bytes = 0;
     if (hipGetDevice(&E->device) != hipSuccess ||
         hipHostMalloc((void **)&E->host, cl.total, hipHostMallocDefault) != hipSuccess) {
         delete E;
         return fail(RS_EHIP, "pinned control mirror of %zu bytes", cl.total);
     }
     memset(E->host, 0, cl.total);
+    {
+        int lds_max = 0;
+        if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, E->device) !=
+            hipSuccess)
+            lds_max = 0;
+        size_t want = std::min(kTailLdsMax, (size_t)std::max(lds_max, 0));
+        if (want >= 64 * 1024 &&
+            hipFuncSetAttribute((const void *)e_tail, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)want) == hipSuccess)
+            E->tail_lds_bytes = want;
+    }
     E->d_slots = dev_at<ESlot>(E, cl.slots);
     E->h_slots = host_at<ESlot>(E, cl.slots);
     E->d_dyn = dev_at<EDyn>(E, cl.dyn);
@@ -989,6 +1069,11 @@ int rs_engine_submit(rs_engine *E, const rs_grid_desc *d, const rs_constitutive 
     S.tol_rel = E->o.tol_rel;
     S.stagnation = E->o.stagnation;
     S.max_corr = E->o.max_corrections;
+    {
+        size_t tb = 0;
+        for (int l = P.wide; l < P.nlev; ++l) tb += 6 * sizeof(float) * (size_t)P.geo[l].N;
+        S.tail_lds = (E->tail_lds_bytes > 0 && tb <= E->tail_lds_bytes) ? 1 : 0;
+    }
     for (int l = 0; l < P.nlev; ++l) {
         ELevel &Lv = E->h_levels[s * kEngMaxLevels + l];
         memset(&Lv, 0, sizeof Lv);
