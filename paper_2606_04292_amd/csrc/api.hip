@@ -64,6 +64,11 @@ int validate_desc(const rs_grid_desc *d)
             return fail(RS_EINVAL, "free drainage is only allowed on the bottom face");
         if (!std::isfinite(d->face_value[f])) return fail(RS_EINVAL, "face_value[%d] not finite", f);
     }
+    {
+        long long N = 1;
+        for (int l = 0; l < d->dim; ++l) N *= d->n[l];
+        if (N >= (1ll << 31)) return fail(RS_EINVAL, "grid of %lld nodes; at most 2^31 - 1", N);
+    }
     if (d->patch_face >= 0) {
         if (d->patch_face >= 2 * d->dim) return fail(RS_EINVAL, "patch_face out of range");
         if (d->dim < 2) return fail(RS_EINVAL, "a face patch needs dim >= 2");

@@ -177,9 +177,9 @@ __device__ __forceinline__ void dim_switch(int dim, Fn &&fn)
 __device__ __forceinline__ void node_ijk(const NodeMap &nm, unsigned long long t, int &i, int &j,
                                          int &k)
 {
-    const unsigned row = udiv(t, nm.n0, nm.inv0);
+    const unsigned row = udiv((unsigned)t, nm.d0);
     i = (int)(t - (unsigned long long)row * nm.n0);
-    k = (int)udiv(row, nm.n1, nm.inv1);
+    k = (int)udiv(row, nm.d1);
     j = (int)row - k * (int)nm.n1;
 }
 
@@ -188,9 +188,9 @@ __device__ __forceinline__ bool colour_ijk(const Geo &g, const ColourMap &cm,
                                            int &k)
 {
     if (t >= cm.total) return false;
-    const unsigned row = udiv(t, cm.H, cm.invH);
+    const unsigned row = udiv((unsigned)t, cm.dH);
     const unsigned ih = (unsigned)(t - (unsigned long long)row * cm.H);
-    k = (int)udiv(row, cm.n1, cm.invN1);
+    k = (int)udiv(row, cm.dN1);
     j = (int)row - k * (int)cm.n1;
     i = 2 * (int)ih + ((j + k + colour) & 1);
     return i < g.n[0];

@@ -48,18 +48,18 @@ inline unsigned xcd_grid(unsigned long long blocks) { return (unsigned)((blocks 
 struct ColourMap {
     unsigned long long total;
     unsigned H;
-    double invH;
+    FastDiv dH;
     unsigned n1;
-    double invN1;
+    FastDiv dN1;
 };
 
 inline ColourMap colour_map(const Geo &g)
 {
     ColourMap m;
     m.H = (unsigned)((g.n[0] + 1) / 2);
-    m.invH = 1.0 / m.H;
+    m.dH = make_fastdiv(m.H);
     m.n1 = (unsigned)g.n[1];
-    m.invN1 = 1.0 / m.n1;
+    m.dN1 = make_fastdiv(m.n1);
     m.total = (unsigned long long)m.H * g.n[1] * g.n[2];
     return m;
 }
@@ -126,7 +126,7 @@ __device__ __forceinline__ Stencil<DIM> stencil(const Geo &g, int i, int j, int 
 
 struct NodeMap {
     unsigned n0, n1;
-    double inv0, inv1;
+    FastDiv d0, d1;
 };
 
 inline NodeMap node_map(const Geo &g)
@@ -134,8 +134,8 @@ inline NodeMap node_map(const Geo &g)
     NodeMap m;
     m.n0 = (unsigned)g.n[0];
     m.n1 = (unsigned)g.n[1];
-    m.inv0 = 1.0 / m.n0;
-    m.inv1 = 1.0 / m.n1;
+    m.d0 = make_fastdiv(m.n0);
+    m.d1 = make_fastdiv(m.n1);
     return m;
 }
 

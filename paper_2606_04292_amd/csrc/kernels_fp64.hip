@@ -317,11 +317,11 @@ __global__ __launch_bounds__(256) void k_sweep(Geo g, Law L, Step st, const doub
     const unsigned long long t =
         (unsigned long long)xcd_block(gridDim.x / 8u) * blockDim.x + threadIdx.x;
     if (t >= cm.total) return;
-    const unsigned row = udiv(t, cm.H, cm.invH);
+    const unsigned row = udiv((unsigned)t, cm.dH);
     const unsigned ih = (unsigned)(t - (unsigned long long)row * cm.H);
     unsigned j = 0, k = 0;
     if (DIM == 3) {
-        k = udiv(row, cm.n1, cm.invN1);
+        k = udiv(row, cm.dN1);
         j = row - k * cm.n1;
     } else if (DIM == 2) {
         j = row;
@@ -375,11 +375,11 @@ __global__ __launch_bounds__(256) void k_residual(Geo g, Law L, Step st, const d
     const unsigned long long t0 = (unsigned long long)xcd_block(gridDim.x / 8u) * chunk;
     const unsigned long long t1 = t0 + chunk < N ? t0 + chunk : N;
     for (unsigned long long t = t0 + threadIdx.x; t < t1; t += blockDim.x) {
-        const unsigned row = udiv(t, nm.n0, nm.inv0);
+        const unsigned row = udiv((unsigned)t, nm.d0);
         const int i = (int)(t - (unsigned long long)row * nm.n0);
         int j = 0, k = 0;
         if (DIM == 3) {
-            k = (int)udiv(row, nm.n1, nm.inv1);
+            k = (int)udiv(row, nm.d1);
             j = (int)row - k * (int)nm.n1;
         } else if (DIM == 2) {
             j = (int)row;

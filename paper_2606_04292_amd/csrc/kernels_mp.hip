@@ -26,11 +26,11 @@ __global__ __launch_bounds__(256) void k_sweep32(Geo g, Law32 L, float a, const 
     const unsigned long long t =
         (unsigned long long)xcd_block(gridDim.x / 8u) * blockDim.x + threadIdx.x;
     if (t >= cm.total) return;
-    const unsigned row = udiv(t, cm.H, cm.invH);
+    const unsigned row = udiv((unsigned)t, cm.dH);
     const unsigned ih = (unsigned)(t - (unsigned long long)row * cm.H);
     unsigned j = 0, k = 0;
     if (DIM == 3) {
-        k = udiv(row, cm.n1, cm.invN1);
+        k = udiv(row, cm.dN1);
         j = row - k * cm.n1;
     } else if (DIM == 2) {
         j = row;

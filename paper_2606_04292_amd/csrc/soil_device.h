@@ -316,14 +316,35 @@ __device__ __forceinline__ bool dirichlet_at(const Geo &g, int i, int j, int k, 
     return dir;
 }
 
-// Quotient and remainder of t by d using a double reciprocal and one
-// correction step (exact for t < 2^40).
-__device__ __forceinline__ unsigned udiv(unsigned long long t, unsigned d, double invd)
+// Division of a 32-bit index by a run-time constant d (Granlund-Montgomery):
+// with l = ceil(log2 d) and p = 31 + l, m = ceil(2^p / d) satisfies
+// m d - 2^p = e < d <= 2^l, so t m / 2^p = t/d + t e / (d 2^p) < t/d + 1/d for
+// t < 2^31 and floor(t m / 2^p) = floor(t / d).  d = 1 is carried as m = 0.
+struct FastDiv {
+    unsigned m;   // ceil(2^p / d), or 0 for d = 1
+    unsigned s;   // p - 32
+};
+
+inline FastDiv make_fastdiv(unsigned d)
 {
-    unsigned long long q = (unsigned long long)((double)t * invd);
-    if (q * d > t) --q;
-    else if ((q + 1) * d <= t) ++q;
-    return (unsigned)q;
+    FastDiv f;
+    if (d <= 1) {
+        f.m = 0;
+        f.s = 0;
+        return f;
+    }
+    unsigned l = 0;
+    while ((1ull << l) < d) ++l;
+    const unsigned long long p = 31ull + l;
+    f.m = (unsigned)(((1ull << p) + d - 1) / d);
+    f.s = (unsigned)(p - 32);
+    return f;
+}
+
+// floor(t / d) for t < 2^31 (grids are limited to 2^31 nodes).
+__device__ __forceinline__ unsigned udiv(unsigned t, const FastDiv &f)
+{
+    return f.m ? (__umulhi(t, f.m) >> f.s) : t;
 }
 
 }  // namespace rs

@@ -252,7 +252,11 @@ __device__ __forceinline__ float local_solve32(const Law32 &L, float a, float be
         else { lo = d; hi = d; }
         const float dn = d - F * f_rcp(dF);
         const bool bisect = !(dF > 0.0f) || (dn != d && !(dn > lo && dn < hi));
+        const float dold = d;
         d = bisect ? 0.5f * (lo + hi) : dn;
+        // a fixed iterate stays fixed in every later iteration: once no lane of
+        // the wave moved, the remaining iterations change nothing
+        if (!__any(d != dold)) break;
     }
     return d;
 }

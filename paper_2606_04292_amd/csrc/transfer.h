@@ -108,9 +108,9 @@ __global__ __launch_bounds__(256) void k_restrict(Geo gc, Geo gf, const T *psi_f
     const unsigned long long t =
         (unsigned long long)xcd_block(gridDim.x / 8u) * blockDim.x + threadIdx.x;
     if (t >= (unsigned long long)gc.N) return;
-    const unsigned row = udiv(t, nm.n0, nm.inv0);
+    const unsigned row = udiv((unsigned)t, nm.d0);
     const int i = (int)(t - (unsigned long long)row * nm.n0);
-    const int k = (int)udiv(row, nm.n1, nm.inv1);
+    const int k = (int)udiv(row, nm.d1);
     const int j = (int)row - k * (int)nm.n1;
     restrict_at<DIM, T>(gc, gf, psi_f, d_f, psibar_c, g_c, i, j, k);
 }
@@ -125,9 +125,9 @@ __global__ __launch_bounds__(256) void k_prolong(Geo gf, Geo gc, const T *psi_c,
     const unsigned long long t =
         (unsigned long long)xcd_block(gridDim.x / 8u) * blockDim.x + threadIdx.x;
     if (t >= (unsigned long long)gc.N) return;
-    const unsigned row = udiv(t, nmc.n0, nmc.inv0);
+    const unsigned row = udiv((unsigned)t, nmc.d0);
     int Ic[3] = {(int)(t - (unsigned long long)row * nmc.n0), 0, 0};
-    Ic[2] = (int)udiv(row, nmc.n1, nmc.inv1);
+    Ic[2] = (int)udiv(row, nmc.d1);
     Ic[1] = (int)row - Ic[2] * (int)nmc.n1;
     // corner offsets (the upper corner clamped at the last coarse node: its
     // weight is 0 there or the fine node lies outside the grid)
