@@ -174,14 +174,16 @@ def test_converged_steps_parity(torch_cuda, name):
     G.close()
 
 
-def test_full_size_block_sampled_sweep_and_setup(torch_cuda):
-    """257^3 Haverkamp block at the benchmark's launch shape: set-up (K*, g) and
-    one red-black sweep checked on sampled nodes that the oracle computes one
-    by one from the GPU's own inputs (red from the pre-sweep state, black from
-    the GPU's red values)."""
+@pytest.mark.parametrize("cfg", ["block257", "rootbox257x129"])
+def test_full_size_sampled_sweep_and_setup(torch_cuda, cfg):
+    """The 257^3 Haverkamp block (the benchmark's launch shape) and the
+    257x257x129 root-uptake box at full size: set-up (K*, g) and one red-black
+    sweep checked on sampled nodes that the oracle computes one by one from
+    the GPU's own inputs (red from the pre-sweep state, black from the GPU's
+    red values)."""
     torch = torch_cuda
-    w = W.config3()
-    say("full-size sampled", w.grid.n)
+    w = W.config3() if cfg == "block257" else W.config4()
+    say("full-size sampled", cfg, w.grid.n)
     G = rsl.Grid(w)
     G.begin_step()
     G.vcycle()      # move away from the initial state
@@ -199,12 +201,11 @@ def test_full_size_block_sampled_sweep_and_setup(torch_cuda):
     S.set(oracle.FIELD_KSTAR, K)
     S.set(oracle.FIELD_G, g)
     rng = np.random.default_rng(11)
-    n = w.grid.n[0]
-    N = n ** 3
-    idx = rng.integers(0, N, size=6000)
-    i0 = idx % n
-    i1 = (idx // n) % n
-    i2 = idx // (n * n)
+    n0, n1, n2 = w.grid.n
+    idx = rng.integers(0, n0 * n1 * n2, size=6000)
+    i0 = idx % n0
+    i1 = (idx // n0) % n1
+    i2 = idx // (n0 * n1)
     colour = (i0 + i1 + i2) % 2
     red = idx[colour == 0].astype(np.int32)
     black = idx[colour == 1].astype(np.int32)
@@ -220,6 +221,29 @@ def test_full_size_block_sampled_sweep_and_setup(torch_cuda):
     e_black = np.abs(psi1.ravel()[black] - black_o).max() / scale
     say("  sampled red rel", e_red, "black rel", e_black)
     assert e_red <= TOL_SWEEP and e_black <= TOL_SWEEP
+    G.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_full_size_slice_converged_steps(torch_cuda, precision):
+    """The 513^2 slice with its lognormal Ks field at full size: two BDF steps
+    iterated to the rounding floor on both sides (FP64, and FP32 correction
+    cycles inside FP64 defect correction) against the FP64 oracle."""
+    w = W.config2()
+    say("full-size slice", precision, w.grid.n)
+    S = oracle.Solver(w, oracle.ORDER_RB)
+    G = rsl.Grid(w, precision=rsl.RS_FP64 if precision == "fp64" else rsl.RS_MIXED)
+    opts = rsl.solve_opts(w.nu1, w.nu2, w.nu_coarse, max_cycles=FLOOR_CYCLES, tol_abs=0.0,
+                          stagnation=1)
+    for step in range(2):
+        S.begin_step()
+        oracle.solve_to_floor(S, FLOOR_CYCLES, 0.0)
+        S.end_step()
+        code, st = G.bdf_step(opts=opts)
+        assert code == rsl.RS_OK, rsl.lib().rs_last_error()
+        e = rel(np_(G.get_state()[0]), S.get(oracle.FIELD_PSI_N))
+        say("  step", step, "cycles", st.cycles, "res %.2e" % st.res, "rel", e)
+        assert e <= TOL_CONV
     G.close()
 
 

@@ -87,6 +87,27 @@ def test_served_results_match_the_fp64_oracle(torch_cuda):
             assert e <= TOL_CONV
 
 
+def test_full_size_requests_match_the_fp64_oracle(torch_cuda):
+    """The largest requests of the stream (a 513^2 slice, a 2049-node column)
+    and a 257^2 slice, served together at full size with the default engine,
+    against the oracle's converged steps."""
+    picked, want = [], [(2, 513), (1, 2049), (2, 257)]
+    for w in W.serving_requests(400):
+        key = (w.grid.dim, w.grid.n[0])
+        if key in want:
+            picked.append(w)
+            want.remove(key)
+        if not want:
+            break
+    res = serve_all(picked, serve.engine_opts())
+    for q, w in enumerate(picked):
+        psi, st = res[q]
+        assert st.state == serve.RS_REQ_FINISHED and st.status == rsl.RS_OK
+        e = rel(psi, oracle_solution(w))
+        say("full size", w.grid.dim, "D n", w.grid.n[0], "corrections", st.corrections, "rel", e)
+        assert e <= TOL_CONV
+
+
 def test_each_result_is_the_same_alone_and_in_the_mix(torch_cuda):
     reqs = small_requests(8, max1d=1025, max2d=129, seed_path=(8,))
     opts = serve.engine_opts(tail_nodes=300, rounds_per_tick=2)
