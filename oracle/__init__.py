@@ -78,6 +78,7 @@ def lib():
         L.orc_restrict.argtypes = [vp, C.c_int]
         L.orc_prolong.argtypes = [vp, C.c_int]
         L.orc_vcycle.argtypes = [vp, C.c_int, C.c_int]
+        L.orc_fmg.argtypes = [vp, C.c_int, C.c_int]
         L.orc_solve_step.restype = C.c_int
         L.orc_solve_step.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_double, _D]
         L.orc_get_field.argtypes = [vp, C.c_int, C.c_int, _D]
@@ -221,6 +222,11 @@ class Solver:
     def vcycle(self, nu1=None, nu2=None):
         lib().orc_vcycle(self.h, self.w.nu1 if nu1 is None else nu1,
                          self.w.nu2 if nu2 is None else nu2)
+
+    def fmg(self, nu1=None, nu2=None):
+        """One full-multigrid cycle FMG(nu1, nu2) on the active step."""
+        lib().orc_fmg(self.h, self.w.nu1 if nu1 is None else nu1,
+                      self.w.nu2 if nu2 is None else nu2)
 
     def solve_step(self, max_cycles=50, tol=0.0, nu1=None, nu2=None):
         hist = np.zeros(max_cycles + 1)

@@ -719,6 +719,61 @@ void orc_vcycle(orc_solver *S, int nu1, int nu2)
     vcycle_level(S, 0, nu1, nu2);
 }
 
+/* Full multigrid (section 3.2, the closing paragraph on V-cycles and FMG: start
+ * on the coarsest grid, interpolate the solution to the finer grids and run
+ * V-cycles on each; the standard scheme, read as follows).  Going down, every
+ * coarser level gets the full-weighting restriction of the finer right-hand
+ * side (zero at its Dirichlet nodes) and the injection of the finer iterate;
+ * the coarsest level is smoothed nu_coarse times; going up, every level starts
+ * from the linear interpolation of the coarser solution at its unknown nodes
+ * (Dirichlet nodes keep their values) and runs one FAS V-cycle V(nu1, nu2)
+ * with its own right-hand side. */
+void orc_fmg(orc_solver *S, int nu1, int nu2)
+{
+    int dim = S->grid.dim;
+    for (int l = 0; l + 1 < S->nlev; l++) {
+        orc_level *fl = &S->lev[l], *cl = &S->lev[l + 1];
+#pragma omp parallel for schedule(static)
+        for (int I = 0; I < cl->N; I++) {
+            int II[3];
+            coords(cl, I, II);
+            int jj[3] = {2 * II[0], 2 * II[1], 2 * II[2]};
+            cl->psi[I] = fl->psi[index_of(fl, jj)];
+            cl->g[I] = is_dirichlet(S, cl, II, NULL) ? 0.0 : fw_at(fl, fl->g, II, dim);
+        }
+    }
+    orc_sweep(S, S->nlev - 1, S->nu_coarse);
+    for (int l = S->nlev - 2; l >= 0; l--) {
+        orc_level *fl = &S->lev[l], *cl = &S->lev[l + 1];
+#pragma omp parallel for schedule(static)
+        for (int i = 0; i < fl->N; i++) {
+            int ii[3];
+            coords(fl, i, ii);
+            if (is_dirichlet(S, fl, ii, NULL)) continue;
+            int ia[3][2], na[3];
+            double wa[3][2];
+            for (int a = 0; a < 3; a++) {
+                if (a >= dim || (ii[a] % 2) == 0) {
+                    na[a] = 1; ia[a][0] = ii[a] / 2; wa[a][0] = 1.0;
+                } else {
+                    na[a] = 2;
+                    ia[a][0] = (ii[a] - 1) / 2; wa[a][0] = 0.5;
+                    ia[a][1] = (ii[a] + 1) / 2; wa[a][1] = 0.5;
+                }
+            }
+            double v = 0.0;
+            for (int c2 = 0; c2 < na[2]; c2++)
+                for (int c1 = 0; c1 < na[1]; c1++)
+                    for (int c0 = 0; c0 < na[0]; c0++) {
+                        int JJ[3] = {ia[0][c0], ia[1][c1], ia[2][c2]};
+                        v += wa[0][c0] * wa[1][c1] * wa[2][c2] * cl->psi[index_of(cl, JJ)];
+                    }
+            fl->psi[i] = v;
+        }
+        vcycle_level(S, l, nu1, nu2);
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Time stepping (eq. fully-bdf1; BDF2 reading).                             */
 /* ------------------------------------------------------------------------ */

@@ -247,3 +247,87 @@ def test_mirror_symmetric_data_give_mirror_symmetric_iterates(orc):
         S.vcycle()
         p = S.psi()
         assert np.abs(p - p[:, ::-1]).max() <= 1e-13 * np.abs(p).max()
+
+
+def inject_1d(nf):
+    nc = (nf - 1) // 2 + 1
+    Q = np.zeros((nc, nf))
+    for I in range(nc):
+        Q[I, 2 * I] = 1.0
+    return Q
+
+
+@pytest.mark.parametrize("dim,n", [(1, 33), (2, 17), (3, 9)])
+def test_linear_law_fmg_equals_textbook_fmg(orc, dim, n):
+    """Full multigrid, linear law: the oracle's FMG(2,2) equals a textbook
+    linear FMG written here from explicit matrices: right-hand sides restricted
+    down the hierarchy by full weighting (zero at Dirichlet nodes), the
+    injected fine state smoothed on the coarsest level, then on every finer
+    level linear interpolation of the coarse solution followed by one
+    correction-scheme V(2,2) cycle."""
+    bcs = [W.BC_NOFLUX] * (2 * dim)
+    bcs[2 * (dim - 1)] = W.BC_DIRICHLET
+    bcs[0] = W.BC_DIRICHLET
+    g = W.GridSpec(dim=dim, n=[n] * dim, L=[1.0] * dim, face_bc=bcs, face_value=[0.0] * (2 * dim))
+    law = W.LawSpec(model=W.MODEL_LINEAR, theta_s=0.4, theta_r=0.1, Ks=1e-3, lin_c=0.02,
+                    xi=1e-5, kappa_rule=W.KAPPA_REL, kappa=0.1, newton_iters=2)
+    psin = RNG.uniform(-1, 1, size=g.shape)
+    S = orc.Solver(workload(g, law, psin), orc.ORDER_RB)
+    S.begin_step()
+    a = S.a
+    levels, grids = [], []
+    gl = g
+    for l in range(S.nlev):
+        grids.append(gl)
+        A = textbook_laplacian(gl) * law.Ks
+        um = unknown_mask(gl)
+        diag = np.full(A.shape[0], a * law.lin_c + law.xi)
+        P = R = None
+        if l < S.nlev - 1:
+            gc = coarsen(gl)
+            umc = unknown_mask(gc)
+            R = kron_all([fw_1d(gl.n[k], 0, 0) for k in range(dim)])[np.ix_(umc, um)]
+            P = kron_all([interp_1d(gl.n[k]) for k in range(dim)])[np.ix_(um, umc)]
+        levels.append((A, P, R, rb_perm(gl, np.where(um)[0]), kappa_rel(A, law.kappa), diag))
+        if l < S.nlev - 1:
+            gl = gc
+    # right-hand sides: full-grid g restricted with zeros kept at Dirichlet nodes
+    G = [S.get(orc.FIELD_G).ravel()]
+    X = [S.psi().ravel()]
+    for l in range(S.nlev - 1):
+        gf, gc = grids[l], grids[l + 1]
+        Rf = kron_all([fw_1d(gf.n[k], 0, 0) for k in range(dim)])
+        Qf = kron_all([inject_1d(gf.n[k]) for k in range(dim)])
+        gn = Rf @ G[-1]
+        gn[~unknown_mask(gc)] = 0.0
+        G.append(gn)
+        X.append(Qf @ X[-1])
+    B = [G[l][unknown_mask(grids[l])] - a * law.theta_r for l in range(S.nlev)]
+    L = S.nlev - 1
+    x = cs_vcycle(levels, L, X[L][unknown_mask(grids[L])], B[L], 2, 2, 32)
+    for l in range(L - 1, -1, -1):
+        x = levels[l][1] @ x
+        x = cs_vcycle(levels, l, x, B[l], 2, 2, 32)
+    S.fmg(2, 2)
+    got = S.psi().ravel()[unknown_mask(g)]
+    np.testing.assert_allclose(got, x, rtol=0, atol=1e-11 * max(1.0, np.abs(x).max()))
+
+
+@pytest.mark.parametrize("name,g", CASES)
+def test_fmg_then_vcycles_reach_the_dense_newton_solution(orc, name, g):
+    """FMG only changes the start of the iteration: FMG(2,2) reduces the
+    residual, and V-cycles after it reach the same step solution as the dense
+    Newton solve."""
+    law = law_vg()
+    rng = np.random.default_rng(3)
+    psin = rng.uniform(-2.0, -0.2, size=g.shape)
+    S = orc.Solver(workload(g, law, psin), orc.ORDER_RB)
+    S.begin_step()
+    ref, _ = dense_newton(orc, S, law)
+    r0 = S.residual()
+    S.fmg(2, 2)
+    r1 = S.residual()
+    assert r1 < 0.1 * r0
+    orc.solve_to_floor(S, 200, 0.0)
+    got = S.psi()
+    assert np.abs(got - ref).max() <= 1e-10 * max(1.0, np.abs(ref).max())
