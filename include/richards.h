@@ -129,6 +129,8 @@ typedef struct rs_solve_opts {
     int stagnation;       /* also stop, with RS_OK, at the rounding floor: two cycles
                              in a row that set no new minimum of the norm */
     int mp_inner_cycles;  /* RS_MIXED: FP32 V-cycles per FP64 defect correction */
+    int fmg;              /* 1: the first cycle of every step is one FMG(nu1, nu2) cycle
+                             (rs_fmg, in FP64), counted as a cycle */
 } rs_solve_opts;
 
 typedef struct rs_step_stats {
@@ -183,6 +185,17 @@ int rs_sweep(rs_grid *g, int level, int nsweeps);
  * not NULL the fine residual max-norm after the cycle is written there and the
  * call synchronises the stream.  Errors: RS_ESTATE without begin_step. */
 int rs_vcycle(rs_grid *g, int nu1, int nu2, double *res_linf);
+
+/* One full-multigrid cycle FMG(nu1, nu2) on the active step system (section
+ * 3.2, the closing paragraph: start on the coarsest grid, interpolate the
+ * solution to the finer grids, V-cycles on each).  Every coarser level gets
+ * the full-weighting restriction of the finer right-hand side (zero at its
+ * Dirichlet nodes) and the injection of the finer iterate; the coarsest level
+ * takes nu_coarse sweeps; then each finer level starts from the linear
+ * interpolation of the coarser solution at its unknowns and runs one
+ * V(nu1, nu2).  FP64 on any grid.  res_linf as for rs_vcycle.
+ * Errors: RS_ESTATE without begin_step. */
+int rs_fmg(rs_grid *g, int nu1, int nu2, double *res_linf);
 
 /* RS_MIXED grids: one FP64 defect correction (spec precision pattern,
  * not in the paper).  The FP64 defect r = g_h - N_h(psi) is formed, then

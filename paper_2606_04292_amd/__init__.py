@@ -27,7 +27,7 @@ EXPORTS = [
     "rs_get_state", "rs_begin_step", "rs_sweep", "rs_vcycle", "rs_residual_norm",
     "rs_residual", "rs_end_step", "rs_bdf_step", "rs_copy_field", "rs_set_field",
     "rs_num_levels", "rs_level_shape", "rs_destroy_grid", "rs_last_error",
-    "rs_profile_enable", "rs_profile_read", "rs_correction_cycle",
+    "rs_profile_enable", "rs_profile_read", "rs_correction_cycle", "rs_fmg",
     # include/richards_serve.h
     "rs_engine_default_opts", "rs_engine_control_bytes", "rs_engine_request_bytes",
     "rs_engine_create", "rs_engine_submit", "rs_engine_tick", "rs_engine_fetch",
@@ -63,7 +63,7 @@ class Constitutive(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("struct_size", C.c_size_t), ("nu1", C.c_int), ("nu2", C.c_int),
                 ("nu_coarse", C.c_int), ("max_cycles", C.c_int), ("tol_abs", C.c_double),
-                ("stagnation", C.c_int), ("mp_inner_cycles", C.c_int)]
+                ("stagnation", C.c_int), ("mp_inner_cycles", C.c_int), ("fmg", C.c_int)]
 
 
 class StepStats(C.Structure):
@@ -106,6 +106,7 @@ def lib():
         L.rs_profile_enable.argtypes = [vp, C.c_int]
         L.rs_profile_read.argtypes = [vp, D, C.POINTER(C.c_longlong), D, C.c_int]
         L.rs_correction_cycle.argtypes = [vp, C.c_int, C.c_int, C.c_int, D]
+        L.rs_fmg.argtypes = [vp, C.c_int, C.c_int, D]
         _lib = L
     return _lib
 
@@ -154,11 +155,12 @@ def workspace_bytes(g, precision=RS_FP64) -> int:
 
 
 def solve_opts(nu1=2, nu2=2, nu_coarse=32, max_cycles=50, tol_abs=1e-10, stagnation=0,
-               mp_inner_cycles=1) -> SolveOpts:
+               mp_inner_cycles=1, fmg=0) -> SolveOpts:
     o = SolveOpts()
     o.struct_size = C.sizeof(SolveOpts)
     o.nu1, o.nu2, o.nu_coarse, o.max_cycles = nu1, nu2, nu_coarse, max_cycles
     o.tol_abs, o.stagnation, o.mp_inner_cycles = tol_abs, stagnation, mp_inner_cycles
+    o.fmg = fmg
     return o
 
 
@@ -296,6 +298,14 @@ class Grid:
         check(lib().rs_profile_read(self.h, C.byref(ms), C.byref(n), C.byref(cells),
                                     1 if reset else 0))
         return ms.value, n.value, cells.value
+
+    def fmg(self, nu1=None, nu2=None, want_norm=False):
+        """One full-multigrid cycle FMG(nu1, nu2) on the active step."""
+        r = C.c_double()
+        check(lib().rs_fmg(self.h, self.w.nu1 if nu1 is None else nu1,
+                           self.w.nu2 if nu2 is None else nu2,
+                           C.byref(r) if want_norm else None))
+        return r.value if want_norm else None
 
     def correction_cycle(self, inner=1, nu1=None, nu2=None, want_norm=False):
         """One FP64 defect correction with FP32 V-cycles (RS_MIXED grids)."""

@@ -474,6 +474,28 @@ int vcycle_level(rs_grid *G, int l, int nu1, int nu2)
     return sweep_level(G, l, nu2);
 }
 
+// Full multigrid (FMG): right-hand side restricted down the hierarchy by full
+// weighting (zero at Dirichlet nodes), iterate injected; nu_coarse sweeps on
+// the coarsest level; then per finer level the linear interpolation of the
+// coarser solution and one FAS V-cycle with that level's right-hand side.
+int fmg_cycle(rs_grid *G, int nu1, int nu2)
+{
+    for (int l = 0; l + 1 < G->nlev; ++l) {
+        LevelData &f = G->lev[l], &c = G->lev[l + 1];
+        launch_restrict(c.geo, f.geo, f.psi, f.g, c.psibar, c.g, G->stream);
+        launch_inject(c.geo, f.geo, f.psi, c.psi, G->stream);
+    }
+    int e = sweep_level(G, G->nlev - 1, G->nu_coarse);
+    if (e) return e;
+    for (int l = G->nlev - 2; l >= 0; --l) {
+        launch_interp(G->lev[l].geo, G->lev[l + 1].geo, G->lev[l + 1].psi, G->lev[l].psi,
+                      G->stream);
+        e = vcycle_level(G, l, nu1, nu2);
+        if (e) return e;
+    }
+    return RS_OK;
+}
+
 double *field_ptr(const rs_grid *G, int level, int field)
 {
     const LevelData &L = G->lev[level];
@@ -695,6 +717,18 @@ int rs_vcycle(rs_grid *G, int nu1, int nu2, double *res)
     return RS_OK;
 }
 
+int rs_fmg(rs_grid *G, int nu1, int nu2, double *res)
+{
+    if (!G) return fail(RS_EINVAL, "null grid");
+    if (!G->in_step) return fail(RS_ESTATE, "no active step (call rs_begin_step)");
+    if (nu1 < 0 || nu2 < 0) return fail(RS_EINVAL, "negative smoothing count");
+    int e = fmg_cycle(G, nu1, nu2);
+    if (e) return e;
+    HIPCALL(hipGetLastError());
+    if (res) return fine_norm(G, res);
+    return RS_OK;
+}
+
 int rs_correction_cycle(rs_grid *G, int inner_cycles, int nu1, int nu2, double *res)
 {
     if (!G) return fail(RS_EINVAL, "null grid");
@@ -771,7 +805,10 @@ int rs_bdf_step(rs_grid *G, double dt, int order, const rs_solve_opts *o, rs_ste
         if (e) return e;
     }
     while (std::isfinite(r) && r > o->tol_abs && cycles < o->max_cycles) {
-        if (mixed) {
+        if (o->fmg && cycles == 0) {
+            e = fmg_cycle(G, o->nu1, o->nu2);
+            if (e) return e;
+        } else if (mixed) {
             mp_correction(G, o->mp_inner_cycles > 0 ? o->mp_inner_cycles : 1, o->nu1, o->nu2);
         } else {
             e = vcycle_level(G, 0, o->nu1, o->nu2);

@@ -627,4 +627,9 @@ void launch_prolong(const Geo &gf, const Geo &gc, const double *psi_c, const dou
     launch_prolong_t<double>(gf, gc, psi_c, psibar_c, psi_f, s);
 }
 
+void launch_interp(const Geo &gf, const Geo &gc, const double *psi_c, double *psi_f, hipStream_t s)
+{
+    launch_prolong_t<double, true>(gf, gc, psi_c, nullptr, psi_f, s);
+}
+
 }  // namespace rs

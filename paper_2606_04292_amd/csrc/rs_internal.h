@@ -88,5 +88,7 @@ void launch_coarse_rhs(const Geo &gc, const Law &law, const Step &st, const doub
                        hipStream_t s);
 void launch_prolong(const Geo &gf, const Geo &gc, const double *psi_c, const double *psibar_c,
                     double *psi_f, hipStream_t s);
+// psi_f = linear interpolation of psi_c at fine unknowns (FMG interpolation)
+void launch_interp(const Geo &gf, const Geo &gc, const double *psi_c, double *psi_f, hipStream_t s);
 
 }  // namespace rs

@@ -118,7 +118,9 @@ __global__ __launch_bounds__(256) void k_restrict(Geo gc, Geo gf, const T *psi_f
 // Prolongation by coarse cell: the thread of coarse node I loads psi_H - psibar_H
 // on the 2^DIM corners I + {0,1}^DIM once and updates the fine nodes 2I + {0,1}^DIM
 // (those inside the grid), each with the sum of prolong_at in the same order.
-template <int DIM, typename T>
+// FULL: interpolate psi_H itself and assign it (the FMG interpolation;
+// psibar_c unused).
+template <int DIM, typename T, bool FULL = false>
 __global__ __launch_bounds__(256) void k_prolong(Geo gf, Geo gc, const T *psi_c, const T *psibar_c,
                                                  T *psi_f, NodeMap nmc)
 {
@@ -148,7 +150,7 @@ __global__ __launch_bounds__(256) void k_prolong(Geo gf, Geo gc, const T *psi_c,
 #pragma unroll
             for (int q0 = 0; q0 < 2; ++q0) {
                 const long long J = (DIM > 2 ? co[2][q2] : 0) + (DIM > 1 ? co[1][q1] : 0) + co[0][q0];
-                E[q2][q1][q0] = psi_c[J] - psibar_c[J];
+                E[q2][q1][q0] = FULL ? psi_c[J] : psi_c[J] - psibar_c[J];
             }
 #pragma unroll
     for (int a2 = 0; a2 < N2; ++a2) {
@@ -177,7 +179,9 @@ __global__ __launch_bounds__(256) void k_prolong(Geo gf, Geo gc, const T *psi_c,
                         for (int q0 = 0; q0 < 2; ++q0)
                             e += w0[q0] * (DIM > 1 ? w1[q1] : T(1)) * (DIM > 2 ? w2[q2] : T(1)) *
                                  E[q2][q1][q0];
-                psi_f[f0 + (long long)f1 * gf.stride[1] + (long long)f2 * gf.stride[2]] += e;
+                const long long fi = f0 + (long long)f1 * gf.stride[1] + (long long)f2 * gf.stride[2];
+                if (FULL) psi_f[fi] = e;
+                else psi_f[fi] += e;
             }
         }
     }
@@ -197,18 +201,21 @@ inline void launch_restrict_t(const Geo &gc, const Geo &gf, const T *psi_f, cons
         hipLaunchKernelGGL((k_restrict<3, T>), grid, dim3(256), 0, s, gc, gf, psi_f, d_f, psibar_c, g_c, nm);
 }
 
-template <typename T>
+template <typename T, bool FULL = false>
 inline void launch_prolong_t(const Geo &gf, const Geo &gc, const T *psi_c, const T *psibar_c,
                              T *psi_f, hipStream_t s)
 {
     const dim3 grid(xcd_grid(((unsigned long long)gc.N + 255) / 256));
     const NodeMap nm = node_map(gc);
     if (gf.dim == 1)
-        hipLaunchKernelGGL((k_prolong<1, T>), grid, dim3(256), 0, s, gf, gc, psi_c, psibar_c, psi_f, nm);
+        hipLaunchKernelGGL((k_prolong<1, T, FULL>), grid, dim3(256), 0, s, gf, gc, psi_c, psibar_c,
+                           psi_f, nm);
     else if (gf.dim == 2)
-        hipLaunchKernelGGL((k_prolong<2, T>), grid, dim3(256), 0, s, gf, gc, psi_c, psibar_c, psi_f, nm);
+        hipLaunchKernelGGL((k_prolong<2, T, FULL>), grid, dim3(256), 0, s, gf, gc, psi_c, psibar_c,
+                           psi_f, nm);
     else
-        hipLaunchKernelGGL((k_prolong<3, T>), grid, dim3(256), 0, s, gf, gc, psi_c, psibar_c, psi_f, nm);
+        hipLaunchKernelGGL((k_prolong<3, T, FULL>), grid, dim3(256), 0, s, gf, gc, psi_c, psibar_c,
+                           psi_f, nm);
 }
 
 // Injection to a coarse level: v_H[I] = v_h[2I].

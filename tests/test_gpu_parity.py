@@ -174,6 +174,50 @@ def test_converged_steps_parity(torch_cuda, name):
     G.close()
 
 
+@pytest.mark.parametrize("name", NAMES)
+def test_fmg_cycle_parity(torch_cuda, name):
+    """One FMG(nu1, nu2) cycle from the same step set-up, then one V-cycle:
+    GPU against the oracle's FMG (normwise 1e-12)."""
+    w = CASES[name]
+    say("fmg parity", name)
+    S = oracle.Solver(w, oracle.ORDER_RB)
+    G = rsl.Grid(w)
+    S.begin_step()
+    G.begin_step()
+    S.fmg()
+    G.fmg()
+    e = rel(np_(G.psi()), S.psi())
+    say("  after FMG rel", e)
+    assert e <= TOL_SWEEP
+    S.vcycle()
+    G.vcycle()
+    e = rel(np_(G.psi()), S.psi())
+    say("  after V-cycle rel", e)
+    assert e <= TOL_SWEEP
+    G.close()
+
+
+@pytest.mark.parametrize("name", ["c1_col257", "c2_slice65", "c3_block33"])
+def test_converged_steps_with_fmg_start(torch_cuda, name):
+    """Steps that start with one FMG cycle reach the oracle's step solutions."""
+    w = CASES[name]
+    say("fmg converged", name)
+    S = oracle.Solver(w, oracle.ORDER_RB)
+    G = rsl.Grid(w)
+    opts = rsl.solve_opts(w.nu1, w.nu2, w.nu_coarse, max_cycles=FLOOR_CYCLES, tol_abs=0.0,
+                          stagnation=1, fmg=1)
+    for step in range(3):
+        S.begin_step()
+        oracle.solve_to_floor(S, FLOOR_CYCLES, 0.0)
+        S.end_step()
+        code, st = G.bdf_step(opts=opts)
+        assert code == rsl.RS_OK, rsl.lib().rs_last_error()
+        e = rel(np_(G.get_state()[0]), S.get(oracle.FIELD_PSI_N))
+        say("  step", step, "cycles", st.cycles, "rel", e)
+        assert e <= TOL_CONV
+    G.close()
+
+
 @pytest.mark.parametrize("cfg", ["block257", "rootbox257x129"])
 def test_full_size_sampled_sweep_and_setup(torch_cuda, cfg):
     """The 257^3 Haverkamp block (the benchmark's launch shape) and the
