@@ -236,6 +236,59 @@ def serving_leg(args):
     }
 
 
+def paper_1d_table(args):
+    """The solver comparison of the paper's 1-D infiltration benchmark
+    (N = 2048, tau = 0.1 s, t = 360 s) on the GPU: V-cycle(5,5) and FMG(5,5)
+    per step until ||r||_inf <= 1e-12, and GS(100) (100 red-black sweeps per
+    step).  The paper's CPU times, on unstated hardware, are context only."""
+    import torch
+    import paper_2606_04292_amd as rsl
+    from paper_2606_04292_amd import workloads as W
+
+    w = W.celia_column(2049)
+    steps = args.paper_steps
+    out = {"workload": "%s: 2049 nodes over 40 cm, Haverkamp, BDF1, tau 0.1 s, %d steps" % (
+        w.name, steps), "paper_cpu_seconds_context": {"V-cycle(5,5)": 20, "FMG(5,5)": 42,
+                                                      "GS(100)": 69}}
+    finals = {}
+    for name, fmg in (("V-cycle(5,5)", 0), ("FMG(5,5)", 1)):
+        G = rsl.Grid(w, device="cuda:0")
+        opts = rsl.solve_opts(5, 5, 32, max_cycles=60, tol_abs=1e-12, stagnation=0, fmg=fmg)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cyc = 0
+        for _ in range(steps):
+            code, st = G.bdf_step(opts=opts)
+            if code != rsl.RS_OK:
+                raise SystemExit("%s step failed: %s" % (name, rsl.lib().rs_last_error().decode()))
+            cyc += st.cycles
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        finals[name] = G.get_state()[0].cpu().numpy()
+        out[name] = {"seconds": round(el, 3), "cycles_per_step": round(cyc / steps, 2)}
+        log("%s: %.2f s, %.2f cycles/step" % (name, el, cyc / steps))
+        G.close()
+    G = rsl.Grid(w, device="cuda:0")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = 0.0
+    for _ in range(steps):
+        G.begin_step()
+        G.sweep(100)
+        G.end_step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    gs = G.get_state()[0].cpu().numpy()
+    out["GS(100)"] = {"seconds": round(el, 3)}
+    ref = finals["V-cycle(5,5)"]
+    scale = float(abs(ref).max())
+    out["max_diff_vs_vcycle"] = {"FMG(5,5)": float(abs(finals["FMG(5,5)"] - ref).max()) / scale,
+                                 "GS(100)": float(abs(gs - ref).max()) / scale}
+    log("GS(100): %.2f s" % el)
+    G.close()
+    return out
+
+
 def cpu_baseline(args, n):
     import numpy as np
     import oracle
@@ -278,6 +331,9 @@ def main():
                     help="requests of the trace solved one at a time in FP64")
     ap.add_argument("--serve-arena-gib", type=float, default=16.0)
     ap.add_argument("--serve-only", action="store_true", help="run only the serving leg")
+    ap.add_argument("--paper-1d", action="store_true",
+                    help="run only the paper's 1-D solver comparison (V-cycle, FMG, GS)")
+    ap.add_argument("--paper-steps", type=int, default=3600)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 512 MiB device copy first (counter calibration)")
     args = ap.parse_args()
@@ -288,6 +344,9 @@ def main():
         sys.exit(2)
     if args.serve_only:
         print(json.dumps({"serving": serving_leg(args)}), flush=True)
+        return
+    if args.paper_1d:
+        print(json.dumps({"paper_1d_table": paper_1d_table(args)}), flush=True)
         return
     r = gpu_run(args)
     w = r["w"]

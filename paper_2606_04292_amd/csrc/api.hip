@@ -15,6 +15,7 @@
 #include "rs_internal.h"
 #include "mp_internal.h"
 #include "host_common.h"
+#include "grid_device.h"
 
 namespace rs {
 void launch_root_beta(int nlev, const int *nvert, const double *hvert, double *const *beta,
@@ -140,7 +141,7 @@ struct Layout {
     size_t lev_off[kMaxLevels][6];   // psi, K, g, d, psibar, psi_alt (fused levels)
     size_t mp_off[kMaxLevels][6];    // RS_MIXED: delta, K32, rhs, r, dbar, psi_b (FP32)
     size_t beta_off[kMaxLevels];
-    size_t psi_n, psi_nm1, ks, scratch;
+    size_t psi_n, psi_nm1, ks, scratch, tail;
     size_t total;
 };
 
@@ -176,6 +177,7 @@ void plan(const rs_grid_desc *d, int precision, Layout *L)
     L->psi_nm1 = off; off = align_up(off + sizeof(double) * N0);
     L->ks = off;      off = align_up(off + sizeof(double) * N0);
     L->scratch = off; off = align_up(off + sizeof(unsigned long long) * kScratchWords);
+    L->tail = off;    off = align_up(off + sizeof(TailArgs));
     L->total = off;
 }
 
@@ -244,6 +246,9 @@ struct rs_grid {
     bool has_ks;
     unsigned long long *scratch;
     unsigned long long *host_bits;   // pinned readback
+    TailArgs *tail_dev;               // per-level records of the one-work-group cycle
+    TailArgs *tail_host;              // pinned copy
+    int tail_top;                     // first level run by it (nlev: none)
     Law law;
     Law32 law32;
     bool law_set;
@@ -461,6 +466,15 @@ void mp_correction(rs_grid *G, int inner, int nu1, int nu2)
 int vcycle_level(rs_grid *G, int l, int nu1, int nu2)
 {
     LevelData &f = G->lev[l];
+    if (l >= G->tail_top && l < G->nlev - 1) {
+        // the rest of the cycle on small levels: one work-group, one launch
+        launch_vcycle_tail(G->tail_dev, l, G->nlev - 1, G->law, G->step, nu1, nu2, G->nu_coarse,
+                           G->desc.dim, G->stream);
+        for (int q = l; q < G->nlev - 1; ++q)
+            G->updates += (double)(nu1 + nu2) * (double)G->lev[q].unknowns;
+        G->updates += (double)G->nu_coarse * (double)G->lev[G->nlev - 1].unknowns;
+        return RS_OK;
+    }
     if (l == G->nlev - 1) return sweep_level(G, l, G->nu_coarse);
     LevelData &c = G->lev[l + 1];
     int e = sweep_level(G, l, nu1);
@@ -584,6 +598,51 @@ int rs_create_grid(const rs_grid_desc *d, int precision, void *ws_dev, size_t ws
         delete G;
         return fail(RS_EHIP, "hipHostMalloc failed");
     }
+    G->tail_dev = (TailArgs *)(base + L.tail);
+    if (hipHostMalloc((void **)&G->tail_host, sizeof(TailArgs), hipHostMallocDefault) != hipSuccess) {
+        (void)hipHostFree(G->host_bits);
+        delete G;
+        return fail(RS_EHIP, "hipHostMalloc failed");
+    }
+    memset(G->tail_host, 0, sizeof(TailArgs));
+    G->tail_top = G->nlev;
+    for (int l = G->nlev - 1; l >= 0 && G->lev[l].geo.N <= kTailNodes && !G->lev[l].psi_alt; --l)
+        G->tail_top = l;
+    for (int l = 0; l < G->nlev; ++l) {
+        const LevelData &v = G->lev[l];
+        TailLevel &T = G->tail_host->lv[l];
+        const ColourMap cm = colour_map(v.geo);
+        const NodeMap nm = node_map(v.geo);
+        T.g = v.geo;
+        T.cm_total = (long long)cm.total;
+        T.H = cm.H;
+        T.n1 = cm.n1;
+        T.dH_m = cm.dH.m;
+        T.dH_s = cm.dH.s;
+        T.dN1_m = cm.dN1.m;
+        T.dN1_s = cm.dN1.s;
+        T.n0 = nm.n0;
+        T.nn1 = nm.n1;
+        T.d0_m = nm.d0.m;
+        T.d0_s = nm.d0.s;
+        T.d1_m = nm.d1.m;
+        T.d1_s = nm.d1.s;
+        T.psi = v.psi;
+        T.K = v.K;
+        T.gv = v.g;
+        T.d = v.d;
+        T.psibar = v.psibar;
+        T.beta = v.beta;
+        T.lambdaU = 0.0;
+    }
+    if (hipMemcpyAsync(G->tail_dev, G->tail_host, sizeof(TailArgs), hipMemcpyHostToDevice,
+                       G->stream) != hipSuccess) {
+        (void)hipStreamSynchronize(G->stream);
+        (void)hipHostFree(G->tail_host);
+        (void)hipHostFree(G->host_bits);
+        delete G;
+        return fail(RS_EHIP, "hipMemcpyAsync failed");
+    }
     *out = G;
     return RS_OK;
 }
@@ -591,9 +650,10 @@ int rs_create_grid(const rs_grid_desc *d, int precision, void *ws_dev, size_t ws
 void rs_destroy_grid(rs_grid *G)
 {
     if (!G) return;
-    if (G->prof_used) (void)hipStreamSynchronize(G->stream);
+    (void)hipStreamSynchronize(G->stream);   // queued copies read the pinned buffers
     for (hipEvent_t ev : G->prof_ev) (void)hipEventDestroy(ev);
     if (G->host_bits) (void)hipHostFree(G->host_bits);
+    if (G->tail_host) (void)hipHostFree(G->tail_host);
     delete G;
 }
 
@@ -687,7 +747,11 @@ int rs_begin_step(rs_grid *G, double dt, int order)
             double v;
             memcpy(&v, &G->host_bits[1 + l], sizeof v);
             G->lev[l].lambdaU = v;
+            G->tail_host->lv[l].lambdaU = v;   // the stream is idle: the last copy is done
         }
+        if (G->tail_top < G->nlev)
+            HIPCALL(hipMemcpyAsync(G->tail_dev, G->tail_host, sizeof(TailArgs),
+                                   hipMemcpyHostToDevice, G->stream));
     }
     G->in_step = true;
     return RS_OK;

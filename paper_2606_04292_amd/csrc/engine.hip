@@ -174,28 +174,6 @@ __device__ __forceinline__ void dim_switch(int dim, Fn &&fn)
     else fn(integral_constant<int, 3>{});
 }
 
-__device__ __forceinline__ void node_ijk(const NodeMap &nm, unsigned long long t, int &i, int &j,
-                                         int &k)
-{
-    const unsigned row = udiv((unsigned)t, nm.d0);
-    i = (int)(t - (unsigned long long)row * nm.n0);
-    k = (int)udiv(row, nm.d1);
-    j = (int)row - k * (int)nm.n1;
-}
-
-__device__ __forceinline__ bool colour_ijk(const Geo &g, const ColourMap &cm,
-                                           unsigned long long t, int colour, int &i, int &j,
-                                           int &k)
-{
-    if (t >= cm.total) return false;
-    const unsigned row = udiv((unsigned)t, cm.dH);
-    const unsigned ih = (unsigned)(t - (unsigned long long)row * cm.H);
-    k = (int)udiv(row, cm.dN1);
-    j = (int)row - k * (int)cm.n1;
-    i = 2 * (int)ih + ((j + k + colour) & 1);
-    return i < g.n[0];
-}
-
 __device__ __forceinline__ Step slot_step(const ESlot &S, const EDyn &D)
 {
     Step st;

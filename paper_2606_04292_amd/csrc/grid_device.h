@@ -139,6 +139,30 @@ inline NodeMap node_map(const Geo &g)
     return m;
 }
 
+// (i, j, k) of node t of a level (t < 2^31).
+__device__ __forceinline__ void node_ijk(const NodeMap &nm, unsigned long long t, int &i, int &j,
+                                         int &k)
+{
+    const unsigned row = udiv((unsigned)t, nm.d0);
+    i = (int)(t - (unsigned long long)row * nm.n0);
+    k = (int)udiv(row, nm.d1);
+    j = (int)row - k * (int)nm.n1;
+}
+
+// (i, j, k) of colour slot t (false for the padding slot of a row).
+__device__ __forceinline__ bool colour_ijk(const Geo &g, const ColourMap &cm,
+                                           unsigned long long t, int colour, int &i, int &j,
+                                           int &k)
+{
+    if (t >= cm.total) return false;
+    const unsigned row = udiv((unsigned)t, cm.dH);
+    const unsigned ih = (unsigned)(t - (unsigned long long)row * cm.H);
+    k = (int)udiv(row, cm.dN1);
+    j = (int)row - k * (int)cm.n1;
+    i = 2 * (int)ih + ((j + k + colour) & 1);
+    return i < g.n[0];
+}
+
 inline dim3 node_grid(const Geo &g)
 {
     return dim3((g.n[0] + kBX - 1) / kBX, (g.n[1] + kBY - 1) / kBY, g.n[2]);

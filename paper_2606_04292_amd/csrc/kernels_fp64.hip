@@ -357,6 +357,100 @@ __global__ __launch_bounds__(256) void k_sweep_small(Geo g, Law L, Step st, cons
 }
 
 // ---------------------------------------------------------------------------
+// The cycle on the small levels of a grid in one work-group (levels of at most
+// kTailNodes nodes): the same per-node operations as the multi-launch cycle,
+// with work-group barriers between the steps instead of launches.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ ColourMap tail_cm(const TailLevel &T)
+{
+    ColourMap m;
+    m.total = (unsigned long long)T.cm_total;
+    m.H = T.H;
+    m.dH = FastDiv{T.dH_m, T.dH_s};
+    m.n1 = T.n1;
+    m.dN1 = FastDiv{T.dN1_m, T.dN1_s};
+    return m;
+}
+
+__device__ __forceinline__ NodeMap tail_nm(const TailLevel &T)
+{
+    NodeMap m;
+    m.n0 = T.n0;
+    m.n1 = T.nn1;
+    m.d0 = FastDiv{T.d0_m, T.d0_s};
+    m.d1 = FastDiv{T.d1_m, T.d1_s};
+    return m;
+}
+
+template <int MODEL, bool SINK, int DIM>
+__device__ void tail_sweeps64(const TailLevel &T, const Law &L, double a, int n)
+{
+    const ColourMap cm = tail_cm(T);
+    for (int sw = 0; sw < n; ++sw)
+        for (int colour = 0; colour < 2; ++colour) {
+            for (unsigned long long t = threadIdx.x; t < cm.total; t += blockDim.x) {
+                int i, j, k;
+                if (!colour_ijk(T.g, cm, t, colour, i, j, k)) continue;
+                if (dirichlet_at(T.g, i, j, k, nullptr)) continue;
+                ngs_cell<MODEL, SINK, DIM>(T.g, L, a, T.beta, T.lambdaU, T.K, T.gv, T.psi, i, j, k,
+                                           colour);
+            }
+            __syncthreads();
+        }
+}
+
+template <int MODEL, bool SINK, int DIM>
+__global__ __launch_bounds__(512) void k_vcycle_tail(const TailArgs *A, int top, int last, Law L,
+                                                     Step st, int nu1, int nu2, int nuc)
+{
+    const double a = st.a;
+    for (int l = top; l < last; ++l) {
+        const TailLevel &F = A->lv[l], &C = A->lv[l + 1];
+        tail_sweeps64<MODEL, SINK, DIM>(F, L, a, nu1);
+        const NodeMap nf = tail_nm(F), nc = tail_nm(C);
+        for (unsigned long long t = threadIdx.x; t < (unsigned long long)F.g.N; t += blockDim.x) {
+            int i, j, k;
+            node_ijk(nf, t, i, j, k);
+            double r = 0.0;
+            if (!dirichlet_at(F.g, i, j, k, nullptr))
+                r = F.gv[t] - apply_N_t<MODEL, SINK, DIM>(F.g, L, a, F.beta, F.K, F.psi, i, j, k,
+                                                          (long long)t);
+            F.d[t] = r;
+        }
+        __syncthreads();
+        for (unsigned long long t = threadIdx.x; t < (unsigned long long)C.g.N; t += blockDim.x) {
+            int i, j, k;
+            node_ijk(nc, t, i, j, k);
+            restrict_at<DIM, double>(C.g, F.g, F.psi, F.d, C.psibar, C.gv, i, j, k);
+        }
+        __syncthreads();
+        for (unsigned long long t = threadIdx.x; t < (unsigned long long)C.g.N; t += blockDim.x) {
+            int i, j, k;
+            node_ijk(nc, t, i, j, k);
+            if (!dirichlet_at(C.g, i, j, k, nullptr))
+                C.gv[t] = apply_N_t<MODEL, SINK, DIM>(C.g, L, a, C.beta, C.K, C.psibar, i, j, k,
+                                                      (long long)t) +
+                          C.gv[t];
+            C.psi[t] = C.psibar[t];
+        }
+        __syncthreads();
+    }
+    tail_sweeps64<MODEL, SINK, DIM>(A->lv[last], L, a, nuc);
+    for (int l = last - 1; l >= top; --l) {
+        const TailLevel &F = A->lv[l], &C = A->lv[l + 1];
+        const NodeMap nf = tail_nm(F);
+        for (unsigned long long t = threadIdx.x; t < (unsigned long long)F.g.N; t += blockDim.x) {
+            int i, j, k;
+            node_ijk(nf, t, i, j, k);
+            prolong_at<DIM, double>(F.g, C.g, C.psi, C.psibar, F.psi, i, j, k);
+        }
+        __syncthreads();
+        tail_sweeps64<MODEL, SINK, DIM>(F, L, a, nu2);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Defect d = g - N(psi) and its max-norm (step 2 of the FAS algorithm)
 // ---------------------------------------------------------------------------
 
@@ -625,6 +719,23 @@ void launch_prolong(const Geo &gf, const Geo &gc, const double *psi_c, const dou
                     double *psi_f, hipStream_t s)
 {
     launch_prolong_t<double>(gf, gc, psi_c, psibar_c, psi_f, s);
+}
+
+struct TailLaunch {
+    const TailArgs *A; int top, last; const Law &law; const Step &st; int nu1, nu2, nuc;
+    hipStream_t s;
+    template <int M, bool S, int D>
+    void go()
+    {
+        hipLaunchKernelGGL((k_vcycle_tail<M, S, D>), dim3(1), dim3(512), 0, s, A, top, last, law,
+                           st, nu1, nu2, nuc);
+    }
+};
+
+void launch_vcycle_tail(const TailArgs *args_dev, int top, int last, const Law &law,
+                        const Step &st, int nu1, int nu2, int nuc, int dim, hipStream_t s)
+{
+    dispatch(law, dim, TailLaunch{args_dev, top, last, law, st, nu1, nu2, nuc, s});
 }
 
 void launch_interp(const Geo &gf, const Geo &gc, const double *psi_c, double *psi_f, hipStream_t s)

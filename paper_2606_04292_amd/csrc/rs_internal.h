@@ -60,8 +60,34 @@ struct Step {
 };
 
 // ---------------------------------------------------------------------------
+// Small levels in one work-group: per-level records of a grid, kept in its
+// workspace (written at creation, lambdaU refreshed at step set-up).
+// ---------------------------------------------------------------------------
+constexpr long long kTailNodes = 8192;   // levels of at most this many nodes
+
+struct TailLevel {
+    Geo g;
+    long long cm_total;
+    unsigned H, n1;
+    unsigned dH_m, dH_s, dN1_m, dN1_s;    // colour-slot division (FastDiv parts)
+    unsigned n0, nn1;
+    unsigned d0_m, d0_s, d1_m, d1_s;      // node division
+    double *psi, *K, *gv, *d, *psibar;
+    const double *beta;
+    double lambdaU;
+};
+
+struct TailArgs {
+    TailLevel lv[kMaxLevels];
+};
+
+// ---------------------------------------------------------------------------
 // Kernel launchers (kernels_fp64.hip)
 // ---------------------------------------------------------------------------
+// The V-cycle from level top (all of whose levels hold at most kTailNodes
+// nodes) down to level last and back, in one work-group.
+void launch_vcycle_tail(const TailArgs *args_dev, int top, int last, const Law &law,
+                        const Step &st, int nu1, int nu2, int nuc, int dim, hipStream_t s);
 void launch_fill_u64(unsigned long long *p, int n, unsigned long long v, hipStream_t s);
 void launch_setup_kstar(const Geo &g, const Law &law, const Step &st, const double *psi_n,
                         const double *psi_nm1, const double *Ks_field, double *K, double *psi,

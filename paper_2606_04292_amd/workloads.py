@@ -232,6 +232,20 @@ def config4(nx: int = 257, nz: int = 129) -> Workload:
                     steps=48, order=2)
 
 
+def celia_column(n: int = 2049) -> Workload:
+    """The 1-D infiltration benchmark of section 4.1 (after Celia et al.):
+    a 40 cm Haverkamp column in cm and s, psi0 = -61.5 cm, Dirichlet -20.7 cm on
+    top and -61.5 cm at the bottom, no sink, xi = 0, Lambda_kappa = 0.1 I,
+    tau = 0.1 s, BDF1, V(5,5), run to t = 360 s."""
+    g = GridSpec(dim=1, n=[n], L=[40.0], face_bc=[BC_DIRICHLET, BC_DIRICHLET],
+                 face_value=[-61.5, -20.7])
+    law = LawSpec(model=MODEL_HAVERKAMP, theta_s=0.287, theta_r=0.075, Ks=0.00944,
+                  hk_alpha=1.611e6, hk_beta=3.96, hk_A=1.175e6, hk_gamma=4.74, psi_unit=1.0,
+                  xi=0.0, kappa_rule=KAPPA_CONST, kappa=0.1)
+    return Workload("celia_column%d" % n, g, law, np.full(n, -61.5), dt=0.1, steps=3600,
+                    order=1, nu1=5, nu2=5)
+
+
 def serving_requests(count: int = 4096, seed_path=(1,)) -> List[Workload]:
     """The request stream: half 1-D columns (65..2049 nodes), half 2-D slices
     (65^2..513^2), random vGM parameters and infiltration/drainage boundaries,

@@ -64,13 +64,8 @@ def test_paper_1d_infiltration_setup_runs_and_stays_bounded(orc):
     Lambda_kappa = 0.1 I, tau = 0.1 s, V(5,5), over the first 36 s.  Every step
     converges, the head stays within the boundary values and the wetting front
     moves down monotonically in time."""
-    n = 129
-    g = W.GridSpec(dim=1, n=[n], L=[40.0], face_bc=[W.BC_DIRICHLET, W.BC_DIRICHLET],
-                   face_value=[-61.5, -20.7])
-    law = W.LawSpec(model=W.MODEL_HAVERKAMP, theta_s=0.287, theta_r=0.075, Ks=0.00944,
-                    hk_alpha=1.611e6, hk_beta=3.96, hk_A=1.175e6, hk_gamma=4.74, psi_unit=1.0,
-                    xi=0.0, kappa_rule=W.KAPPA_CONST, kappa=0.1)
-    w = W.Workload("celia", g, law, np.full(n, -61.5), dt=0.1, steps=360, order=1, nu1=5, nu2=5)
+    w = W.celia_column(129)
+    w.steps = 360
     S = orc.Solver(w, orc.ORDER_LEX)
     front = []
     for _ in range(w.steps):
