@@ -102,7 +102,10 @@ typedef struct rs_grid_desc {
  * count).  psi_unit scales psi before the Haverkamp law (100: law in cm).
  * Ks_field: nullable HOST pointer, one saturated conductivity per fine node,
  * copied by the call. lag_extrap: for BDF2, lag the diffusion matrix at
- * 2 psi^n - psi^{n-1} instead of psi^n. */
+ * 2 psi^n - psi^{n-1} instead of psi^n.  newton_tol: the pointwise solve
+ * (eq. point-update) takes at most newton_iters safeguarded Newton steps and
+ * ends after a Newton step that moved psi by at most newton_tol |psi| (0: only
+ * a zero step ends it early; 1e-10 leaves out steps below rounding); 0..1e-3. */
 typedef struct rs_constitutive {
     size_t struct_size;   /* sizeof(rs_constitutive) */
     int model;
@@ -117,6 +120,7 @@ typedef struct rs_constitutive {
     double kappa;
     int newton_iters;
     int lag_extrap;
+    double newton_tol;
     const double *Ks_field;
 } rs_constitutive;
 

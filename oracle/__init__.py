@@ -48,7 +48,8 @@ class Params(C.Structure):
                 ("sink", C.c_int), ("Tp", C.c_double), ("root_len", C.c_double),
                 ("h1", C.c_double), ("h2", C.c_double), ("h3", C.c_double),
                 ("h4", C.c_double), ("xi", C.c_double), ("kappa_rule", C.c_int),
-                ("kappa", C.c_double), ("newton_iters", C.c_int), ("lag_extrap", C.c_int)]
+                ("kappa", C.c_double), ("newton_iters", C.c_int), ("lag_extrap", C.c_int),
+                ("newton_tol", C.c_double)]
 
 
 _lib = None
@@ -94,7 +95,7 @@ def lib():
         L.orc_get_lambdaU.argtypes = [vp, C.c_int]
         L.orc_local_solve.restype = C.c_double
         L.orc_local_solve.argtypes = [C.POINTER(Params), C.c_double, C.c_double, C.c_double,
-                                      C.c_double, C.c_double, C.c_int]
+                                      C.c_double, C.c_double, C.c_int, _I]
         for nm in ("orc_theta", "orc_dtheta", "orc_Krel", "orc_feddes", "orc_dfeddes"):
             f = getattr(L, nm)
             f.restype = C.c_double
@@ -264,9 +265,12 @@ def law_fns(law):
             lambda x: L.orc_dfeddes(C.byref(P), float(x)))
 
 
-def local_solve(law, a, beta, c, f, x0, iters):
+def local_solve(law, a, beta, c, f, x0, iters, evals=False):
+    """The pointwise solve; with evals=True also the number of F evaluations."""
     P = make_params(law)
-    return lib().orc_local_solve(C.byref(P), a, beta, c, f, x0, iters)
+    n = C.c_int(0)
+    x = lib().orc_local_solve(C.byref(P), a, beta, c, f, x0, iters, C.byref(n))
+    return (x, n.value) if evals else x
 
 
 def run_steps(w, steps=None, ordering=ORDER_RB, max_cycles=60, tol=0.0, stagnation=True):

@@ -89,6 +89,7 @@ typedef struct {
     double kappa;
     int newton_iters;
     int lag_extrap;
+    double newton_tol;  /* stop once a Newton step moves x by <= newton_tol |x| (0: never early) */
 } orc_params;
 
 typedef struct {
@@ -462,8 +463,8 @@ static void compute_lambdaU(orc_solver *S, orc_level *lv)
 
 /* Scalar solve of a theta(x) + beta a_F(x) + c x = f (eq. point-update with
  * the BDF coefficient a, the sink S = beta * a_F and c = xi + kappa_i + m_ii).
- * The paper asks for "a few (damped) Newton steps with optional
- * backtracking"; reading: exactly `iters` Newton steps from x0, each kept
+ * The paper leaves the number of (damped) Newton steps open, backtracking
+ * optional; reading: at most `iters` Newton steps from x0, each kept
  * inside a bracket [lo, hi] that holds the root (initially
  * [(f - a theta_s - beta)/c, (f - a theta_r)/c], widened by 1e-12 of the sum
  * of the ends' magnitudes so that a root on an end -- a saturated cell, where
@@ -472,9 +473,15 @@ static void compute_lambdaU(orc_solver *S, orc_level *lv)
  * or a non-positive F', is replaced by bisection, except a step that leaves
  * the iterate unchanged (below rounding resolution), which is kept so that a
  * converged cell stays put.  Landing on a bracket end is rejected because a
- * previous iterate sits there, which would allow a two-cycle.  No early exit. */
+ * previous iterate sits there, which would allow a two-cycle.  The iteration
+ * ends early after a Newton step (not a bisection) that moved x by at most
+ * newton_tol |x_new|: near the root Newton converges quadratically, so the
+ * steps left out would have moved x by about (F''/2F') times that step
+ * squared, below rounding for newton_tol = 1e-10.  A step of zero always ends
+ * it (a fixed iterate stays fixed).  *evals (nullable) receives the number of
+ * evaluations of F taken. */
 double orc_local_solve(const orc_params *p, double a, double beta, double c, double f,
-                       double x0, int iters)
+                       double x0, int iters, int *evals)
 {
     double lo, hi;
     if (p->model == ORC_MODEL_LINEAR) {
@@ -488,7 +495,9 @@ double orc_local_solve(const orc_params *p, double a, double beta, double c, dou
         hi += pad;
     }
     double x = x0;
-    for (int k = 0; k < iters; k++) {
+    int k = 0;
+    while (k < iters) {
+        k++;
         double F = a * orc_theta(p, x) + c * x - f;
         double dF = a * orc_dtheta(p, x) + c;
         if (p->sink == ORC_SINK_FEDDES_EXP) {
@@ -504,9 +513,13 @@ double orc_local_solve(const orc_params *p, double a, double beta, double c, dou
             hi = x;
         }
         double xn = x - F / dF;
-        if (!(dF > 0.0) || (xn != x && !(xn > lo && xn < hi))) xn = 0.5 * (lo + hi);
+        int bisect = !(dF > 0.0) || (xn != x && !(xn > lo && xn < hi));
+        if (bisect) xn = 0.5 * (lo + hi);
+        int small = !bisect && fabs(xn - x) <= p->newton_tol * fabs(xn);
         x = xn;
+        if (small) break;
     }
+    if (evals) *evals = k;
     return x;
 }
 
@@ -526,7 +539,7 @@ static void point_update(orc_solver *S, orc_level *lv, int i, const int ii[3])
     f += kap * lv->psi[i];
     double c = S->p.xi + kap + mii;
     double beta = root_beta(S, elev(S, lv, ii));
-    lv->psi[i] = orc_local_solve(&S->p, S->a, beta, c, f, lv->psi[i], S->p.newton_iters);
+    lv->psi[i] = orc_local_solve(&S->p, S->a, beta, c, f, lv->psi[i], S->p.newton_iters, NULL);
 }
 
 /* One NGS sweep on level l in the solver's ordering. */
@@ -579,7 +592,7 @@ void orc_update_points(orc_solver *S, int l, int npts, const int *idx, double *o
         f += kap * lv->psi[i];
         double c = S->p.xi + kap + mii;
         double beta = root_beta(S, elev(S, lv, ii));
-        out[q] = orc_local_solve(&S->p, S->a, beta, c, f, lv->psi[i], S->p.newton_iters);
+        out[q] = orc_local_solve(&S->p, S->a, beta, c, f, lv->psi[i], S->p.newton_iters, NULL);
     }
 }
 

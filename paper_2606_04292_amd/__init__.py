@@ -57,7 +57,8 @@ class Constitutive(C.Structure):
                 ("root_len", C.c_double), ("h1", C.c_double), ("h2", C.c_double),
                 ("h3", C.c_double), ("h4", C.c_double), ("xi", C.c_double),
                 ("kappa_rule", C.c_int), ("kappa", C.c_double), ("newton_iters", C.c_int),
-                ("lag_extrap", C.c_int), ("Ks_field", C.POINTER(C.c_double))]
+                ("lag_extrap", C.c_int), ("newton_tol", C.c_double),
+                ("Ks_field", C.POINTER(C.c_double))]
 
 
 class SolveOpts(C.Structure):

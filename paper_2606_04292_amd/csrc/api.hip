@@ -297,6 +297,7 @@ Law make_law(const rs_constitutive *c)
     L.kappa_rule = c->kappa_rule;
     L.kappa = c->kappa;
     L.newton = c->newton_iters;
+    L.newton_tol = c->newton_tol;
     return L;
 }
 
@@ -330,6 +331,8 @@ int validate_law(const rs_constitutive *c)
         return fail(RS_EINVAL, "kappa must be >= 0");
     if (c->newton_iters < 1 || c->newton_iters > 64)
         return fail(RS_EINVAL, "newton_iters must be in 1..64");
+    if (!(c->newton_tol >= 0.0 && c->newton_tol <= 1e-3))
+        return fail(RS_EINVAL, "newton_tol must be in 0..1e-3");
     return RS_OK;
 }
 

@@ -40,6 +40,16 @@ __device__ __forceinline__ unsigned xcd_block(unsigned per)
     return (blockIdx.x % 8u) * per + blockIdx.x / 8u;
 }
 
+// The same, with each XCD walking its slab from the far end when reverse is
+// set: a pass that follows another in the opposite direction starts on the
+// lines the previous one touched last, which are still in the memory-side
+// cache.
+__device__ __forceinline__ unsigned xcd_block_dir(unsigned per, bool reverse)
+{
+    const unsigned pos = blockIdx.x / 8u;
+    return (blockIdx.x % 8u) * per + (reverse ? per - 1u - pos : pos);
+}
+
 inline unsigned xcd_grid(unsigned long long blocks) { return (unsigned)((blocks + 7) / 8 * 8); }
 
 // Packed enumeration of the cells of one colour: rows (fixed j, k) of

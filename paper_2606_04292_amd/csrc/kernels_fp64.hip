@@ -315,7 +315,7 @@ __global__ __launch_bounds__(256) void k_sweep(Geo g, Law L, Step st, const doub
                                                double *psi, int colour, ColourMap cm)
 {
     const unsigned long long t =
-        (unsigned long long)xcd_block(gridDim.x / 8u) * blockDim.x + threadIdx.x;
+        (unsigned long long)xcd_block_dir(gridDim.x / 8u, colour & 1) * blockDim.x + threadIdx.x;
     if (t >= cm.total) return;
     const unsigned row = udiv((unsigned)t, cm.dH);
     const unsigned ih = (unsigned)(t - (unsigned long long)row * cm.H);

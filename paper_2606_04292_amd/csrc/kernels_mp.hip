@@ -24,7 +24,7 @@ __global__ __launch_bounds__(256) void k_sweep32(Geo g, Law32 L, float a, const 
                                                  ColourMap cm)
 {
     const unsigned long long t =
-        (unsigned long long)xcd_block(gridDim.x / 8u) * blockDim.x + threadIdx.x;
+        (unsigned long long)xcd_block_dir(gridDim.x / 8u, colour & 1) * blockDim.x + threadIdx.x;
     if (t >= cm.total) return;
     const unsigned row = udiv((unsigned)t, cm.dH);
     const unsigned ih = (unsigned)(t - (unsigned long long)row * cm.H);
@@ -202,6 +202,10 @@ Law32 make_law32(const Law &L)
     f.kappa = (float)L.kappa;
     f.kappa_rule = L.kappa_rule;
     f.newton = L.newton;
+    // The correction solve feeds FP64 defect correction, which only needs it to
+    // a few digits: whenever the FP64 solve may stop early, the FP32 one stops
+    // after a step of 1e-5 |d| (the steps it leaves out are ~1e-10 |d|).
+    f.newton_tol = L.newton_tol > 0.0 ? 1e-5f : 0.0f;
     return f;
 }
 

@@ -49,6 +49,7 @@ struct Law {
     int kappa_rule;
     double kappa;
     int newton;
+    double newton_tol;   // a Newton step of at most newton_tol |x| ends the pointwise solve
 };
 
 // Step coefficients (by value).

@@ -216,7 +216,9 @@ __device__ __forceinline__ void feddes(const Law &L, double x, double &a, double
 // root of a saturated cell -- the lower end, F being linear there -- lies
 // strictly inside; narrowed by the sign of F at each iterate); a step that does
 // not land strictly inside, or a non-positive F', becomes a bisection, unless
-// the step leaves the iterate unchanged.
+// the step leaves the iterate unchanged.  A Newton step (not a bisection) that
+// moves x by at most L.newton_tol |x_new| ends the solve for that cell: the
+// steps left out would move it by about that step squared times F''/2F'.
 template <int MODEL, bool SINK, int NEWTON>
 __device__ __forceinline__ double local_solve_t(const Law &L, double a, double beta, double c,
                                                 double f, double x0)
@@ -234,6 +236,7 @@ __device__ __forceinline__ double local_solve_t(const Law &L, double a, double b
         hi += pad;
     }
     double x = x0;
+    bool done = false;
     const int iters = NEWTON > 0 ? NEWTON : L.newton;
     for (int k = 0; k < iters; ++k) {
         ThetaEval t = theta_t<MODEL>(L, x);
@@ -254,13 +257,14 @@ __device__ __forceinline__ double local_solve_t(const Law &L, double a, double b
             hi = x;
         }
         double xn = x - F * rcp_1nr(dF);
-        bool bisect = !(dF > 0.0) || (xn != x && !(xn > lo && xn < hi));
-        const double xo = x;
-        x = bisect ? 0.5 * (lo + hi) : xn;
-        // An iterate that did not move stays put in every later iteration (same
-        // F, F', no bisection): once no lane of the wave moved, the remaining
-        // iterations are skipped with identical results.
-        if (!__any(x != xo)) break;
+        const bool bisect = !(dF > 0.0) || (xn != x && !(xn > lo && xn < hi));
+        if (bisect) xn = 0.5 * (lo + hi);
+        const bool small = !bisect && fabs(xn - x) <= L.newton_tol * fabs(xn);
+        // lanes whose solve has ended keep their value while the rest of the
+        // wave iterates; the wave leaves once every lane has ended
+        if (!done) x = xn;
+        done = done || small;
+        if (__all(done)) break;
     }
     return x;
 }

@@ -71,6 +71,7 @@ struct Law32 {
     float xi, kappa;
     int kappa_rule;
     int newton;
+    float newton_tol;   // a Newton step of at most newton_tol |d| ends the correction solve
 };
 
 // Base-state quantities of one node (evaluated once per update).
@@ -214,7 +215,8 @@ __device__ __forceinline__ float feddes_value32(const Law32 &L, float x)
 
 // Scalar correction update: a dtheta(d) + beta da(d) + c d = f by the same
 // safeguarded Newton iteration as the FP64 smoother (bracket from the room
-// theta has to move and the sink range, widened by 1e-6 of its ends).
+// theta has to move and the sink range, widened by 1e-6 of its ends), ending
+// after a Newton step of at most newton_tol |d|.
 template <int MODEL, bool SINK>
 __device__ __forceinline__ float local_solve32(const Law32 &L, float a, float beta, float c,
                                                float f, const Base &b, float d0)
@@ -236,6 +238,7 @@ __device__ __forceinline__ float local_solve32(const Law32 &L, float a, float be
         hi += pad;
     }
     float d = d0;
+    bool done = false;
     for (int k = 0; k < L.newton; ++k) {
         float dth, slope;
         dtheta32<MODEL>(L, b, d, dth, slope);
@@ -250,13 +253,13 @@ __device__ __forceinline__ float local_solve32(const Law32 &L, float a, float be
         if (F > 0.0f) hi = fminf(hi, d);
         else if (F < 0.0f) lo = fmaxf(lo, d);
         else { lo = d; hi = d; }
-        const float dn = d - F * f_rcp(dF);
+        float dn = d - F * f_rcp(dF);
         const bool bisect = !(dF > 0.0f) || (dn != d && !(dn > lo && dn < hi));
-        const float dold = d;
-        d = bisect ? 0.5f * (lo + hi) : dn;
-        // a fixed iterate stays fixed in every later iteration: once no lane of
-        // the wave moved, the remaining iterations change nothing
-        if (!__any(d != dold)) break;
+        if (bisect) dn = 0.5f * (lo + hi);
+        const bool small = !bisect && fabsf(dn - d) <= L.newton_tol * fabsf(dn);
+        if (!done) d = dn;
+        done = done || small;
+        if (__all(done)) break;
     }
     return d;
 }

@@ -101,8 +101,9 @@ class LawSpec:
     xi: float = 0.0
     kappa_rule: int = KAPPA_REL
     kappa: float = 0.1
-    newton_iters: int = 3
+    newton_iters: int = 3             # pointwise Newton steps at most
     lag_extrap: int = 0               # BDF2 lag: 0 psi^n, 1 2 psi^n - psi^{n-1}
+    newton_tol: float = 1e-10         # ... ending after a Newton step <= newton_tol |psi|
 
 
 @dataclasses.dataclass

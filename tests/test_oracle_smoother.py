@@ -78,6 +78,43 @@ def test_local_solve_keeps_a_converged_cell(orc, k):
         assert abs(x3 - x) <= 4 * np.spacing(abs(x))
 
 
+@pytest.mark.parametrize("k", range(len(LAWS)))
+def test_early_newton_stop_changes_the_solve_only_at_rounding(orc, k):
+    """The early stop after a Newton step of at most newton_tol |x| (the
+    reading of the open Newton step count): from starts at every distance from the
+    root, the result equals that of all the steps to within rounding (the
+    steps left out are quadratically small), converged starts take one
+    evaluation, and far starts still reach the bisection root."""
+    law = LAWS[k]
+    exact = dataclasses.replace(law, newton_tol=0.0)
+    th, dth, _, fa, dfa = orc.law_fns(law)
+    stopped = 0
+    for _ in range(200):
+        a = 10 ** RNG.uniform(-4, -1)
+        c = 10 ** RNG.uniform(-9, -2)
+        beta = 1e-6 * RNG.uniform(0, 1) if law.sink else 0.0
+        target = -10 ** RNG.uniform(-2, 0.5)
+        f = a * th(target) + c * target + beta * fa(target)
+        x0 = target * (1.0 + 10 ** RNG.uniform(-14, -1) * RNG.choice([-1.0, 1.0]))
+        for iters in (3, 6):
+            x, n = orc.local_solve(law, a, beta, c, f, x0, iters, evals=True)
+            xe, ne = orc.local_solve(exact, a, beta, c, f, x0, iters, evals=True)
+            # rounding floor of the root: F's rounding error over F'
+            noise = 8 * np.finfo(float).eps * (a * th(xe) + c * abs(xe) + abs(f)) / (
+                a * dth(xe) + c + beta * dfa(xe))
+            assert abs(x - xe) <= 1e-14 * abs(xe) + noise
+            assert n <= ne <= iters
+            stopped += n < ne
+        x, n = orc.local_solve(law, a, beta, c, f, target, 3, evals=True)
+        xr, nr = orc.local_solve(law, a, beta, c, f, x, 3, evals=True)
+        floor = 8 * np.finfo(float).eps * (a * th(x) + c * abs(x) + abs(f)) / (
+            a * dth(x) + c + beta * dfa(x))
+        assert nr == 1 and abs(xr - x) <= 4 * np.spacing(abs(x)) + floor
+        far, nf = orc.local_solve(law, a, beta, c, f, -2.5, 60, evals=True)
+        assert nf < 60 and abs(far - target) <= 1e-12 * max(1.0, abs(target))
+    assert stopped > 100
+
+
 def linear_setup(orc, dim, n, ordering, rule=W.KAPPA_REL):
     bcs = [W.BC_NOFLUX] * (2 * dim)
     bcs[2 * (dim - 1)] = W.BC_DIRICHLET
