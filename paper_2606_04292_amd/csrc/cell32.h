@@ -73,23 +73,25 @@ __device__ __forceinline__ float apply_Nd(const Geo &g, const Law32 &L, float a,
                                           const double *beta, const float *K, const float *pb,
                                           const float *dl, int i, int j, int k, long long idx)
 {
+    const Stencil<DIM> st = stencil<DIM>(g, i, j, k, idx);
     const float x = dl[idx];
     const float Ki = K[idx];
-    const Base b = base_of<MODEL>(L, pb[idx]);
+    const float p = pb[idx];
+    float Kn[2 * DIM], dn[2 * DIM];
+#pragma unroll
+    for (int q = 0; q < 2 * DIM; ++q) {
+        Kn[q] = K[st.jn[q]];
+        dn[q] = dl[st.jn[q]];
+    }
+    const float bz = SINK ? (float)beta[vert_index<DIM>(i, j, k)] : 0.0f;
+    const Base b = base_of<MODEL>(L, p);
     float dth, slope;
     dtheta32<MODEL>(L, b, x, dth, slope);
     float s = a * dth;
     if (SINK) {
         float da, ds;
         dfeddes32(L, b.psi, x, da, ds);
-        s += (float)beta[vert_index<DIM>(i, j, k)] * da;
-    }
-    const Stencil<DIM> st = stencil<DIM>(g, i, j, k, idx);
-    float Kn[2 * DIM], dn[2 * DIM];
-#pragma unroll
-    for (int q = 0; q < 2 * DIM; ++q) {
-        Kn[q] = K[st.jn[q]];
-        dn[q] = dl[st.jn[q]];
+        s += bz * da;
     }
     float md = 0.0f;
 #pragma unroll

@@ -64,26 +64,29 @@ __device__ __forceinline__ double g_at(const Geo &g, const Law &L, const Step &s
 }
 
 // N(psi)_i = a theta(psi_i) + beta a_F(psi_i) + xi psi_i + (M psi)_i
+// (the whole stencil is loaded before the law is evaluated, so that the loads
+// overlap the theta chain instead of following it).
 template <int MODEL, bool SINK, int DIM>
 __device__ __forceinline__ double apply_N_t(const Geo &g, const Law &L, double a,
                                             const double *beta, const double *K,
                                             const double *psi, int i, int j, int k, long long idx)
 {
+    const Stencil<DIM> st = stencil<DIM>(g, i, j, k, idx);
     const double x = psi[idx];
     const double Ki = K[idx];
-    double s = a * theta_only_t<MODEL>(L, x);
-    if (SINK) {
-        double fa, dfa;
-        feddes(L, x, fa, dfa);
-        const int vk = (DIM == 1) ? i : (DIM == 2 ? j : k);
-        s += beta[vk] * fa;
-    }
-    const Stencil<DIM> st = stencil<DIM>(g, i, j, k, idx);
     double Kn[2 * DIM], pn[2 * DIM];
 #pragma unroll
     for (int q = 0; q < 2 * DIM; ++q) {
         Kn[q] = K[st.jn[q]];
         pn[q] = psi[st.jn[q]];
+    }
+    double bz = 0.0;
+    if (SINK) bz = beta[(DIM == 1) ? i : (DIM == 2 ? j : k)];
+    double s = a * theta_only_t<MODEL>(L, x);
+    if (SINK) {
+        double fa, dfa;
+        feddes(L, x, fa, dfa);
+        s += bz * fa;
     }
     double mpsi = 0.0;
 #pragma unroll

@@ -28,25 +28,6 @@ __device__ __forceinline__ double sink_beta(const Law &L, const double *beta, co
 }
 
 // N(psi)_i = a theta(psi_i) + beta a_F(psi_i) + xi psi_i + (M psi)_i  (eq. Nh-def)
-__device__ __forceinline__ double apply_N(const Geo &g, const Law &L, const Step &st,
-                                          const double *beta, const double *K, const double *psi,
-                                          const int c[3], long long idx)
-{
-    double x = psi[idx];
-    double Ki = K[idx];
-    double s = st.a * theta_only(L, x);
-    if (L.sink == kSinkFeddes) {
-        double fa, dfa;
-        feddes(L, x, fa, dfa);
-        s += beta[c[g.vert]] * fa;
-    }
-    double mpsi = 0.0;
-    for_each_nb(g, c, idx, [&](long long j, double cf, int, int) {
-        mpsi += cf * (Ki + K[j]) * (x - psi[j]);
-    });
-    return s + (L.xi * x + mpsi);
-}
-
 __global__ void k_fill_u64(unsigned long long *p, int n, unsigned long long v)
 {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -454,7 +435,8 @@ __global__ __launch_bounds__(512) void k_vcycle_tail(const TailArgs *A, int top,
 // Defect d = g - N(psi) and its max-norm (step 2 of the FAS algorithm)
 // ---------------------------------------------------------------------------
 
-// Grid-stride over the nodes; one block maximum and one atomic per block.
+// One node per thread (work-groups numbered per XCD); the block maximum goes
+// to the running maximum.
 template <int MODEL, bool SINK, int DIM>
 __global__ __launch_bounds__(256) void k_residual(Geo g, Law L, Step st, const double *beta,
                                                   const double *K, const double *gv,
@@ -462,32 +444,26 @@ __global__ __launch_bounds__(256) void k_residual(Geo g, Law L, Step st, const d
                                                   unsigned long long *norm_bits, NodeMap nm)
 {
     double v = 0.0;
-    const unsigned long long N = (unsigned long long)g.N;
-    // each group walks a contiguous chunk of nodes (XCD-aware numbering)
-    const unsigned long long chunk =
-        ((N + gridDim.x - 1) / gridDim.x + blockDim.x - 1) / blockDim.x * blockDim.x;
-    const unsigned long long t0 = (unsigned long long)xcd_block(gridDim.x / 8u) * chunk;
-    const unsigned long long t1 = t0 + chunk < N ? t0 + chunk : N;
-    for (unsigned long long t = t0 + threadIdx.x; t < t1; t += blockDim.x) {
-        const unsigned row = udiv((unsigned)t, nm.d0);
-        const int i = (int)(t - (unsigned long long)row * nm.n0);
-        int j = 0, k = 0;
-        if (DIM == 3) {
-            k = (int)udiv(row, nm.d1);
-            j = (int)row - k * (int)nm.n1;
-        } else if (DIM == 2) {
-            j = (int)row;
-        }
+    const unsigned long long t =
+        (unsigned long long)xcd_block(gridDim.x / 8u) * blockDim.x + threadIdx.x;
+    if (t < (unsigned long long)g.N) {
+        int i, j, k;
+        node_ijk(nm, t, i, j, k);
         double r = 0.0;
         if (!dirichlet_at(g, i, j, k, nullptr))
             r = gv[t] - apply_N_t<MODEL, SINK, DIM>(g, L, st.a, beta, K, psi, i, j, k, (long long)t);
         if (d) d[t] = r;
-        const double ar = fabs(r);
-        v = (ar > v || ar != ar) ? ar : v;
+        v = fabs(r);
     }
     if (norm_bits) {
         v = block_max(v);
-        if (threadIdx.x == 0) atomicMax(norm_bits, (unsigned long long)__double_as_longlong(v));
+        if (threadIdx.x == 0) {
+            // the bits of non-negative doubles (and NaN) order like their values;
+            // most groups do not raise the running max and skip the atomic
+            const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
+            if (bits > __hip_atomic_load(norm_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                atomicMax(norm_bits, bits);
+        }
     }
 }
 
@@ -496,20 +472,20 @@ __global__ __launch_bounds__(256) void k_residual(Geo g, Law L, Step st, const d
 // ---------------------------------------------------------------------------
 
 // g_H = N_H(psibar_H) + d_H (g_H holds d_H on entry), psi_H = psibar_H.
+template <int MODEL, bool SINK, int DIM>
 __global__ __launch_bounds__(256) void k_coarse_rhs(Geo g, Law L, Step st, const double *beta,
                                                     const double *K, const double *psibar,
-                                                    double *gv, double *psi)
+                                                    double *gv, double *psi, NodeMap nm)
 {
-    int i = blockIdx.x * kBX + threadIdx.x;
-    int j = blockIdx.y * kBY + threadIdx.y;
-    int k = blockIdx.z;
-    if (i >= g.n[0] || j >= g.n[1]) return;
-    long long idx = i + (long long)j * g.stride[1] + (long long)k * g.stride[2];
-    if (!dirichlet_at(g, i, j, k, nullptr)) {
-        int c[3] = {i, j, k};
-        gv[idx] = apply_N(g, L, st, beta, K, psibar, c, idx) + gv[idx];
-    }
-    psi[idx] = psibar[idx];
+    const unsigned long long t =
+        (unsigned long long)xcd_block(gridDim.x / 8u) * blockDim.x + threadIdx.x;
+    if (t >= (unsigned long long)g.N) return;
+    int i, j, k;
+    node_ijk(nm, t, i, j, k);
+    if (!dirichlet_at(g, i, j, k, nullptr))
+        gv[t] = apply_N_t<MODEL, SINK, DIM>(g, L, st.a, beta, K, psibar, i, j, k, (long long)t) +
+                gv[t];
+    psi[t] = psibar[t];
 }
 
 // Root density of the Feddes-exponential sink on every level:
@@ -666,14 +642,25 @@ struct SweepLaunch {
     }
 };
 
+struct CoarseRhsLaunch {
+    const Geo &g; const Law &law; const Step &st; const double *beta; const double *K;
+    const double *psibar; double *gvec; double *psi; hipStream_t s;
+    template <int M, bool S, int D>
+    void go()
+    {
+        hipLaunchKernelGGL((k_coarse_rhs<M, S, D>),
+                           dim3(xcd_grid(((unsigned long long)g.N + 255) / 256)), dim3(256), 0, s,
+                           g, law, st, beta, K, psibar, gvec, psi, node_map(g));
+    }
+};
+
 struct ResidualLaunch {
     const Geo &g; const Law &law; const Step &st; const double *beta; const double *K;
     const double *gvec; const double *psi; double *d; unsigned long long *norm_bits; hipStream_t s;
     template <int M, bool S, int D>
     void go()
     {
-        unsigned long long blocks = ((unsigned long long)g.N + 255) / 256;
-        if (blocks > 2048) blocks = 2048;
+        const unsigned long long blocks = ((unsigned long long)g.N + 255) / 256;
         hipLaunchKernelGGL((k_residual<M, S, D>), dim3(xcd_grid(blocks)), dim3(256), 0, s, g,
                            law, st, beta, K, gvec, psi, d, norm_bits, node_map(g));
     }
@@ -711,8 +698,7 @@ void launch_coarse_rhs(const Geo &gc, const Law &law, const Step &st, const doub
                        const double *K, const double *psibar, double *gvec, double *psi,
                        hipStream_t s)
 {
-    hipLaunchKernelGGL(k_coarse_rhs, node_grid(gc), dim3(kBX, kBY), 0, s, gc, law, st, beta, K,
-                       psibar, gvec, psi);
+    dispatch(law, gc.dim, CoarseRhsLaunch{gc, law, st, beta, K, psibar, gvec, psi, s});
 }
 
 void launch_prolong(const Geo &gf, const Geo &gc, const double *psi_c, const double *psibar_c,

@@ -68,13 +68,15 @@ __global__ __launch_bounds__(256) void k_sweep32_small(Geo g, Law32 L, float a, 
 template <int MODEL, bool SINK, int DIM>
 __global__ __launch_bounds__(256) void k_residual32(Geo g, Law32 L, float a, const double *beta,
                                                     const float *K, const float *rhs,
-                                                    const float *pb, const float *dl, float *r)
+                                                    const float *pb, const float *dl, float *r,
+                                                    NodeMap nm)
 {
-    int i = blockIdx.x * kBX + threadIdx.x;
-    int j = blockIdx.y * kBY + threadIdx.y;
-    int k = blockIdx.z;
-    if (i >= g.n[0] || j >= g.n[1]) return;
-    long long idx = i + (long long)j * g.stride[1] + (long long)k * g.stride[2];
+    const unsigned long long t =
+        (unsigned long long)xcd_block(gridDim.x / 8u) * blockDim.x + threadIdx.x;
+    if (t >= (unsigned long long)g.N) return;
+    int i, j, k;
+    node_ijk(nm, t, i, j, k);
+    const long long idx = (long long)t;
     float v = 0.0f;
     if (!dirichlet_at(g, i, j, k, nullptr))
         v = rhs[idx] - apply_Nd<MODEL, SINK, DIM>(g, L, a, beta, K, pb, dl, i, j, k, idx);
@@ -86,13 +88,15 @@ __global__ __launch_bounds__(256) void k_residual32(Geo g, Law32 L, float a, con
 template <int MODEL, bool SINK, int DIM>
 __global__ __launch_bounds__(256) void k_coarse_rhs32(Geo g, Law32 L, float a, const double *beta,
                                                       const float *K, const float *pb,
-                                                      const float *dbar, float *rhs, float *dl)
+                                                      const float *dbar, float *rhs, float *dl,
+                                                      NodeMap nm)
 {
-    int i = blockIdx.x * kBX + threadIdx.x;
-    int j = blockIdx.y * kBY + threadIdx.y;
-    int k = blockIdx.z;
-    if (i >= g.n[0] || j >= g.n[1]) return;
-    long long idx = i + (long long)j * g.stride[1] + (long long)k * g.stride[2];
+    const unsigned long long t =
+        (unsigned long long)xcd_block(gridDim.x / 8u) * blockDim.x + threadIdx.x;
+    if (t >= (unsigned long long)g.N) return;
+    int i, j, k;
+    node_ijk(nm, t, i, j, k);
+    const long long idx = (long long)t;
     if (!dirichlet_at(g, i, j, k, nullptr))
         rhs[idx] = apply_Nd<MODEL, SINK, DIM>(g, L, a, beta, K, pb, dbar, i, j, k, idx) + rhs[idx];
     dl[idx] = dbar[idx];
@@ -152,8 +156,8 @@ struct Residual32Launch {
     template <int M, bool S, int D>
     void go()
     {
-        hipLaunchKernelGGL((k_residual32<M, S, D>), node_grid(g), dim3(kBX, kBY), 0, s, g, law, a,
-                           beta, K, rhs, pb, dl, r);
+        hipLaunchKernelGGL((k_residual32<M, S, D>), dim3(xcd_grid(((unsigned long long)g.N + 255) / 256)),
+                           dim3(256), 0, s, g, law, a, beta, K, rhs, pb, dl, r, node_map(g));
     }
 };
 
@@ -163,8 +167,9 @@ struct CoarseRhs32Launch {
     template <int M, bool S, int D>
     void go()
     {
-        hipLaunchKernelGGL((k_coarse_rhs32<M, S, D>), node_grid(g), dim3(kBX, kBY), 0, s, g, law, a,
-                           beta, K, pb, dbar, rhs, dl);
+        hipLaunchKernelGGL((k_coarse_rhs32<M, S, D>),
+                           dim3(xcd_grid(((unsigned long long)g.N + 255) / 256)), dim3(256), 0, s,
+                           g, law, a, beta, K, pb, dbar, rhs, dl, node_map(g));
     }
 };
 

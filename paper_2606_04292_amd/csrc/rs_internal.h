@@ -64,7 +64,7 @@ struct Step {
 // Small levels in one work-group: per-level records of a grid, kept in its
 // workspace (written at creation, lambdaU refreshed at step set-up).
 // ---------------------------------------------------------------------------
-constexpr long long kTailNodes = 8192;   // levels of at most this many nodes
+constexpr long long kTailNodes = 2049;   // levels of at most this many nodes
 
 struct TailLevel {
     Geo g;
