@@ -49,7 +49,7 @@ class Params(C.Structure):
                 ("h1", C.c_double), ("h2", C.c_double), ("h3", C.c_double),
                 ("h4", C.c_double), ("xi", C.c_double), ("kappa_rule", C.c_int),
                 ("kappa", C.c_double), ("newton_iters", C.c_int), ("lag_extrap", C.c_int),
-                ("newton_tol", C.c_double)]
+                ("newton_tol", C.c_double), ("gd_alpha", C.c_double)]
 
 
 _lib = None
@@ -93,6 +93,8 @@ def lib():
         L.orc_set_a.argtypes = [vp, C.c_double]
         L.orc_get_lambdaU.restype = C.c_double
         L.orc_get_lambdaU.argtypes = [vp, C.c_int]
+        L.orc_set_soils.restype = C.c_int
+        L.orc_set_soils.argtypes = [vp, C.c_int, C.POINTER(Params), C.c_void_p]
         L.orc_local_solve.restype = C.c_double
         L.orc_local_solve.argtypes = [C.POINTER(Params), C.c_double, C.c_double, C.c_double,
                                       C.c_double, C.c_double, C.c_int, _I]
@@ -155,6 +157,11 @@ class Solver:
             n = (C.c_int * 3)()
             lib().orc_level_shape(self.h, l, n)
             self.shapes.append(tuple(reversed([n[a] for a in range(w.grid.dim)])))
+        if w.soils:
+            table = (Params * len(w.soils))(*[make_params(s) for s in w.soils])
+            ids = np.ascontiguousarray(w.soil_id, dtype=np.uint8)
+            if lib().orc_set_soils(self.h, len(w.soils), table, ids.ctypes.data_as(C.c_void_p)) != 0:
+                raise ValueError("bad soil table or soil index")
         self.set_state(w.psi0)
 
     def __del__(self):

@@ -8,7 +8,9 @@
  * Everything is written as the paper states it, in the paper's order, with no
  * blocking or fusion:
  *   - constitutive laws: Table "tab:models" (Haverkamp, van Genuchten-Mualem
- *     with l = 1/2), psi >= 0 treated as saturated;
+ *     with l = 1/2, Gardner), psi >= 0 treated as saturated; optionally a law
+ *     per node from a table of soils (the layered and two-layer cases of
+ *     section 4);
  *   - space: the conservative second-order finite-difference operator of
  *     eq. (discrete-strong) with arithmetic face averages of K, on a
  *     vertex-centred grid (2^k+1 nodes per axis);
@@ -44,6 +46,9 @@
 #define ORC_MODEL_VGM 1
 #define ORC_MODEL_HAVERKAMP 2
 #define ORC_MODEL_LINEAR 3
+#define ORC_MODEL_GARDNER 4
+
+#define ORC_MAXSOIL 16
 
 #define ORC_SINK_NONE 0
 #define ORC_SINK_FEDDES_EXP 1
@@ -90,6 +95,7 @@ typedef struct {
     int newton_iters;
     int lag_extrap;
     double newton_tol;  /* stop once a Newton step moves x by <= newton_tol |x| (0: never early) */
+    double gd_alpha;    /* Gardner exponent (per law unit of psi) */
 } orc_params;
 
 typedef struct {
@@ -99,6 +105,7 @@ typedef struct {
     int patch_lo[2], patch_hi[2];
     double *psi, *Kstar, *g, *psibar, *d;
     double lambdaU;    /* max row sum of U on this level (kappa rule REMARK) */
+    unsigned char *sid; /* soil of each node (NULL: one law everywhere) */
 } orc_level;
 
 typedef struct {
@@ -114,6 +121,8 @@ typedef struct {
     double dt, a;      /* current step size and BDF leading coefficient */
     int order_eff;
     double beta_norm;  /* normalising integral of the root density */
+    int nsoil;         /* soils of the per-node table (0: the law in p everywhere) */
+    orc_params soil[ORC_MAXSOIL];
 } orc_solver;
 
 /* ------------------------------------------------------------------------ */
@@ -122,13 +131,16 @@ typedef struct {
 
 /* Water content theta(psi).  Haverkamp: theta_r + alpha (theta_s - theta_r) /
  * (alpha + |psi|^beta); vGM: theta_r + (theta_s - theta_r) (1 + (alpha |psi|)^n)^-m,
- * m = 1 - 1/n.  For psi >= 0 the soil is saturated, theta = theta_s. */
+ * m = 1 - 1/n; Gardner: theta_r + (theta_s - theta_r) e^(alpha psi).  For
+ * psi >= 0 the soil is saturated, theta = theta_s. */
 double orc_theta(const orc_params *p, double psi)
 {
     if (p->model == ORC_MODEL_LINEAR)
         return p->theta_r + p->lin_c * psi;
     if (psi >= 0.0)
         return p->theta_s;
+    if (p->model == ORC_MODEL_GARDNER)
+        return p->theta_r + (p->theta_s - p->theta_r) * exp(p->gd_alpha * p->psi_unit * psi);
     if (p->model == ORC_MODEL_HAVERKAMP) {
         double hu = fabs(p->psi_unit * psi);
         return p->theta_r + p->hk_alpha * (p->theta_s - p->theta_r) /
@@ -148,6 +160,10 @@ double orc_dtheta(const orc_params *p, double psi)
         return p->lin_c;
     if (psi >= 0.0)
         return 0.0;
+    if (p->model == ORC_MODEL_GARDNER) {
+        double au = p->gd_alpha * p->psi_unit;
+        return (p->theta_s - p->theta_r) * au * exp(au * psi);
+    }
     if (p->model == ORC_MODEL_HAVERKAMP) {
         /* d/dpsi of alpha dT / (alpha + (u|psi|)^beta), u = psi_unit */
         double hu = fabs(p->psi_unit * psi);
@@ -167,13 +183,15 @@ double orc_dtheta(const orc_params *p, double psi)
 }
 
 /* Relative conductivity K(psi)/Ks.  Haverkamp: A / (A + |psi|^gamma);
- * vGM (Mualem, l = 1/2): Se^(1/2) [1 - (1 - Se^(1/m))^m]^2. */
+ * vGM (Mualem, l = 1/2): Se^(1/2) [1 - (1 - Se^(1/m))^m]^2; Gardner: e^(alpha psi). */
 double orc_Krel(const orc_params *p, double psi)
 {
     if (p->model == ORC_MODEL_LINEAR)
         return 1.0;
     if (psi >= 0.0)
         return 1.0;
+    if (p->model == ORC_MODEL_GARDNER)
+        return exp(p->gd_alpha * p->psi_unit * psi);
     if (p->model == ORC_MODEL_HAVERKAMP) {
         double hu = fabs(p->psi_unit * psi);
         return p->hk_A / (p->hk_A + pow(hu, p->hk_gamma));
@@ -307,6 +325,13 @@ static double root_beta(const orc_solver *S, double z)
     return S->p.Tp * exp(-(S->grid.L[v] - z) / S->p.root_len) / S->beta_norm;
 }
 
+/* The soil law of node i of a level: its entry of the soil table (layered
+ * media, section 4), else the one law of the problem. */
+static const orc_params *law_at(const orc_solver *S, const orc_level *lv, int i)
+{
+    return lv->sid ? &S->soil[lv->sid[i]] : &S->p;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Operator M(psi*) (eq. discrete-strong and the matrix M of section 2).      */
 /* ------------------------------------------------------------------------ */
@@ -372,7 +397,8 @@ static double Mpsi(const orc_solver *S, const orc_level *lv, const double *psi, 
 static double Nop(const orc_solver *S, const orc_level *lv, const double *psi, int i, const int ii[3])
 {
     double x = psi[i];
-    double s = S->a * orc_theta(&S->p, x);
+    const orc_params *law = law_at(S, lv, i);
+    double s = S->a * orc_theta(law, x);
     if (S->p.sink == ORC_SINK_FEDDES_EXP)
         s += root_beta(S, elev(S, lv, ii)) * orc_feddes(&S->p, x);
     s += S->p.xi * x + Mpsi(S, lv, psi, i, ii);
@@ -539,7 +565,8 @@ static void point_update(orc_solver *S, orc_level *lv, int i, const int ii[3])
     f += kap * lv->psi[i];
     double c = S->p.xi + kap + mii;
     double beta = root_beta(S, elev(S, lv, ii));
-    lv->psi[i] = orc_local_solve(&S->p, S->a, beta, c, f, lv->psi[i], S->p.newton_iters, NULL);
+    lv->psi[i] = orc_local_solve(law_at(S, lv, i), S->a, beta, c, f, lv->psi[i],
+                                 S->p.newton_iters, NULL);
 }
 
 /* One NGS sweep on level l in the solver's ordering. */
@@ -592,7 +619,8 @@ void orc_update_points(orc_solver *S, int l, int npts, const int *idx, double *o
         f += kap * lv->psi[i];
         double c = S->p.xi + kap + mii;
         double beta = root_beta(S, elev(S, lv, ii));
-        out[q] = orc_local_solve(&S->p, S->a, beta, c, f, lv->psi[i], S->p.newton_iters, NULL);
+        out[q] = orc_local_solve(law_at(S, lv, i), S->a, beta, c, f, lv->psi[i],
+                                 S->p.newton_iters, NULL);
     }
 }
 
@@ -819,8 +847,9 @@ void orc_begin_step(orc_solver *S, double dt, int order)
             psistar[i] = (S->order_eff == 2 && S->p.lag_extrap) ? 2.0 * S->psi_n[i] - S->psi_nm1[i] : S->psi_n[i];
             f0->psi[i] = S->psi_n[i];
         }
-        double ks = S->Ks_field ? S->Ks_field[i] : S->p.Ks;
-        f0->Kstar[i] = ks * orc_Krel(&S->p, psistar[i]);
+        const orc_params *law = law_at(S, f0, i);
+        double ks = S->Ks_field ? S->Ks_field[i] : law->Ks;
+        f0->Kstar[i] = ks * orc_Krel(law, psistar[i]);
     }
     int v = S->grid.dim - 1;
 #pragma omp parallel for schedule(static)
@@ -828,11 +857,12 @@ void orc_begin_step(orc_solver *S, double dt, int order)
         int ii[3];
         coords(f0, i, ii);
         if (is_dirichlet(S, f0, ii, NULL)) { f0->g[i] = 0.0; continue; }
+        const orc_params *law = law_at(S, f0, i);
         double H;
         if (S->order_eff == 1)
-            H = orc_theta(&S->p, S->psi_n[i]) / dt;
+            H = orc_theta(law, S->psi_n[i]) / dt;
         else
-            H = (4.0 * orc_theta(&S->p, S->psi_n[i]) - orc_theta(&S->p, S->psi_nm1[i])) / (2.0 * dt);
+            H = (4.0 * orc_theta(law, S->psi_n[i]) - orc_theta(law, S->psi_nm1[i])) / (2.0 * dt);
         double gi = H + S->p.xi * psistar[i] - Mz(S, f0, i, ii);
         if (ii[v] == 0 && S->grid.face_bc[2 * v] == ORC_BC_FREEDRAIN)
             gi -= f0->Kstar[i] / (wfrac(f0, ii, v) * f0->h[v]);
@@ -945,12 +975,61 @@ orc_solver *orc_create(const orc_grid *g, const orc_params *p, const double *Ks_
     return S;
 }
 
+/* Per-node soils (the layered and two-layer media of section 4): table
+ * entries supply the soil law (model, theta_s, theta_r, Ks and the model's
+ * parameters); everything else (sink, xi, kappa, Newton settings) stays that
+ * of the problem.  ids holds one table index per fine node.  Reading: a
+ * coarse node takes the soil of the fine node it coincides with (injection,
+ * as for K*).  Returns 0, or -1 for a bad table or index, or when a per-node
+ * Ks field is set (a soil's Ks comes from its entry). */
+int orc_set_soils(orc_solver *S, int n, const orc_params *table, const unsigned char *ids)
+{
+    if (n < 1 || n > ORC_MAXSOIL || S->Ks_field) return -1;
+    orc_level *f0 = &S->lev[0];
+    for (int i = 0; i < f0->N; i++)
+        if (ids[i] >= n) return -1;
+    S->nsoil = n;
+    for (int s = 0; s < n; s++) {
+        orc_params q = S->p;
+        q.model = table[s].model;
+        q.theta_s = table[s].theta_s;
+        q.theta_r = table[s].theta_r;
+        q.Ks = table[s].Ks;
+        q.vg_alpha = table[s].vg_alpha;
+        q.vg_n = table[s].vg_n;
+        q.hk_alpha = table[s].hk_alpha;
+        q.hk_beta = table[s].hk_beta;
+        q.hk_A = table[s].hk_A;
+        q.hk_gamma = table[s].hk_gamma;
+        q.psi_unit = table[s].psi_unit;
+        q.lin_c = table[s].lin_c;
+        q.gd_alpha = table[s].gd_alpha;
+        S->soil[s] = q;
+    }
+    for (int k = 0; k < S->nlev; k++) {
+        orc_level *lv = &S->lev[k];
+        if (!lv->sid) lv->sid = (unsigned char *)malloc((size_t)lv->N);
+        if (k == 0) {
+            memcpy(lv->sid, ids, (size_t)lv->N);
+            continue;
+        }
+        orc_level *fl = &S->lev[k - 1];
+        for (int I = 0; I < lv->N; I++) {
+            int II[3];
+            coords(lv, I, II);
+            int jj[3] = {2 * II[0], 2 * II[1], 2 * II[2]};
+            lv->sid[I] = fl->sid[index_of(fl, jj)];
+        }
+    }
+    return 0;
+}
+
 void orc_destroy(orc_solver *S)
 {
     if (!S) return;
     for (int k = 0; k < S->nlev; k++) {
         free(S->lev[k].psi); free(S->lev[k].Kstar); free(S->lev[k].g);
-        free(S->lev[k].psibar); free(S->lev[k].d);
+        free(S->lev[k].psibar); free(S->lev[k].d); free(S->lev[k].sid);
     }
     free(S->psi_n); free(S->psi_nm1); free(S->Ks_field);
     free(S);

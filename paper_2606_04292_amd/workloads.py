@@ -35,6 +35,7 @@ BC_FREEDRAIN = 3
 MODEL_VGM = 1         # van Genuchten - Mualem (l = 0.5)
 MODEL_HAVERKAMP = 2   # Haverkamp et al.
 MODEL_LINEAR = 3      # test-only law: theta affine in psi, K constant
+MODEL_GARDNER = 4     # Gardner: theta and K exponential in psi
 
 SINK_NONE = 0
 SINK_FEDDES_EXP = 1   # Feddes-type a(psi) times an exponential root density
@@ -104,6 +105,7 @@ class LawSpec:
     newton_iters: int = 3             # pointwise Newton steps at most
     lag_extrap: int = 0               # BDF2 lag: 0 psi^n, 1 2 psi^n - psi^{n-1}
     newton_tol: float = 1e-10         # ... ending after a Newton step <= newton_tol |psi|
+    gd_alpha: float = 0.0             # MODEL_GARDNER exponent (per law unit of psi)
 
 
 @dataclasses.dataclass
@@ -119,6 +121,11 @@ class Workload:
     nu1: int = 2
     nu2: int = 2
     nu_coarse: int = 32
+    # layered media: per-node soil index into soils (uint8, grid.shape); each
+    # soil supplies the law's model, theta_s, theta_r, Ks and model parameters,
+    # law supplies everything else
+    soils: Optional[List[LawSpec]] = None
+    soil_id: Optional[np.ndarray] = None
 
 
 def _coords(grid: GridSpec):
@@ -245,6 +252,58 @@ def celia_column(n: int = 2049) -> Workload:
                   xi=0.0, kappa_rule=KAPPA_CONST, kappa=0.1)
     return Workload("celia_column%d" % n, g, law, np.full(n, -61.5), dt=0.1, steps=3600,
                     order=1, nu1=5, nu2=5)
+
+
+# Soils of the layered 1-D column of section 4.1: the Haverkamp soil of the
+# Celia benchmark and the Gardner and van Genuchten-Mualem soils the paper
+# matches to it (alpha_G, n*, alpha_VG* as printed there; Ks, theta_s and
+# theta_r shared; psi in cm).
+CELIA_GARDNER_ALPHA = 0.01877      # 1/cm
+CELIA_VG_N = 3.349
+CELIA_VG_ALPHA = 0.03165           # 1/cm
+
+
+def celia_soils() -> List[LawSpec]:
+    """[Gardner, Haverkamp, vGM] soils of the layered column (section 4.1)."""
+    common = dict(theta_s=0.287, theta_r=0.075, Ks=0.00944, psi_unit=1.0, xi=0.0,
+                  kappa_rule=KAPPA_CONST, kappa=0.1)
+    return [LawSpec(model=MODEL_GARDNER, gd_alpha=CELIA_GARDNER_ALPHA, **common),
+            LawSpec(model=MODEL_HAVERKAMP, hk_alpha=1.611e6, hk_beta=3.96, hk_A=1.175e6,
+                    hk_gamma=4.74, **common),
+            LawSpec(model=MODEL_VGM, vg_alpha=CELIA_VG_ALPHA, vg_n=CELIA_VG_N, **common)]
+
+
+def celia_composite(n: int = 2049) -> Workload:
+    """The layered column of section 4.1: the Celia set-up with the composite
+    law, Gardner for 30 <= z < 40 cm, Haverkamp for 20 <= z < 30 cm and vGM
+    elsewhere (the printed half-open zones; the top node z = 40 falls in the
+    vGM zone)."""
+    w = celia_column(n)
+    z = elevation(w.grid)
+    sid = np.where((z >= 30.0) & (z < 40.0), 0, np.where((z >= 20.0) & (z < 30.0), 1, 2))
+    soils = celia_soils()
+    return dataclasses.replace(w, name="celia_composite%d" % n, law=soils[1], soils=soils,
+                               soil_id=sid.astype(np.uint8))
+
+
+def two_layer_vg(n: int = 257, steps: int = 100) -> Workload:
+    """The two-layer infiltration of section 4.2: (0,100)^2 cm, vGM soils above
+    and below the interface zeta(x) = 100 (0.1 (1 - cos(pi x / 100)) + 0.45)
+    (parameters in cm and h), psi0 = -z, psi = 0 on top and bottom, no flux on
+    the sides, Lambda_kappa = 0.1 I, xi = 0, tau = 0.01 h, FMG(10, 10) starts.
+    The paper gives no end time; `steps` sets it."""
+    g = GridSpec(dim=2, n=[n, n], L=[100.0, 100.0],
+                 face_bc=[BC_NOFLUX, BC_NOFLUX, BC_DIRICHLET, BC_DIRICHLET],
+                 face_value=[0.0, 0.0, 0.0, 0.0])
+    common = dict(model=MODEL_VGM, psi_unit=1.0, xi=0.0, kappa_rule=KAPPA_CONST, kappa=0.1)
+    upper = LawSpec(theta_s=0.50, theta_r=0.120, vg_alpha=0.025, vg_n=3.00, Ks=0.25, **common)
+    lower = LawSpec(theta_s=0.46, theta_r=0.034, vg_alpha=0.016, vg_n=1.37, Ks=2.00, **common)
+    x, z = _coords(g)
+    zeta = 100.0 * (0.1 * (1.0 - np.cos(np.pi * x / 100.0)) + 0.45)
+    sid = np.broadcast_to(np.where(z >= zeta, 0, 1), g.shape).astype(np.uint8)
+    psi0 = -elevation(g)
+    return Workload("two_layer_vg%d" % n, g, upper, psi0, dt=0.01, steps=steps, order=1,
+                    nu1=10, nu2=10, soils=[upper, lower], soil_id=np.ascontiguousarray(sid))
 
 
 def serving_requests(count: int = 4096, seed_path=(1,)) -> List[Workload]:

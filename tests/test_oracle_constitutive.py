@@ -144,3 +144,33 @@ def test_feddes_piecewise_shape(orc):
     # A2: non-negative slope on [psi_start, psi_opt] = [h4, h2)
     for x in np.linspace(-80.0, -0.2500001, 50):
         assert da(x) >= 0.0
+
+
+def test_gardner_law_closed_forms_and_printed_matching(orc):
+    """Table tab:models, Gardner: theta_r + dT e^(alpha psi) and Ks e^(alpha psi)
+    below saturation.  With the printed alpha_G = 0.01877 /cm, theta passes the
+    Haverkamp midpoint at the printed 36.94 cm (to the printed digits) and WRC
+    and HCF share that half suction; theta' against a Richardson difference."""
+    soil = W.celia_soils()[0]
+    assert soil.gd_alpha == GOLD["printed"]["alpha_G_per_cm"]
+    th, dth, Kr, _, _ = orc.law_fns(soil)
+    dT = soil.theta_s - soil.theta_r
+    h_half = math.log(2.0) / soil.gd_alpha
+    assert abs(h_half - GOLD["printed"]["h_half_theta_cm"]) <= 0.02
+    assert th(-h_half) == pytest.approx(soil.theta_r + 0.5 * dT, rel=1e-15)
+    assert Kr(-h_half) == pytest.approx(0.5, rel=1e-15)
+    for psi in (-0.5, -12.0, -61.5, -400.0):
+        e = math.exp(soil.gd_alpha * psi)
+        assert th(psi) == pytest.approx(soil.theta_r + dT * e, rel=1e-15)
+        assert Kr(psi) == pytest.approx(e, rel=1e-15)
+        h = 1e-3 * abs(psi)
+        d1 = (th(psi + h) - th(psi - h)) / (2 * h)
+        d2 = (th(psi + h / 2) - th(psi - h / 2)) / h
+        assert dth(psi) == pytest.approx((4 * d2 - d1) / 3, rel=1e-6)
+        assert dth(psi) > 0.0
+    assert th(0.0) == soil.theta_s and dth(0.0) == 0.0 and Kr(0.0) == 1.0 and Kr(5.0) == 1.0
+    # psi_unit scales psi before the law, as for Haverkamp
+    m = dataclasses.replace(soil, psi_unit=100.0, gd_alpha=soil.gd_alpha)
+    thm, _, Krm, _, _ = orc.law_fns(m)
+    assert thm(-0.3) == pytest.approx(th(-30.0), rel=1e-15)
+    assert Krm(-0.3) == pytest.approx(Kr(-30.0), rel=1e-15)
