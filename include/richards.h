@@ -61,6 +61,8 @@ extern "C" {
 #define RS_VGM 1          /* van Genuchten - Mualem, m = 1 - 1/n, l = 1/2 */
 #define RS_HAVERKAMP 2    /* Haverkamp et al. */
 #define RS_LINEAR 3       /* theta = theta_r + lin_c psi, K = Ks (testing) */
+#define RS_GARDNER 4      /* Gardner: theta_r + (theta_s - theta_r) e^(alpha psi), K = Ks e^(alpha psi) */
+#define RS_MAX_SOILS 16
 
 #define RS_SINK_NONE 0
 #define RS_SINK_FEDDES_EXP 1  /* S = beta(z) a(psi): Feddes stress factor,
@@ -105,7 +107,28 @@ typedef struct rs_grid_desc {
  * 2 psi^n - psi^{n-1} instead of psi^n.  newton_tol: the pointwise solve
  * (eq. point-update) takes at most newton_iters safeguarded Newton steps and
  * ends after a Newton step that moved psi by at most newton_tol |psi| (0: only
- * a zero step ends it early; 1e-10 leaves out steps below rounding); 0..1e-3. */
+ * a zero step ends it early; 1e-10 leaves out steps below rounding); 0..1e-3.
+ * gd_alpha: the Gardner exponent (per law unit of psi, psi_unit applies).
+ *
+ * Layered media (section 4: the composite column of 4.1, the two-layer
+ * medium of 4.2): n_soils > 0 gives every fine node its own soil law,
+ * soils[soil_id[node]]; each rs_soil supplies the law (model, theta_s,
+ * theta_r, Ks and the model's parameters) and every other field of this
+ * struct (sink, xi, kappa, Newton settings) stays shared.  Coarse nodes take
+ * the soil of the fine node they coincide with.  soils and soil_id are HOST
+ * pointers copied by the call; soil_id has one entry per fine node, each
+ * < n_soils <= RS_MAX_SOILS.  The scalar law fields above are then unused.
+ * Layered media and the Gardner law run on RS_FP64 grids only (RS_EINVAL
+ * on RS_MIXED grids and in the serving engine); Ks_field must be null. */
+typedef struct rs_soil {
+    int model;            /* RS_VGM, RS_HAVERKAMP, RS_GARDNER or RS_LINEAR */
+    double theta_s, theta_r, Ks;
+    double vg_alpha, vg_n;
+    double hk_alpha, hk_beta, hk_A, hk_gamma, psi_unit;
+    double lin_c;
+    double gd_alpha;
+} rs_soil;
+
 typedef struct rs_constitutive {
     size_t struct_size;   /* sizeof(rs_constitutive) */
     int model;
@@ -122,6 +145,10 @@ typedef struct rs_constitutive {
     int lag_extrap;
     double newton_tol;
     const double *Ks_field;
+    double gd_alpha;
+    int n_soils;                  /* 0: the law above everywhere */
+    const rs_soil *soils;         /* HOST, n_soils entries */
+    const unsigned char *soil_id; /* HOST, one per fine node */
 } rs_constitutive;
 
 /* V-cycle parameters (nu_1, nu_2, nu_H of section 3.2) and stopping test

@@ -48,6 +48,14 @@ class GridDesc(C.Structure):
                 ("patch_value", C.c_double)]
 
 
+class Soil(C.Structure):
+    _fields_ = [("model", C.c_int), ("theta_s", C.c_double), ("theta_r", C.c_double),
+                ("Ks", C.c_double), ("vg_alpha", C.c_double), ("vg_n", C.c_double),
+                ("hk_alpha", C.c_double), ("hk_beta", C.c_double), ("hk_A", C.c_double),
+                ("hk_gamma", C.c_double), ("psi_unit", C.c_double), ("lin_c", C.c_double),
+                ("gd_alpha", C.c_double)]
+
+
 class Constitutive(C.Structure):
     _fields_ = [("struct_size", C.c_size_t), ("model", C.c_int), ("theta_s", C.c_double),
                 ("theta_r", C.c_double), ("Ks", C.c_double), ("vg_alpha", C.c_double),
@@ -58,7 +66,8 @@ class Constitutive(C.Structure):
                 ("h3", C.c_double), ("h4", C.c_double), ("xi", C.c_double),
                 ("kappa_rule", C.c_int), ("kappa", C.c_double), ("newton_iters", C.c_int),
                 ("lag_extrap", C.c_int), ("newton_tol", C.c_double),
-                ("Ks_field", C.POINTER(C.c_double))]
+                ("Ks_field", C.POINTER(C.c_double)), ("gd_alpha", C.c_double),
+                ("n_soils", C.c_int), ("soils", C.POINTER(Soil)), ("soil_id", C.c_void_p)]
 
 
 class SolveOpts(C.Structure):
@@ -135,17 +144,31 @@ def grid_desc(g: "workloads.GridSpec") -> GridDesc:
     return d
 
 
-def constitutive(law: "workloads.LawSpec", ks_field=None):
+def constitutive(law: "workloads.LawSpec", ks_field=None, soils=None, soil_id=None):
+    """Marshal a law (and optionally a per-node Ks field, or a soil table with
+    one soil index per node) into rs_constitutive; returns it with the arrays
+    it points to, which the caller keeps alive for the call."""
     c = Constitutive()
     c.struct_size = C.sizeof(Constitutive)
     for name, _ in Constitutive._fields_:
-        if name in ("struct_size", "Ks_field"):
+        if name in ("struct_size", "Ks_field", "n_soils", "soils", "soil_id"):
             continue
         setattr(c, name, getattr(law, name))
-    keep = None
+    keep = []
     if ks_field is not None:
-        keep = np.ascontiguousarray(ks_field, dtype=np.float64)
-        c.Ks_field = keep.ctypes.data_as(C.POINTER(C.c_double))
+        ks = np.ascontiguousarray(ks_field, dtype=np.float64)
+        c.Ks_field = ks.ctypes.data_as(C.POINTER(C.c_double))
+        keep.append(ks)
+    if soils:
+        tab = (Soil * len(soils))()
+        for s, spec in enumerate(soils):
+            for name, _ in Soil._fields_:
+                setattr(tab[s], name, getattr(spec, name))
+        ids = np.ascontiguousarray(soil_id, dtype=np.uint8)
+        c.n_soils = len(soils)
+        c.soils = tab
+        c.soil_id = ids.ctypes.data
+        keep += [tab, ids]
     return c, keep
 
 
@@ -198,7 +221,7 @@ class Grid:
             n = (C.c_int * 3)()
             check(lib().rs_level_shape(h, l, n))
             self.shapes.append(tuple(reversed([n[a] for a in range(w.grid.dim)])))
-        c, keep = constitutive(w.law, w.Ks_field)
+        c, keep = constitutive(w.law, w.Ks_field, w.soils, w.soil_id)
         check(lib().rs_set_constitutive(h, C.byref(c)))
         del keep
         self.set_state(torch.as_tensor(np.ascontiguousarray(w.psi0), device=self.device))

@@ -141,7 +141,8 @@ struct Layout {
     size_t lev_off[kMaxLevels][6];   // psi, K, g, d, psibar, psi_alt (fused levels)
     size_t mp_off[kMaxLevels][6];    // RS_MIXED: delta, K32, rhs, r, dbar, psi_b (FP32)
     size_t beta_off[kMaxLevels];
-    size_t psi_n, psi_nm1, ks, scratch, tail;
+    size_t soil_off[kMaxLevels];     // soil index per node (layered media)
+    size_t psi_n, psi_nm1, ks, scratch, tail, soil_tab;
     size_t total;
 };
 
@@ -164,6 +165,8 @@ void plan(const rs_grid_desc *d, int precision, Layout *L)
         }
         L->beta_off[l] = off;
         off = align_up(off + sizeof(double) * (size_t)g.n[g.vert]);
+        L->soil_off[l] = off;
+        off = align_up(off + (size_t)g.N);
         for (int a = 0; a < 6; ++a) {
             L->mp_off[l][a] = 0;
             if (precision == RS_MIXED) {
@@ -178,6 +181,7 @@ void plan(const rs_grid_desc *d, int precision, Layout *L)
     L->ks = off;      off = align_up(off + sizeof(double) * N0);
     L->scratch = off; off = align_up(off + sizeof(unsigned long long) * kScratchWords);
     L->tail = off;    off = align_up(off + sizeof(TailArgs));
+    L->soil_tab = off; off = align_up(off + sizeof(Law) * kMaxSoils);
     L->total = off;
 }
 
@@ -246,6 +250,7 @@ struct rs_grid {
     bool has_ks;
     unsigned long long *scratch;
     unsigned long long *host_bits;   // pinned readback
+    Law *soil_tab;                    // device table of per-soil laws (layered media)
     TailArgs *tail_dev;               // per-level records of the one-work-group cycle
     TailArgs *tail_host;              // pinned copy
     int tail_top;                     // first level run by it (nlev: none)
@@ -298,7 +303,35 @@ Law make_law(const rs_constitutive *c)
     L.kappa = c->kappa;
     L.newton = c->newton_iters;
     L.newton_tol = c->newton_tol;
+    L.gd_alpha = c->gd_alpha;
+    L.soils = nullptr;
+    if (c->n_soils > 0) L.model = kMulti;   // the table is attached by the grid
     return L;
+}
+
+// The constitutive record of one soil of a layered medium: the soil's law
+// fields over the shared ones.
+rs_constitutive soil_constitutive(const rs_constitutive *c, const rs_soil &s)
+{
+    rs_constitutive q = *c;
+    q.model = s.model;
+    q.theta_s = s.theta_s;
+    q.theta_r = s.theta_r;
+    q.Ks = s.Ks;
+    q.vg_alpha = s.vg_alpha;
+    q.vg_n = s.vg_n;
+    q.hk_alpha = s.hk_alpha;
+    q.hk_beta = s.hk_beta;
+    q.hk_A = s.hk_A;
+    q.hk_gamma = s.hk_gamma;
+    q.psi_unit = s.psi_unit;
+    q.lin_c = s.lin_c;
+    q.gd_alpha = s.gd_alpha;
+    q.Ks_field = nullptr;
+    q.n_soils = 0;
+    q.soils = nullptr;
+    q.soil_id = nullptr;
+    return q;
 }
 
 int validate_law(const rs_constitutive *c)
@@ -307,8 +340,23 @@ int validate_law(const rs_constitutive *c)
     if (c->struct_size != sizeof(rs_constitutive))
         return fail(RS_EINVAL, "rs_constitutive.struct_size %zu != %zu", c->struct_size,
                     sizeof(rs_constitutive));
-    if (c->model != RS_VGM && c->model != RS_HAVERKAMP && c->model != RS_LINEAR)
+    if (c->n_soils != 0) {
+        if (c->n_soils < 0 || c->n_soils > RS_MAX_SOILS)
+            return fail(RS_EINVAL, "n_soils must be in 0..%d", RS_MAX_SOILS);
+        if (!c->soils || !c->soil_id) return fail(RS_EINVAL, "layered medium needs soils and soil_id");
+        if (c->Ks_field) return fail(RS_EINVAL, "a layered medium takes Ks from its soils");
+        for (int s = 0; s < c->n_soils; ++s) {
+            rs_constitutive q = soil_constitutive(c, c->soils[s]);
+            int e = validate_law(&q);
+            if (e) return e;
+        }
+        return RS_OK;
+    }
+    if (c->model != RS_VGM && c->model != RS_HAVERKAMP && c->model != RS_LINEAR &&
+        c->model != RS_GARDNER)
         return fail(RS_EINVAL, "unknown model %d", c->model);
+    if (c->model == RS_GARDNER && !(c->gd_alpha > 0.0))
+        return fail(RS_EINVAL, "Gardner needs alpha > 0");
     if (c->model != RS_LINEAR && !(c->theta_s > c->theta_r && c->theta_r >= 0.0))
         return fail(RS_EINVAL, "need theta_s > theta_r >= 0");
     if (!(c->Ks > 0.0) && !c->Ks_field) return fail(RS_EINVAL, "Ks must be positive");
@@ -567,6 +615,7 @@ int rs_create_grid(const rs_grid_desc *d, int precision, void *ws_dev, size_t ws
     for (int l = 0; l < L.nlev; ++l) {
         LevelData &v = G->lev[l];
         v.geo = make_geo(d, l);
+        v.geo.soil = (const unsigned char *)(base + L.soil_off[l]);
         v.psi = (double *)(base + L.lev_off[l][0]);
         v.K = (double *)(base + L.lev_off[l][1]);
         v.g = (double *)(base + L.lev_off[l][2]);
@@ -584,6 +633,7 @@ int rs_create_grid(const rs_grid_desc *d, int precision, void *ws_dev, size_t ws
     G->psi_nm1 = (double *)(base + L.psi_nm1);
     G->ks = (double *)(base + L.ks);
     G->scratch = (unsigned long long *)(base + L.scratch);
+    G->soil_tab = (Law *)(base + L.soil_tab);
     G->has_ks = false;
     G->law_set = false;
     G->in_step = false;
@@ -665,7 +715,30 @@ int rs_set_constitutive(rs_grid *G, const rs_constitutive *c)
     if (!G) return fail(RS_EINVAL, "null grid");
     int e = validate_law(c);
     if (e) return e;
+    if (G->precision == RS_MIXED && (c->n_soils > 0 || c->model == RS_GARDNER))
+        return fail(RS_EINVAL, "layered media and the Gardner law need an RS_FP64 grid");
+    if (c->n_soils > 0) {
+        const long long N = G->lev[0].geo.N;
+        for (long long i = 0; i < N; ++i)
+            if (c->soil_id[i] >= c->n_soils)
+                return fail(RS_EINVAL, "soil_id[%lld] = %d >= n_soils", i, (int)c->soil_id[i]);
+        std::vector<Law> tab((size_t)c->n_soils);
+        for (int s = 0; s < c->n_soils; ++s) {
+            rs_constitutive q = soil_constitutive(c, c->soils[s]);
+            tab[(size_t)s] = make_law(&q);
+        }
+        HIPCALL(hipMemcpyAsync(G->soil_tab, tab.data(), sizeof(Law) * tab.size(),
+                               hipMemcpyHostToDevice, G->stream));
+        HIPCALL(hipMemcpyAsync((void *)G->lev[0].geo.soil, c->soil_id, (size_t)N,
+                               hipMemcpyHostToDevice, G->stream));
+        for (int l = 1; l < G->nlev; ++l)
+            launch_inject_u8(G->lev[l].geo, G->lev[l - 1].geo, G->lev[l - 1].geo.soil,
+                             (unsigned char *)G->lev[l].geo.soil, G->stream);
+        HIPCALL(hipGetLastError());
+        HIPCALL(hipStreamSynchronize(G->stream));   // the host table and ids are the caller's
+    }
     G->law = make_law(c);
+    if (c->n_soils > 0) G->law.soils = G->soil_tab;
     G->law32 = make_law32(G->law);
     G->step.lag_extrap = c->lag_extrap ? 1 : 0;
     if (c->Ks_field) {

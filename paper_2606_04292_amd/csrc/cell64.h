@@ -27,6 +27,11 @@ __device__ __forceinline__ double kstar_at(const Geo &g, const Law &L, const Ste
         ps = (st.order == 2 && st.lag_extrap) ? 2.0 * pn - psi_nm1[idx] : pn;
         *psi0 = pn;
     }
+    if (L.soils) {
+        // layered media: the node's own soil, with that soil's Ks
+        const Law &Ls = L.soils[g.soil[idx]];
+        return Ls.Ks * krel(Ls, ps);
+    }
     return ks * krel(L, ps);
 }
 
@@ -40,14 +45,14 @@ __device__ __forceinline__ double g_at(const Geo &g, const Law &L, const Step &s
     int c[3] = {i, j, k};
     double pn = psi_n[idx];
     double H, ps;
-    if (st.order == 1) {
-        H = theta_only(L, pn) / st.dt;
-        ps = pn;
-    } else {
-        double pm = psi_nm1[idx];
-        H = (4.0 * theta_only(L, pn) - theta_only(L, pm)) / (2.0 * st.dt);
-        ps = st.lag_extrap ? 2.0 * pn - pm : pn;
-    }
+    const double pm = st.order == 1 ? pn : psi_nm1[idx];
+    // history term with the node's soil (layered media) or the one law
+    auto history = [&](const Law &Lt) {
+        return st.order == 1 ? theta_only(Lt, pn) / st.dt
+                             : (4.0 * theta_only(Lt, pn) - theta_only(Lt, pm)) / (2.0 * st.dt);
+    };
+    H = L.soils ? history(L.soils[g.soil[idx]]) : history(L);
+    ps = (st.order == 2 && st.lag_extrap) ? 2.0 * pn - pm : pn;
     // gravity (M z)_i: only faces along the vertical axis, z_i - z_j = -side h
     double Ki = K[idx];
     double mz = 0.0;
@@ -82,7 +87,9 @@ __device__ __forceinline__ double apply_N_t(const Geo &g, const Law &L, double a
     }
     double bz = 0.0;
     if (SINK) bz = beta[(DIM == 1) ? i : (DIM == 2 ? j : k)];
-    double s = a * theta_only_t<MODEL>(L, x);
+    double s;
+    if constexpr (MODEL == kMulti) s = a * theta_only(L.soils[g.soil[idx]], x);
+    else s = a * theta_only_t<MODEL>(L, x);
     if (SINK) {
         double fa, dfa;
         feddes(L, x, fa, dfa);

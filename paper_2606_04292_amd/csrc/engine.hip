@@ -1012,6 +1012,8 @@ int rs_engine_submit(rs_engine *E, const rs_grid_desc *d, const rs_constitutive 
     int e = validate_law(c);
     if (e) return e;
     if (c->sink != RS_SINK_NONE) return fail(RS_EINVAL, "the engine serves requests without a sink");
+    if (c->n_soils > 0 || c->model == RS_GARDNER)
+        return fail(RS_EINVAL, "the engine serves the vGM, Haverkamp and linear laws, one per request");
     if (c->kappa_rule == RS_KAPPA_REMARK)
         return fail(RS_EINVAL, "the engine serves kappa rules CONST and REL");
     if (c->Ks_field) return fail(RS_EINVAL, "the engine serves uniform Ks");

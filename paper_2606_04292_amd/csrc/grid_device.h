@@ -180,7 +180,8 @@ inline dim3 node_grid(const Geo &g)
 
 
 // Call fn.template operator()<MODEL, SINK, DIM>() for the law and level.
-template <typename Fn>
+// EXT: also the Gardner law and per-node soils (FP64 kernels only).
+template <bool EXT = false, typename Fn>
 inline void dispatch(const Law &law, int dim, Fn &&fn)
 {
     const bool s = law.sink == kSinkFeddes;
@@ -190,6 +191,16 @@ inline void dispatch(const Law &law, int dim, Fn &&fn)
         else if (dim == 2) fn.template go<M, S, 2>();   \
         else fn.template go<M, S, 3>();                 \
     } while (0)
+    if constexpr (EXT) {
+        if (law.model == kGardner) {
+            if (s) RS_DIMS(kGardner, true); else RS_DIMS(kGardner, false);
+            return;
+        }
+        if (law.model == kMulti) {
+            if (s) RS_DIMS(kMulti, true); else RS_DIMS(kMulti, false);
+            return;
+        }
+    }
     if (law.model == kHaverkamp) {
         if (s) RS_DIMS(kHaverkamp, true); else RS_DIMS(kHaverkamp, false);
     } else if (law.model == kVgm) {

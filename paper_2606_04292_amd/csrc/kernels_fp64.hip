@@ -133,6 +133,11 @@ __device__ __forceinline__ double ngs_value(const Geo &g, const Law &L, double a
     const double cc = L.xi + kap + mii;
     const int vk = (DIM == 1) ? i : (DIM == 2 ? j : k);
     const double b = SINK ? beta[vk] : 0.0;
+    if constexpr (MODEL == kMulti) {
+        const Law &Ls = L.soils[g.soil[idx]];
+        if (L.newton == 3) return local_solve_soil<SINK, 3>(Ls, a, b, cc, f, x0);
+        return local_solve_soil<SINK, 0>(Ls, a, b, cc, f, x0);
+    }
     if (L.newton == 3) return local_solve_t<MODEL, SINK, 3>(L, a, b, cc, f, x0);
     return local_solve_t<MODEL, SINK, 0>(L, a, b, cc, f, x0);
 }
@@ -182,8 +187,14 @@ __device__ __forceinline__ void ngs_cell(const Geo &g, const Law &L, double a, c
     const double cc = L.xi + kap + mii;
     const int vk = (DIM == 1) ? i : (DIM == 2 ? j : k);
     const double b = SINK ? beta[vk] : 0.0;
-    psi[idx] = (L.newton == 3) ? local_solve_t<MODEL, SINK, 3>(L, a, b, cc, f, x0)
-                               : local_solve_t<MODEL, SINK, 0>(L, a, b, cc, f, x0);
+    if constexpr (MODEL == kMulti) {
+        const Law &Ls = L.soils[g.soil[idx]];
+        psi[idx] = (L.newton == 3) ? local_solve_soil<SINK, 3>(Ls, a, b, cc, f, x0)
+                                   : local_solve_soil<SINK, 0>(Ls, a, b, cc, f, x0);
+    } else {
+        psi[idx] = (L.newton == 3) ? local_solve_t<MODEL, SINK, 3>(L, a, b, cc, f, x0)
+                                   : local_solve_t<MODEL, SINK, 0>(L, a, b, cc, f, x0);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -563,6 +574,13 @@ void launch_setup_g(const Geo &g, const Law &law, const Step &st, const double *
                        K, gvec);
 }
 
+void launch_inject_u8(const Geo &gc, const Geo &gf, const unsigned char *vf, unsigned char *vc,
+                      hipStream_t s)
+{
+    hipLaunchKernelGGL((k_inject_t<unsigned char>), node_grid(gc), dim3(kBX, kBY), 0, s, gc, gf,
+                       vf, vc);
+}
+
 void launch_inject(const Geo &gc, const Geo &gf, const double *Kf, double *Kc, hipStream_t s)
 {
     hipLaunchKernelGGL(k_inject, node_grid(gc), dim3(kBX, kBY), 0, s, gc, gf, Kf, Kc);
@@ -671,7 +689,7 @@ int launch_sweep_rb(const Geo &g, const Law &law, const Step &st, const double *
                     double **psi_alt, int nsweeps, hipStream_t s)
 {
     if (nsweeps <= 0) return 0;
-    dispatch(law, g.dim, SweepLaunch{g, law, st, beta, lambdaU, K, gvec, psi, psi_alt, nsweeps, s});
+    dispatch<true>(law, g.dim, SweepLaunch{g, law, st, beta, lambdaU, K, gvec, psi, psi_alt, nsweeps, s});
     if (g.N <= 1024) return 1;
     return (g.dim == 3 && psi_alt && *psi_alt && fused_enabled()) ? nsweeps : 2 * nsweeps;
 }
@@ -685,7 +703,7 @@ void launch_residual(const Geo &g, const Law &law, const Step &st, const double 
                      const double *K, const double *gvec, const double *psi, double *d,
                      unsigned long long *norm_bits, hipStream_t s)
 {
-    dispatch(law, g.dim, ResidualLaunch{g, law, st, beta, K, gvec, psi, d, norm_bits, s});
+    dispatch<true>(law, g.dim, ResidualLaunch{g, law, st, beta, K, gvec, psi, d, norm_bits, s});
 }
 
 void launch_restrict(const Geo &gc, const Geo &gf, const double *psi_f, const double *d_f,
@@ -698,7 +716,7 @@ void launch_coarse_rhs(const Geo &gc, const Law &law, const Step &st, const doub
                        const double *K, const double *psibar, double *gvec, double *psi,
                        hipStream_t s)
 {
-    dispatch(law, gc.dim, CoarseRhsLaunch{gc, law, st, beta, K, psibar, gvec, psi, s});
+    dispatch<true>(law, gc.dim, CoarseRhsLaunch{gc, law, st, beta, K, psibar, gvec, psi, s});
 }
 
 void launch_prolong(const Geo &gf, const Geo &gc, const double *psi_c, const double *psibar_c,
@@ -721,7 +739,7 @@ struct TailLaunch {
 void launch_vcycle_tail(const TailArgs *args_dev, int top, int last, const Law &law,
                         const Step &st, int nu1, int nu2, int nuc, int dim, hipStream_t s)
 {
-    dispatch(law, dim, TailLaunch{args_dev, top, last, law, st, nu1, nu2, nuc, s});
+    dispatch<true>(law, dim, TailLaunch{args_dev, top, last, law, st, nu1, nu2, nuc, s});
 }
 
 void launch_interp(const Geo &gf, const Geo &gc, const double *psi_c, double *psi_f, hipStream_t s)

@@ -14,6 +14,9 @@ constexpr int kBcFreedrain = 3;
 constexpr int kVgm = 1;
 constexpr int kHaverkamp = 2;
 constexpr int kLinear = 3;
+constexpr int kGardner = 4;
+constexpr int kMulti = 5;      // a soil per node (Law::soils), FP64 path only
+constexpr int kMaxSoils = 16;
 constexpr int kSinkFeddes = 1;
 constexpr int kKappaConst = 1;
 constexpr int kKappaRel = 2;
@@ -33,6 +36,7 @@ struct Geo {
     int pface;       // patch face or -1
     int plo[2], phi[2];
     double pval;
+    const unsigned char *soil;   // soil index per node (read only under kMulti)
 };
 
 // Soil law and smoother parameters (by value).
@@ -50,6 +54,8 @@ struct Law {
     double kappa;
     int newton;
     double newton_tol;   // a Newton step of at most newton_tol |x| ends the pointwise solve
+    double gd_alpha;     // Gardner exponent (per law unit of psi)
+    const Law *soils;    // kMulti: device table of per-soil laws, indexed by Geo::soil
 };
 
 // Step coefficients (by value).
@@ -96,6 +102,8 @@ void launch_setup_kstar(const Geo &g, const Law &law, const Step &st, const doub
 void launch_setup_g(const Geo &g, const Law &law, const Step &st, const double *psi_n,
                     const double *psi_nm1, const double *K, double *gvec, hipStream_t s);
 void launch_inject(const Geo &gc, const Geo &gf, const double *Kf, double *Kc, hipStream_t s);
+void launch_inject_u8(const Geo &gc, const Geo &gf, const unsigned char *vf, unsigned char *vc,
+                      hipStream_t s);
 void launch_lambda_u(const Geo &g, const double *K, unsigned long long *out, hipStream_t s);
 // Red-black sweeps; 3-D levels with a second psi buffer use the fused kernel
 // and swap *psi / *psi_alt after every sweep.  Returns the kernel launches made.

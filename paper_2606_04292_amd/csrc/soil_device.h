@@ -137,6 +137,13 @@ __device__ __forceinline__ ThetaEval theta_t(const Law &L, double x)
         r.dth = 0.0;
         return r;
     }
+    if (MODEL == kGardner) {
+        const double au = L.gd_alpha * L.unit;
+        const double E = rs_exp(au * x);
+        r.th = L.tr + L.dT * E;
+        r.dth = au * L.dT * E;
+        return r;
+    }
     if (MODEL == kHaverkamp) {
         // one reciprocal serves 1/(alpha + Q) = hu w and 1/hu = (alpha + Q) w
         double hu = -L.unit * x;
@@ -162,6 +169,7 @@ __device__ __forceinline__ double theta_only_t(const Law &L, double x)
 {
     if (MODEL == kLinear) return L.tr + L.lin_c * x;
     if (!(x < 0.0)) return L.ts;
+    if (MODEL == kGardner) return L.tr + L.dT * rs_exp(L.gd_alpha * L.unit * x);
     if (MODEL == kHaverkamp) {
         double hu = -L.unit * x;
         double Q = rs_exp(L.hk_beta * rs_log(hu));
@@ -176,6 +184,7 @@ __device__ __forceinline__ double theta_only_t(const Law &L, double x)
 __device__ __forceinline__ double theta_only(const Law &L, double x)
 {
     switch (L.model) {
+    case kGardner: return theta_only_t<kGardner>(L, x);
     case kHaverkamp: return theta_only_t<kHaverkamp>(L, x);
     case kVgm: return theta_only_t<kVgm>(L, x);
     default: return theta_only_t<kLinear>(L, x);
@@ -186,6 +195,7 @@ __device__ __forceinline__ double theta_only(const Law &L, double x)
 __device__ __forceinline__ double krel(const Law &L, double x)
 {
     if (L.model == kLinear || !(x < 0.0)) return 1.0;
+    if (L.model == kGardner) return exp(L.gd_alpha * L.unit * x);
     if (L.model == kHaverkamp) {
         double hu = -L.unit * x;
         return L.hk_A / (L.hk_A + exp(L.hk_gamma * log(hu)));
@@ -274,6 +284,9 @@ __device__ __forceinline__ double local_solve(const Law &L, double a, double bet
 {
     const bool s = L.sink == kSinkFeddes;
     switch (L.model) {
+    case kGardner:
+        return s ? local_solve_t<kGardner, true, 0>(L, a, beta, c, f, x0)
+                 : local_solve_t<kGardner, false, 0>(L, a, beta, c, f, x0);
     case kHaverkamp:
         return s ? local_solve_t<kHaverkamp, true, 0>(L, a, beta, c, f, x0)
                  : local_solve_t<kHaverkamp, false, 0>(L, a, beta, c, f, x0);
@@ -283,6 +296,20 @@ __device__ __forceinline__ double local_solve(const Law &L, double a, double bet
     default:
         return s ? local_solve_t<kLinear, true, 0>(L, a, beta, c, f, x0)
                  : local_solve_t<kLinear, false, 0>(L, a, beta, c, f, x0);
+    }
+}
+
+// The pointwise solve with the law of one soil picked at run time (layered
+// media): the same iteration as local_solve_t for that soil's model.
+template <bool SINK, int NEWTON>
+__device__ __forceinline__ double local_solve_soil(const Law &Ls, double a, double beta, double c,
+                                                   double f, double x0)
+{
+    switch (Ls.model) {
+    case kGardner: return local_solve_t<kGardner, SINK, NEWTON>(Ls, a, beta, c, f, x0);
+    case kHaverkamp: return local_solve_t<kHaverkamp, SINK, NEWTON>(Ls, a, beta, c, f, x0);
+    case kVgm: return local_solve_t<kVgm, SINK, NEWTON>(Ls, a, beta, c, f, x0);
+    default: return local_solve_t<kLinear, SINK, NEWTON>(Ls, a, beta, c, f, x0);
     }
 }
 

@@ -121,7 +121,7 @@ class Engine:
         None when no slot or arena space is free."""
         torch = self.torch
         d = grid_desc(w.grid)
-        c, keep = constitutive(w.law, w.Ks_field)
+        c, keep = constitutive(w.law, w.Ks_field, w.soils, w.soil_id)
         with torch.cuda.stream(self.stream):
             psi0 = torch.as_tensor(np.ascontiguousarray(w.psi0, dtype=np.float64)).to(
                 self.device)

@@ -12,6 +12,9 @@ import paper_2606_04292_amd as rsl
 from paper_2606_04292_amd import workloads as W
 from tests.test_gpu_parity import CASES, NAMES, FLOOR_CYCLES, rel, np_, say, advance
 
+# the mixed path serves one vGM / Haverkamp / linear law per grid
+MP_NAMES = [n for n in NAMES if CASES[n].soils is None and CASES[n].law.model != W.MODEL_GARDNER]
+
 pytestmark = pytest.mark.gpu
 
 TOL_CONV = 1e-10
@@ -24,7 +27,7 @@ def torch_cuda():
     return torch
 
 
-@pytest.mark.parametrize("name", NAMES)
+@pytest.mark.parametrize("name", MP_NAMES)
 def test_mixed_converged_steps_match_fp64_oracle(torch_cuda, name):
     w = CASES[name]
     say("mixed converged", name)

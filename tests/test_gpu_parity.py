@@ -54,6 +54,11 @@ def cases():
     w = W.shrink(W.config2(), 33)
     out["c2_const_xi33"] = dataclasses.replace(
         w, law=dataclasses.replace(w.law, kappa_rule=W.KAPPA_CONST, kappa=1e-4, xi=1e-5))
+    # layered media and the Gardner law (section 4)
+    out["lay_celia129"] = W.celia_composite(129)
+    out["lay_2layer33"] = W.two_layer_vg(33)
+    out["gd_col129"] = dataclasses.replace(W.celia_column(129), name="gardner_col129",
+                                           law=W.celia_soils()[0])
     return out
 
 
@@ -197,7 +202,7 @@ def test_fmg_cycle_parity(torch_cuda, name):
     G.close()
 
 
-@pytest.mark.parametrize("name", ["c1_col257", "c2_slice65", "c3_block33"])
+@pytest.mark.parametrize("name", ["c1_col257", "c2_slice65", "c3_block33", "lay_2layer33"])
 def test_converged_steps_with_fmg_start(torch_cuda, name):
     """Steps that start with one FMG cycle reach the oracle's step solutions."""
     w = CASES[name]
@@ -218,7 +223,7 @@ def test_converged_steps_with_fmg_start(torch_cuda, name):
     G.close()
 
 
-@pytest.mark.parametrize("cfg", ["block257", "rootbox257x129"])
+@pytest.mark.parametrize("cfg", ["block257", "rootbox257x129", "twolayer257"])
 def test_full_size_sampled_sweep_and_setup(torch_cuda, cfg):
     """The 257^3 Haverkamp block (the benchmark's launch shape) and the
     257x257x129 root-uptake box at full size: set-up (K*, g) and one red-black
@@ -226,7 +231,7 @@ def test_full_size_sampled_sweep_and_setup(torch_cuda, cfg):
     the GPU's own inputs (red from the pre-sweep state, black from the GPU's
     red values)."""
     torch = torch_cuda
-    w = W.config3() if cfg == "block257" else W.config4()
+    w = {"block257": W.config3, "rootbox257x129": W.config4, "twolayer257": W.two_layer_vg}[cfg]()
     say("full-size sampled", cfg, w.grid.n)
     G = rsl.Grid(w)
     G.begin_step()
@@ -245,7 +250,7 @@ def test_full_size_sampled_sweep_and_setup(torch_cuda, cfg):
     S.set(oracle.FIELD_KSTAR, K)
     S.set(oracle.FIELD_G, g)
     rng = np.random.default_rng(11)
-    n0, n1, n2 = w.grid.n
+    n0, n1, n2 = (list(w.grid.n) + [1, 1])[:3]
     idx = rng.integers(0, n0 * n1 * n2, size=6000)
     i0 = idx % n0
     i1 = (idx // n0) % n1
@@ -407,3 +412,32 @@ def test_fused_sweep_is_independent_of_the_tiling(torch_cuda):
     S.begin_step()
     S.sweep(2)
     assert rel(outs[0], S.psi()) <= TOL_SWEEP
+
+
+def test_layered_media_errors(torch_cuda):
+    """Layered media and the Gardner law run on FP64 grids; a soil index beyond
+    the table is refused; the serving engine refuses both."""
+    w = W.two_layer_vg(17)
+    with pytest.raises(rsl.RsError) as ei:
+        rsl.Grid(w, precision=rsl.RS_MIXED)
+    assert ei.value.code == rsl.RS_EINVAL
+    g = W.celia_soils()[0]
+    with pytest.raises(rsl.RsError) as ei:
+        rsl.Grid(dataclasses.replace(W.celia_column(65), law=g), precision=rsl.RS_MIXED)
+    assert ei.value.code == rsl.RS_EINVAL
+    bad = w.soil_id.copy()
+    bad[3, 4] = 2
+    with pytest.raises(rsl.RsError) as ei:
+        rsl.Grid(dataclasses.replace(w, soil_id=bad))
+    assert ei.value.code == rsl.RS_EINVAL
+    with pytest.raises(rsl.RsError) as ei:
+        rsl.Grid(dataclasses.replace(w, Ks_field=np.full(w.grid.shape, 1.0)))
+    assert ei.value.code == rsl.RS_EINVAL
+    from paper_2606_04292_amd import serve
+    opts = serve.engine_opts(max_slots=4)
+    E = serve.Engine(serve.control_bytes(opts) + (64 << 20), opts)
+    for bad_w in (w, dataclasses.replace(W.celia_column(65), law=g)):
+        with pytest.raises(rsl.RsError) as ei:
+            E.submit(bad_w)
+        assert ei.value.code == rsl.RS_EINVAL
+    E.close()
