@@ -42,6 +42,7 @@
 #define ORC_BC_DIRICHLET 1
 #define ORC_BC_NOFLUX 2
 #define ORC_BC_FREEDRAIN 3
+#define ORC_BC_DIRICHLET_STATE 4
 
 #define ORC_MODEL_VGM 1
 #define ORC_MODEL_HAVERKAMP 2
@@ -277,29 +278,46 @@ static int in_patch(const orc_solver *S, const orc_level *lv, const int ii[3])
     return 1;
 }
 
+static int dirichlet_face(int bc)
+{
+    return bc == ORC_BC_DIRICHLET || bc == ORC_BC_DIRICHLET_STATE;
+}
+
 /* A node is Dirichlet if it lies on a Dirichlet face or on the patch.  Its
  * value: the patch value on the patch, otherwise that of the last Dirichlet
- * face (in face order) holding it. */
-static int is_dirichlet(const orc_solver *S, const orc_level *lv, const int ii[3], double *val)
+ * face (in face order) holding it.  A face of kind DIRICHLET_STATE holds
+ * non-uniform boundary data (the 2-D top boundary of section 4.2): its value
+ * is the node's entry of the state psi^n, reported through *from_state. */
+static int is_dirichlet_src(const orc_solver *S, const orc_level *lv, const int ii[3],
+                            double *val, int *from_state)
 {
-    int dir = 0;
+    int dir = 0, st = 0;
     double v = 0.0;
     for (int l = 0; l < S->grid.dim; l++) {
-        if (ii[l] == 0 && S->grid.face_bc[2 * l] == ORC_BC_DIRICHLET) {
+        if (ii[l] == 0 && dirichlet_face(S->grid.face_bc[2 * l])) {
             dir = 1;
             v = S->grid.face_value[2 * l];
+            st = S->grid.face_bc[2 * l] == ORC_BC_DIRICHLET_STATE;
         }
-        if (ii[l] == lv->n[l] - 1 && S->grid.face_bc[2 * l + 1] == ORC_BC_DIRICHLET) {
+        if (ii[l] == lv->n[l] - 1 && dirichlet_face(S->grid.face_bc[2 * l + 1])) {
             dir = 1;
             v = S->grid.face_value[2 * l + 1];
+            st = S->grid.face_bc[2 * l + 1] == ORC_BC_DIRICHLET_STATE;
         }
     }
     if (in_patch(S, lv, ii)) {
         dir = 1;
         v = S->grid.patch_value;
+        st = 0;
     }
     if (val) *val = v;
+    if (from_state) *from_state = st;
     return dir;
+}
+
+static int is_dirichlet(const orc_solver *S, const orc_level *lv, const int ii[3], double *val)
+{
+    return is_dirichlet_src(S, lv, ii, val, NULL);
 }
 
 /* Control-volume fraction along axis l for an unknown node: a node on the
@@ -840,7 +858,9 @@ void orc_begin_step(orc_solver *S, double dt, int order)
         int ii[3];
         double bv;
         coords(f0, i, ii);
-        if (is_dirichlet(S, f0, ii, &bv)) {
+        int from_state;
+        if (is_dirichlet_src(S, f0, ii, &bv, &from_state)) {
+            if (from_state) bv = S->psi_n[i];
             psistar[i] = bv;
             f0->psi[i] = bv;
         } else {

@@ -30,6 +30,7 @@ import numpy as np
 BC_DIRICHLET = 1
 BC_NOFLUX = 2
 BC_FREEDRAIN = 3
+BC_DIRICHLET_STATE = 4  # prescribed head taken from the state (non-uniform boundary data)
 
 # Constitutive models.
 MODEL_VGM = 1         # van Genuchten - Mualem (l = 0.5)
@@ -304,6 +305,28 @@ def two_layer_vg(n: int = 257, steps: int = 100) -> Workload:
     psi0 = -elevation(g)
     return Workload("two_layer_vg%d" % n, g, upper, psi0, dt=0.01, steps=steps, order=1,
                     nu1=10, nu2=10, soils=[upper, lower], soil_id=np.ascontiguousarray(sid))
+
+
+def gardner_2d(n: int = 129, steps: int = 30) -> Workload:
+    """The 2-D Gardner infiltration of section 4.2: (0,10)^2 m, theta_s 0.45,
+    theta_r 0.15, alpha 0.164 /m, Ks 0.1 m/day, psi0 = -10 m; on top the
+    non-uniform head (1/alpha) ln(e^(-10 alpha) + (1 - e^(-10 alpha)) sin(pi x/10)),
+    -10 m on the other boundaries; tau = 0.1 day for 3 days (30 steps), N = 128.
+    The top values enter through the initial state (a DIRICHLET_STATE face).
+    Not given by the paper for this case (readings): kappa and xi as in its
+    1-D case (Lambda_kappa = 0.1 I, xi = 0), BDF1, V(5,5)."""
+    g = GridSpec(dim=2, n=[n, n], L=[10.0, 10.0],
+                 face_bc=[BC_DIRICHLET, BC_DIRICHLET, BC_DIRICHLET, BC_DIRICHLET_STATE],
+                 face_value=[-10.0, -10.0, -10.0, 0.0])
+    alpha = 0.164
+    law = LawSpec(model=MODEL_GARDNER, theta_s=0.45, theta_r=0.15, Ks=0.1, gd_alpha=alpha,
+                  psi_unit=1.0, xi=0.0, kappa_rule=KAPPA_CONST, kappa=0.1)
+    x, _ = _coords(g)
+    e = math.exp(-10.0 * alpha)
+    top = np.log(e + (1.0 - e) * np.sin(np.pi * x.ravel() / 10.0)) / alpha
+    psi0 = np.full(g.shape, -10.0)
+    psi0[-1, :] = top
+    return Workload("gardner2d_%d" % n, g, law, psi0, dt=0.1, steps=steps, order=1, nu1=5, nu2=5)
 
 
 def serving_requests(count: int = 4096, seed_path=(1,)) -> List[Workload]:
