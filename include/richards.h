@@ -56,6 +56,10 @@ extern "C" {
 #define RS_BC_DIRICHLET 1 /* prescribed head (value stored in the psi array) */
 #define RS_BC_NOFLUX 2    /* zero normal flux, half control volume */
 #define RS_BC_FREEDRAIN 3 /* unit total-head gradient outflow; bottom face only */
+#define RS_BC_DIRICHLET_STATE 4 /* prescribed head taken node by node from the state psi^n
+                                   (non-uniform boundary data, e.g. the top boundary of the
+                                   2-D Gardner case of section 4.2); face_value unused.
+                                   RS_FP64 and RS_MIXED grids; not in the serving engine */
 
 /* constitutive models (Table tab:models) */
 #define RS_VGM 1          /* van Genuchten - Mualem, m = 1 - 1/n, l = 1/2 */

@@ -59,7 +59,8 @@ int validate_desc(const rs_grid_desc *d)
     }
     for (int f = 0; f < 2 * d->dim; ++f) {
         int b = d->face_bc[f];
-        if (b != RS_BC_DIRICHLET && b != RS_BC_NOFLUX && b != RS_BC_FREEDRAIN)
+        if (b != RS_BC_DIRICHLET && b != RS_BC_NOFLUX && b != RS_BC_FREEDRAIN &&
+            b != RS_BC_DIRICHLET_STATE)
             return fail(RS_EINVAL, "face_bc[%d]=%d invalid", f, b);
         if (b == RS_BC_FREEDRAIN && f != 2 * (d->dim - 1))
             return fail(RS_EINVAL, "free drainage is only allowed on the bottom face");
@@ -117,7 +118,11 @@ Geo make_geo(const rs_grid_desc *d, int lev)
     g.stride[1] = g.n[0];
     g.stride[2] = g.n[0] * g.n[1];
     for (int f = 0; f < 6; ++f) {
-        g.bc[f] = f < 2 * d->dim ? d->face_bc[f] : 0;
+        // a state-valued Dirichlet face is a Dirichlet face whose values come
+        // from the state: the kernels see kBcDirichlet plus its bit in state_mask
+        const int b = f < 2 * d->dim ? d->face_bc[f] : 0;
+        g.bc[f] = b == RS_BC_DIRICHLET_STATE ? kBcDirichlet : b;
+        if (b == RS_BC_DIRICHLET_STATE) g.state_mask |= 1 << f;
         g.bcval[f] = f < 2 * d->dim ? d->face_value[f] : 0.0;
     }
     g.pface = d->patch_face;

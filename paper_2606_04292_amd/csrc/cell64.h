@@ -19,7 +19,9 @@ __device__ __forceinline__ double kstar_at(const Geo &g, const Law &L, const Ste
 {
     double bv;
     double ps;
-    if (dirichlet_at(g, i, j, k, &bv)) {
+    bool from_state;
+    if (dirichlet_at(g, i, j, k, &bv, &from_state)) {
+        if (from_state) bv = psi_n[idx];
         ps = bv;
         *psi0 = bv;
     } else {

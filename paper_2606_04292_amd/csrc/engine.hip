@@ -680,6 +680,9 @@ int plan_request(const rs_engine_opts &o, const rs_grid_desc *d, ReqPlan *p)
 {
     int e = validate_desc(d);
     if (e) return e;
+    for (int f = 0; f < 2 * d->dim; ++f)
+        if (d->face_bc[f] == RS_BC_DIRICHLET_STATE)
+            return fail(RS_EINVAL, "the engine serves faces with constant boundary values");
     p->nlev = level_count(d);
     if (p->nlev > kEngMaxLevels)
         return fail(RS_EINVAL, "grid needs %d levels; the engine handles %d", p->nlev,

@@ -32,6 +32,7 @@ struct Geo {
     double h[3];
     double ih2[3];   // 1 / h^2
     int bc[6];       // face kinds
+    int state_mask;  // bit f: face f's Dirichlet values come from the state psi^n
     double bcval[6];
     int pface;       // patch face or -1
     int plo[2], phi[2];

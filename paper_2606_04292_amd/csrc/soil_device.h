@@ -315,17 +315,24 @@ __device__ __forceinline__ double local_solve_soil(const Law &Ls, double a, doub
 
 // Node kinds from indices (no node-type array): Dirichlet if on a Dirichlet
 // face or on the patch; value = patch value, else the highest-numbered
-// Dirichlet face holding the node.
-__device__ __forceinline__ bool dirichlet_at(const Geo &g, int i, int j, int k, double *val)
+// Dirichlet face holding the node (*from_state: that face takes its values
+// from the state psi^n).
+__device__ __forceinline__ bool dirichlet_at(const Geo &g, int i, int j, int k, double *val,
+                                             bool *from_state = nullptr)
 {
     int c[3] = {i, j, k};
     bool dir = false;
     double v = 0.0;
+    int face = -1;
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
         if (l >= g.dim) break;
-        if (c[l] == 0 && g.bc[2 * l] == kBcDirichlet) { dir = true; v = g.bcval[2 * l]; }
-        if (c[l] == g.n[l] - 1 && g.bc[2 * l + 1] == kBcDirichlet) { dir = true; v = g.bcval[2 * l + 1]; }
+        if (c[l] == 0 && g.bc[2 * l] == kBcDirichlet) { dir = true; v = g.bcval[2 * l]; face = 2 * l; }
+        if (c[l] == g.n[l] - 1 && g.bc[2 * l + 1] == kBcDirichlet) {
+            dir = true;
+            v = g.bcval[2 * l + 1];
+            face = 2 * l + 1;
+        }
     }
     if (g.pface >= 0) {
         int ax = g.pface >> 1;
@@ -340,10 +347,11 @@ __device__ __forceinline__ bool dirichlet_at(const Geo &g, int i, int j, int k, 
                 if (c[l] < g.plo[t] || c[l] > g.phi[t]) in = false;
                 ++t;
             }
-            if (in) { dir = true; v = g.pval; }
+            if (in) { dir = true; v = g.pval; face = -1; }
         }
     }
     if (val) *val = v;
+    if (from_state) *from_state = face >= 0 && ((g.state_mask >> face) & 1);
     return dir;
 }
 

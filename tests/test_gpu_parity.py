@@ -59,6 +59,16 @@ def cases():
     out["lay_2layer33"] = W.two_layer_vg(33)
     out["gd_col129"] = dataclasses.replace(W.celia_column(129), name="gardner_col129",
                                            law=W.celia_soils()[0])
+    # non-uniform boundary data through the state: the 2-D Gardner infiltration,
+    # and a vGM slice whose top head varies along the face
+    out["gd_2d33"] = W.gardner_2d(33)
+    w = W.shrink(W.config2(), 33)
+    bc = list(w.grid.face_bc)
+    bc[3] = W.BC_DIRICHLET_STATE
+    psi0 = w.psi0.copy()
+    psi0[-1, :] = -0.5 + 0.4 * np.sin(np.pi * np.linspace(0.0, 1.0, 33))
+    out["st_vg33"] = dataclasses.replace(w, name="state_top_vg33", psi0=psi0,
+                                         grid=dataclasses.replace(w.grid, face_bc=bc))
     return out
 
 
@@ -436,7 +446,7 @@ def test_layered_media_errors(torch_cuda):
     from paper_2606_04292_amd import serve
     opts = serve.engine_opts(max_slots=4)
     E = serve.Engine(serve.control_bytes(opts) + (64 << 20), opts)
-    for bad_w in (w, dataclasses.replace(W.celia_column(65), law=g)):
+    for bad_w in (w, dataclasses.replace(W.celia_column(65), law=g), CASES["st_vg33"]):
         with pytest.raises(rsl.RsError) as ei:
             E.submit(bad_w)
         assert ei.value.code == rsl.RS_EINVAL
