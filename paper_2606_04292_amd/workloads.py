@@ -287,18 +287,19 @@ def celia_composite(n: int = 2049) -> Workload:
                                soil_id=sid.astype(np.uint8))
 
 
-def two_layer_vg(n: int = 257, steps: int = 100) -> Workload:
+def two_layer_vg(n: int = 257, steps: int = 175) -> Workload:
     """The two-layer infiltration of section 4.2: (0,100)^2 cm, vGM soils above
-    and below the interface zeta(x) = 100 (0.1 (1 - cos(pi x / 100)) + 0.45)
-    (parameters in cm and h), psi0 = -z, psi = 0 on top and bottom, no flux on
-    the sides, Lambda_kappa = 0.1 I, xi = 0, tau = 0.01 h, FMG(10, 10) starts.
-    The paper gives no end time; `steps` sets it."""
+    and below the interface zeta(x) = 100 (0.1 (1 - cos(pi x / 100)) + 0.45),
+    psi0 = -z, psi = 0 on top and bottom, no flux on the sides,
+    Lambda_kappa = 0.1 I, xi = 0, tau = 0.01, FMG(10, 10) starts.  Reading:
+    the paper gives Ks in cm/h but shows the solution in days up to 1.75 days,
+    so time is in days (Ks converted, tau = 0.01 day, 175 steps)."""
     g = GridSpec(dim=2, n=[n, n], L=[100.0, 100.0],
                  face_bc=[BC_NOFLUX, BC_NOFLUX, BC_DIRICHLET, BC_DIRICHLET],
                  face_value=[0.0, 0.0, 0.0, 0.0])
     common = dict(model=MODEL_VGM, psi_unit=1.0, xi=0.0, kappa_rule=KAPPA_CONST, kappa=0.1)
-    upper = LawSpec(theta_s=0.50, theta_r=0.120, vg_alpha=0.025, vg_n=3.00, Ks=0.25, **common)
-    lower = LawSpec(theta_s=0.46, theta_r=0.034, vg_alpha=0.016, vg_n=1.37, Ks=2.00, **common)
+    upper = LawSpec(theta_s=0.50, theta_r=0.120, vg_alpha=0.025, vg_n=3.00, Ks=0.25 * 24.0, **common)
+    lower = LawSpec(theta_s=0.46, theta_r=0.034, vg_alpha=0.016, vg_n=1.37, Ks=2.00 * 24.0, **common)
     x, z = _coords(g)
     zeta = 100.0 * (0.1 * (1.0 - np.cos(np.pi * x / 100.0)) + 0.45)
     sid = np.broadcast_to(np.where(z >= zeta, 0, 1), g.shape).astype(np.uint8)
