@@ -153,40 +153,37 @@ struct Layout {
 
 constexpr int kScratchWords = 64;
 
+// Every array is placed with at least kPad zeroed bytes before and after it
+// (the workspace is cleared at creation): the single-grid stencils load the
+// axis-0 neighbours idx -/+ 1 unconditionally (see stencil<DIM, true>).
+constexpr size_t kPad = 256;
+
 void plan(const rs_grid_desc *d, int precision, Layout *L)
 {
     size_t off = 0;
+    auto place = [&](size_t bytes) {
+        off = align_up(off + kPad);
+        const size_t at = off;
+        off = align_up(off + bytes + kPad);
+        return at;
+    };
     L->nlev = level_count(d);
     for (int l = 0; l < L->nlev; ++l) {
         Geo g = make_geo(d, l);
-        for (int a = 0; a < 5; ++a) {
-            L->lev_off[l][a] = off;
-            off = align_up(off + sizeof(double) * (size_t)g.N);
-        }
-        L->lev_off[l][5] = 0;
-        if (fused_sweep_level(g)) {
-            L->lev_off[l][5] = off;
-            off = align_up(off + sizeof(double) * (size_t)g.N);
-        }
-        L->beta_off[l] = off;
-        off = align_up(off + sizeof(double) * (size_t)g.n[g.vert]);
-        L->soil_off[l] = off;
-        off = align_up(off + (size_t)g.N);
-        for (int a = 0; a < 6; ++a) {
-            L->mp_off[l][a] = 0;
-            if (precision == RS_MIXED) {
-                L->mp_off[l][a] = off;
-                off = align_up(off + sizeof(float) * (size_t)g.N);
-            }
-        }
+        for (int a = 0; a < 5; ++a) L->lev_off[l][a] = place(sizeof(double) * (size_t)g.N);
+        L->lev_off[l][5] = fused_sweep_level(g) ? place(sizeof(double) * (size_t)g.N) : 0;
+        L->beta_off[l] = place(sizeof(double) * (size_t)g.n[g.vert]);
+        L->soil_off[l] = place((size_t)g.N);
+        for (int a = 0; a < 6; ++a)
+            L->mp_off[l][a] = precision == RS_MIXED ? place(sizeof(float) * (size_t)g.N) : 0;
     }
     size_t N0 = (size_t)make_geo(d, 0).N;
-    L->psi_n = off;   off = align_up(off + sizeof(double) * N0);
-    L->psi_nm1 = off; off = align_up(off + sizeof(double) * N0);
-    L->ks = off;      off = align_up(off + sizeof(double) * N0);
-    L->scratch = off; off = align_up(off + sizeof(unsigned long long) * kScratchWords);
-    L->tail = off;    off = align_up(off + sizeof(TailArgs));
-    L->soil_tab = off; off = align_up(off + sizeof(Law) * kMaxSoils);
+    L->psi_n = place(sizeof(double) * N0);
+    L->psi_nm1 = place(sizeof(double) * N0);
+    L->ks = place(sizeof(double) * N0);
+    L->scratch = place(sizeof(unsigned long long) * kScratchWords);
+    L->tail = place(sizeof(TailArgs));
+    L->soil_tab = place(sizeof(Law) * kMaxSoils);
     L->total = off;
 }
 
@@ -609,6 +606,8 @@ int rs_create_grid(const rs_grid_desc *d, int precision, void *ws_dev, size_t ws
     plan(d, precision, &L);
     if (ws_bytes < L.total)
         return fail(RS_ENOMEM, "workspace %zu bytes < required %zu", ws_bytes, L.total);
+    // the padding around every array must hold finite values (zeros)
+    HIPCALL(hipMemsetAsync(ws_dev, 0, L.total, (hipStream_t)stream));
     rs_grid *G = new (std::nothrow) rs_grid();
     if (!G) return fail(RS_ENOMEM, "host allocation failed");
     G->desc = *d;

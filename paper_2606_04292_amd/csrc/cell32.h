@@ -17,15 +17,16 @@ __device__ __forceinline__ int vert_index(int i, int j, int k)
 }
 
 // New delta at unknown (i, j, k): f = rhs + sum_j m_ij delta_j + kappa delta_i,
-// c = xi + kappa + m_ii, then the scalar correction solve.
-template <int MODEL, bool SINK, int DIM>
+// c = xi + kappa + m_ii, then the scalar correction solve.  XPAD: the arrays
+// have finite padding around them (see stencil()).
+template <int MODEL, bool SINK, int DIM, bool XPAD = false>
 __device__ __forceinline__ void ngs_cell32(const Geo &g, const Law32 &L, float a,
                                            const double *beta, float lambdaU, const float *K,
                                            const float *rhs, const float *pb, float *dl, int i,
                                            int j, int k, int colour)
 {
     const long long idx = i + (long long)j * g.stride[1] + (long long)k * g.stride[2];
-    const Stencil<DIM> st = stencil<DIM>(g, i, j, k, idx);
+    const Stencil<DIM> st = stencil<DIM, XPAD>(g, i, j, k, idx);
     const float Ki = K[idx];
     const float d0 = dl[idx];
     float f = rhs[idx];
@@ -68,12 +69,12 @@ __device__ __forceinline__ void ngs_cell32(const Geo &g, const Law32 &L, float a
 }
 
 // N_delta(delta)_i = a dtheta + beta da + xi delta_i + sum_j m_ij (delta_i - delta_j)
-template <int MODEL, bool SINK, int DIM>
+template <int MODEL, bool SINK, int DIM, bool XPAD = false>
 __device__ __forceinline__ float apply_Nd(const Geo &g, const Law32 &L, float a,
                                           const double *beta, const float *K, const float *pb,
                                           const float *dl, int i, int j, int k, long long idx)
 {
-    const Stencil<DIM> st = stencil<DIM>(g, i, j, k, idx);
+    const Stencil<DIM> st = stencil<DIM, XPAD>(g, i, j, k, idx);
     const float x = dl[idx];
     const float Ki = K[idx];
     const float p = pb[idx];

@@ -72,13 +72,13 @@ __device__ __forceinline__ double g_at(const Geo &g, const Law &L, const Step &s
 
 // N(psi)_i = a theta(psi_i) + beta a_F(psi_i) + xi psi_i + (M psi)_i
 // (the whole stencil is loaded before the law is evaluated, so that the loads
-// overlap the theta chain instead of following it).
-template <int MODEL, bool SINK, int DIM>
+// overlap the theta chain instead of following it; XPAD as for stencil()).
+template <int MODEL, bool SINK, int DIM, bool XPAD = false>
 __device__ __forceinline__ double apply_N_t(const Geo &g, const Law &L, double a,
                                             const double *beta, const double *K,
                                             const double *psi, int i, int j, int k, long long idx)
 {
-    const Stencil<DIM> st = stencil<DIM>(g, i, j, k, idx);
+    const Stencil<DIM> st = stencil<DIM, XPAD>(g, i, j, k, idx);
     const double x = psi[idx];
     const double Ki = K[idx];
     double Kn[2 * DIM], pn[2 * DIM];

@@ -109,14 +109,17 @@ __device__ __forceinline__ void for_each_nb(const Geo &g, const int c[3], long l
 // and coefficients 1/(2 w h^2).  A neighbour outside the domain gets the node
 // itself as index and a zero coefficient, so every load of a stencil can be
 // issued before any arithmetic (no branch per neighbour) and the zero terms
-// leave the sums unchanged.
+// leave the sums unchanged.  XPAD (arrays with finite padding around them, as
+// in a grid workspace): the axis-0 neighbours are always idx -/+ 1 (the
+// neighbouring row's end node, or the padding, when outside the domain, still
+// with a zero coefficient), so the three loads of a row merge into wide loads.
 template <int DIM>
 struct Stencil {
     long long jn[2 * DIM];
     double cf[2 * DIM];
 };
 
-template <int DIM>
+template <int DIM, bool XPAD = false>
 __device__ __forceinline__ Stencil<DIM> stencil(const Geo &g, int i, int j, int k, long long idx)
 {
     Stencil<DIM> s;
@@ -124,11 +127,12 @@ __device__ __forceinline__ Stencil<DIM> stencil(const Geo &g, int i, int j, int 
     for (int l = 0; l < DIM; ++l) {
         const int cl = (l == 0) ? i : (l == 1 ? j : k);
         const double cf = ((cl == 0 || cl == g.n[l] - 1) ? 1.0 : 0.5) * g.ih2[l];
-        const long long st = g.stride[l];
+        const long long st = l == 0 ? 1 : g.stride[l];   // axis 0 is contiguous
         const bool lo = cl > 0, hi = cl < g.n[l] - 1;
-        s.jn[2 * l] = lo ? idx - st : idx;
+        const bool xp = XPAD && l == 0;
+        s.jn[2 * l] = (lo || xp) ? idx - st : idx;
         s.cf[2 * l] = lo ? cf : 0.0;
-        s.jn[2 * l + 1] = hi ? idx + st : idx;
+        s.jn[2 * l + 1] = (hi || xp) ? idx + st : idx;
         s.cf[2 * l + 1] = hi ? cf : 0.0;
     }
     return s;

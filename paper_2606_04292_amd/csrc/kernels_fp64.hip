@@ -148,7 +148,7 @@ __device__ __forceinline__ void ngs_cell(const Geo &g, const Law &L, double a, c
                                          double *psi, int i, int j, int k, int colour)
 {
     const long long idx = i + (long long)j * g.stride[1] + (long long)k * g.stride[2];
-    const Stencil<DIM> st = stencil<DIM>(g, i, j, k, idx);
+    const Stencil<DIM> st = stencil<DIM, true>(g, i, j, k, idx);   // workspace arrays are padded
     const double Ki = K[idx];
     const double x0 = psi[idx];
     double f = gv[idx];
@@ -406,7 +406,7 @@ __global__ __launch_bounds__(512) void k_vcycle_tail(const TailArgs *A, int top,
             node_ijk(nf, t, i, j, k);
             double r = 0.0;
             if (!dirichlet_at(F.g, i, j, k, nullptr))
-                r = F.gv[t] - apply_N_t<MODEL, SINK, DIM>(F.g, L, a, F.beta, F.K, F.psi, i, j, k,
+                r = F.gv[t] - apply_N_t<MODEL, SINK, DIM, true>(F.g, L, a, F.beta, F.K, F.psi, i, j, k,
                                                           (long long)t);
             F.d[t] = r;
         }
@@ -421,7 +421,7 @@ __global__ __launch_bounds__(512) void k_vcycle_tail(const TailArgs *A, int top,
             int i, j, k;
             node_ijk(nc, t, i, j, k);
             if (!dirichlet_at(C.g, i, j, k, nullptr))
-                C.gv[t] = apply_N_t<MODEL, SINK, DIM>(C.g, L, a, C.beta, C.K, C.psibar, i, j, k,
+                C.gv[t] = apply_N_t<MODEL, SINK, DIM, true>(C.g, L, a, C.beta, C.K, C.psibar, i, j, k,
                                                       (long long)t) +
                           C.gv[t];
             C.psi[t] = C.psibar[t];
@@ -462,7 +462,7 @@ __global__ __launch_bounds__(256) void k_residual(Geo g, Law L, Step st, const d
         node_ijk(nm, t, i, j, k);
         double r = 0.0;
         if (!dirichlet_at(g, i, j, k, nullptr))
-            r = gv[t] - apply_N_t<MODEL, SINK, DIM>(g, L, st.a, beta, K, psi, i, j, k, (long long)t);
+            r = gv[t] - apply_N_t<MODEL, SINK, DIM, true>(g, L, st.a, beta, K, psi, i, j, k, (long long)t);
         if (d) d[t] = r;
         v = fabs(r);
     }
@@ -494,7 +494,7 @@ __global__ __launch_bounds__(256) void k_coarse_rhs(Geo g, Law L, Step st, const
     int i, j, k;
     node_ijk(nm, t, i, j, k);
     if (!dirichlet_at(g, i, j, k, nullptr))
-        gv[t] = apply_N_t<MODEL, SINK, DIM>(g, L, st.a, beta, K, psibar, i, j, k, (long long)t) +
+        gv[t] = apply_N_t<MODEL, SINK, DIM, true>(g, L, st.a, beta, K, psibar, i, j, k, (long long)t) +
                 gv[t];
     psi[t] = psibar[t];
 }

@@ -38,7 +38,7 @@ __global__ __launch_bounds__(256) void k_sweep32(Geo g, Law32 L, float a, const 
     const int i = 2 * (int)ih + (int)((j + k + colour) & 1);
     if (i >= g.n[0]) return;
     if (dirichlet_at(g, i, (int)j, (int)k, nullptr)) return;
-    ngs_cell32<MODEL, SINK, DIM>(g, L, a, beta, lambdaU, K, rhs, pb, dl, i, (int)j, (int)k, colour);
+    ngs_cell32<MODEL, SINK, DIM, true>(g, L, a, beta, lambdaU, K, rhs, pb, dl, i, (int)j, (int)k, colour);
 }
 
 template <int MODEL, bool SINK, int DIM>
@@ -57,7 +57,7 @@ __global__ __launch_bounds__(256) void k_sweep32_small(Geo g, Law32 L, float a, 
                 int k = r / g.n[1];
                 if (((i + j + k) & 1) != colour) continue;
                 if (dirichlet_at(g, i, j, k, nullptr)) continue;
-                ngs_cell32<MODEL, SINK, DIM>(g, L, a, beta, lambdaU, K, rhs, pb, dl, i, j, k, colour);
+                ngs_cell32<MODEL, SINK, DIM, true>(g, L, a, beta, lambdaU, K, rhs, pb, dl, i, j, k, colour);
             }
             __syncthreads();
         }
@@ -79,7 +79,7 @@ __global__ __launch_bounds__(256) void k_residual32(Geo g, Law32 L, float a, con
     const long long idx = (long long)t;
     float v = 0.0f;
     if (!dirichlet_at(g, i, j, k, nullptr))
-        v = rhs[idx] - apply_Nd<MODEL, SINK, DIM>(g, L, a, beta, K, pb, dl, i, j, k, idx);
+        v = rhs[idx] - apply_Nd<MODEL, SINK, DIM, true>(g, L, a, beta, K, pb, dl, i, j, k, idx);
     r[idx] = v;
 }
 
@@ -98,7 +98,7 @@ __global__ __launch_bounds__(256) void k_coarse_rhs32(Geo g, Law32 L, float a, c
     node_ijk(nm, t, i, j, k);
     const long long idx = (long long)t;
     if (!dirichlet_at(g, i, j, k, nullptr))
-        rhs[idx] = apply_Nd<MODEL, SINK, DIM>(g, L, a, beta, K, pb, dbar, i, j, k, idx) + rhs[idx];
+        rhs[idx] = apply_Nd<MODEL, SINK, DIM, true>(g, L, a, beta, K, pb, dbar, i, j, k, idx) + rhs[idx];
     dl[idx] = dbar[idx];
 }
 
