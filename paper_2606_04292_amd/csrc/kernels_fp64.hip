@@ -478,6 +478,103 @@ __global__ __launch_bounds__(256) void k_residual(Geo g, Law L, Step st, const d
     }
 }
 
+// The same defect for two neighbouring nodes of a row per thread (i = 2 ih,
+// 2 ih + 1): both stencils are loaded as pairs of adjacent values, so a row
+// window of four values and every off-row pair become wide loads, and the two
+// theta chains overlap.  Each node's arithmetic is that of apply_N_t with
+// XPAD.  Slots are those of the colour packing (H = (n0 + 1) / 2 per row).
+template <int MODEL, bool SINK, int DIM>
+__global__ __launch_bounds__(256) void k_residual_pair(Geo g, Law L, Step st, const double *beta,
+                                                       const double *K, const double *gv,
+                                                       const double *psi, double *d,
+                                                       unsigned long long *norm_bits, ColourMap cm)
+{
+    double v = 0.0;
+    const unsigned long long t =
+        (unsigned long long)xcd_block(gridDim.x / 8u) * blockDim.x + threadIdx.x;
+    if (t < cm.total) {
+        const unsigned row = udiv((unsigned)t, cm.dH);
+        const int i0 = 2 * (int)((unsigned)(t - (unsigned long long)row * cm.H));
+        int j = 0, k = 0;
+        if (DIM == 3) {
+            k = (int)udiv(row, cm.dN1);
+            j = (int)row - k * (int)cm.n1;
+        } else if (DIM == 2) {
+            j = (int)row;
+        }
+        const long long idx0 = i0 + (long long)j * g.stride[1] + (long long)k * g.stride[2];
+        // row window psi/K[idx0 - 1 .. idx0 + 2] (padding keeps it in bounds)
+        double P[4], KK[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            P[q] = psi[idx0 - 1 + q];
+            KK[q] = K[idx0 - 1 + q];
+        }
+        // off-row neighbours as pairs: base (or the node itself when outside)
+        constexpr int NO = 2 * (DIM - 1);
+        double Po[NO > 0 ? NO : 1][2], Ko[NO > 0 ? NO : 1][2], cfo[NO > 0 ? NO : 1];
+#pragma unroll
+        for (int q = 0; q < NO; ++q) {
+            const int l = 1 + q / 2;
+            const int cl = l == 1 ? j : k;
+            const bool up = q & 1;
+            const bool ok = up ? cl < g.n[l] - 1 : cl > 0;
+            const long long b = ok ? idx0 + (up ? g.stride[l] : -(long long)g.stride[l]) : idx0;
+            Po[q][0] = psi[b];
+            Po[q][1] = psi[b + 1];
+            Ko[q][0] = K[b];
+            Ko[q][1] = K[b + 1];
+            cfo[q] = ok ? ((cl == 0 || cl == g.n[l] - 1) ? 1.0 : 0.5) * g.ih2[l] : 0.0;
+        }
+        const double g0 = gv[idx0], g1 = gv[idx0 + 1];
+        double bz = 0.0;
+        if (SINK) bz = beta[(DIM == 1) ? i0 : (DIM == 2 ? j : k)];
+        double r[2] = {0.0, 0.0};
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const int i = i0 + a;
+            if (i >= g.n[0] || dirichlet_at(g, i, j, k, nullptr)) continue;
+            const double x = P[1 + a], Ki = KK[1 + a];
+            double s;
+            if constexpr (MODEL == kMulti) s = st.a * theta_only(L.soils[g.soil[idx0 + a]], x);
+            else s = st.a * theta_only_t<MODEL>(L, x);
+            if (SINK) {
+                double fa, dfa;
+                feddes(L, x, fa, dfa);
+                s += bz * fa;
+            }
+            // neighbours in the order of stencil(): axis 0 low/high, then the others
+            const double cx = ((i == 0 || i == g.n[0] - 1) ? 1.0 : 0.5) * g.ih2[0];
+            const double cm0 = i > 0 ? cx : 0.0, cp0 = i < g.n[0] - 1 ? cx : 0.0;
+            double mpsi = 0.0;
+            mpsi += cm0 * (Ki + KK[a]) * (x - P[a]);
+            mpsi += cp0 * (Ki + KK[2 + a]) * (x - P[2 + a]);
+#pragma unroll
+            for (int q = 0; q < NO; ++q) {
+                // a missing neighbour is the node itself (coefficient 0)
+                const bool ok = cfo[q] != 0.0;
+                const double pn = ok ? Po[q][a] : x, kn = ok ? Ko[q][a] : Ki;
+                mpsi += cfo[q] * (Ki + kn) * (x - pn);
+            }
+            r[a] = (a ? g1 : g0) - (s + (L.xi * x + mpsi));
+        }
+        if (d) {
+            d[idx0] = r[0];
+            if (i0 + 1 < g.n[0]) d[idx0 + 1] = r[1];
+        }
+        const double a0 = fabs(r[0]), a1 = fabs(r[1]);
+        v = (a1 > a0 || a1 != a1) ? a1 : a0;
+    }
+    if (norm_bits) {
+        v = block_max(v);
+        if (threadIdx.x == 0) {
+            const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
+            if (bits > __hip_atomic_load(norm_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                atomicMax(norm_bits, bits);
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Transfers (section 3.2 steps 3, 4 and 6)
 // ---------------------------------------------------------------------------
@@ -678,9 +775,9 @@ struct ResidualLaunch {
     template <int M, bool S, int D>
     void go()
     {
-        const unsigned long long blocks = ((unsigned long long)g.N + 255) / 256;
-        hipLaunchKernelGGL((k_residual<M, S, D>), dim3(xcd_grid(blocks)), dim3(256), 0, s, g,
-                           law, st, beta, K, gvec, psi, d, norm_bits, node_map(g));
+        const ColourMap cm = colour_map(g);
+        hipLaunchKernelGGL((k_residual_pair<M, S, D>), dim3(xcd_grid((cm.total + 255) / 256)),
+                           dim3(256), 0, s, g, law, st, beta, K, gvec, psi, d, norm_bits, cm);
     }
 };
 
