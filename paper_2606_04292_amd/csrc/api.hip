@@ -521,8 +521,10 @@ int vcycle_level(rs_grid *G, int l, int nu1, int nu2)
     LevelData &f = G->lev[l];
     if (l >= G->tail_top && l < G->nlev - 1) {
         // the rest of the cycle on small levels: one work-group, one launch
+        long long nodes[kMaxLevels];
+        for (int q = 0; q < G->nlev; ++q) nodes[q] = G->lev[q].geo.N;
         launch_vcycle_tail(G->tail_dev, l, G->nlev - 1, G->law, G->step, nu1, nu2, G->nu_coarse,
-                           G->desc.dim, G->stream);
+                           G->desc.dim, nodes, G->stream);
         for (int q = l; q < G->nlev - 1; ++q)
             G->updates += (double)(nu1 + nu2) * (double)G->lev[q].unknowns;
         G->updates += (double)G->nu_coarse * (double)G->lev[G->nlev - 1].unknowns;

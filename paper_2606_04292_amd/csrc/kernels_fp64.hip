@@ -392,13 +392,52 @@ __device__ void tail_sweeps64(const TailLevel &T, const Law &L, double a, int n)
         }
 }
 
+// Levels lds_from..last live in LDS for the duration of the cycle (psi, K*, g,
+// d, psibar of each, with one zero element before and after every array for
+// the padded stencils): K* and, for the top level, psi and g are copied in;
+// the top level's psi is copied back (the only result used after the cycle;
+// the top level's psibar and beta stay in global memory).
 template <int MODEL, bool SINK, int DIM>
 __global__ __launch_bounds__(512) void k_vcycle_tail(const TailArgs *A, int top, int last, Law L,
-                                                     Step st, int nu1, int nu2, int nuc)
+                                                     Step st, int nu1, int nu2, int nuc,
+                                                     int lds_from)
 {
+    extern __shared__ double lds[];
+    __shared__ TailLevel SL[kMaxLevels];
+    for (int l = top + (int)threadIdx.x; l <= last; l += (int)blockDim.x) SL[l] = A->lv[l];
+    __syncthreads();
+    if (lds_from <= last) {
+        if (threadIdx.x == 0) {
+            long long off = 0;
+            for (int l = lds_from; l <= last; ++l) {
+                const long long n = SL[l].g.N + 2;
+                double **arr[5] = {&SL[l].psi, &SL[l].K, &SL[l].gv, &SL[l].d, &SL[l].psibar};
+                for (int q = 0; q < 5; ++q) {
+                    if (l == top && q == 4) continue;   // read-only, stays global
+                    *arr[q] = lds + off + 1;
+                    off += n;
+                }
+            }
+        }
+        __syncthreads();
+        for (int l = lds_from; l <= last; ++l) {
+            const TailLevel &G = A->lv[l], &S = SL[l];
+            const long long N = S.g.N;
+            for (long long t = threadIdx.x; t < N + 2; t += blockDim.x) {
+                const long long u = t - 1;
+                const bool in = u >= 0 && u < N;
+                S.K[u] = in ? G.K[u] : 0.0;
+                S.psi[u] = (in && l == top) ? G.psi[u] : 0.0;
+                S.gv[u] = (in && l == top) ? G.gv[u] : 0.0;
+                S.d[u] = 0.0;
+                if (l != top) S.psibar[u] = 0.0;
+            }
+        }
+        __syncthreads();
+    }
     const double a = st.a;
     for (int l = top; l < last; ++l) {
-        const TailLevel &F = A->lv[l], &C = A->lv[l + 1];
+        const TailLevel &F = SL[l], &C = SL[l + 1];
         tail_sweeps64<MODEL, SINK, DIM>(F, L, a, nu1);
         const NodeMap nf = tail_nm(F), nc = tail_nm(C);
         for (unsigned long long t = threadIdx.x; t < (unsigned long long)F.g.N; t += blockDim.x) {
@@ -428,9 +467,9 @@ __global__ __launch_bounds__(512) void k_vcycle_tail(const TailArgs *A, int top,
         }
         __syncthreads();
     }
-    tail_sweeps64<MODEL, SINK, DIM>(A->lv[last], L, a, nuc);
+    tail_sweeps64<MODEL, SINK, DIM>(SL[last], L, a, nuc);
     for (int l = last - 1; l >= top; --l) {
-        const TailLevel &F = A->lv[l], &C = A->lv[l + 1];
+        const TailLevel &F = SL[l], &C = SL[l + 1];
         const NodeMap nf = tail_nm(F);
         for (unsigned long long t = threadIdx.x; t < (unsigned long long)F.g.N; t += blockDim.x) {
             int i, j, k;
@@ -440,6 +479,8 @@ __global__ __launch_bounds__(512) void k_vcycle_tail(const TailArgs *A, int top,
         __syncthreads();
         tail_sweeps64<MODEL, SINK, DIM>(F, L, a, nu2);
     }
+    if (top >= lds_from)
+        for (long long t = threadIdx.x; t < SL[top].g.N; t += blockDim.x) A->lv[top].psi[t] = SL[top].psi[t];
 }
 
 // ---------------------------------------------------------------------------
@@ -824,19 +865,31 @@ void launch_prolong(const Geo &gf, const Geo &gc, const double *psi_c, const dou
 
 struct TailLaunch {
     const TailArgs *A; int top, last; const Law &law; const Step &st; int nu1, nu2, nuc;
-    hipStream_t s;
+    int lds_from; size_t lds_bytes; hipStream_t s;
     template <int M, bool S, int D>
     void go()
     {
-        hipLaunchKernelGGL((k_vcycle_tail<M, S, D>), dim3(1), dim3(512), 0, s, A, top, last, law,
-                           st, nu1, nu2, nuc);
+        hipLaunchKernelGGL((k_vcycle_tail<M, S, D>), dim3(1), dim3(512), lds_bytes, s, A, top, last,
+                           law, st, nu1, nu2, nuc, lds_from);
     }
 };
 
-void launch_vcycle_tail(const TailArgs *args_dev, int top, int last, const Law &law,
-                        const Step &st, int nu1, int nu2, int nuc, int dim, hipStream_t s)
+size_t tail_lds_bytes(const long long *nodes, int top, int from, int last)
 {
-    dispatch<true>(law, dim, TailLaunch{args_dev, top, last, law, st, nu1, nu2, nuc, s});
+    size_t b = 0;
+    for (int l = from; l <= last; ++l) b += (l == top ? 4 : 5) * sizeof(double) * (size_t)(nodes[l] + 2);
+    return b;
+}
+
+void launch_vcycle_tail(const TailArgs *args_dev, int top, int last, const Law &law,
+                        const Step &st, int nu1, int nu2, int nuc, int dim, const long long *nodes,
+                        hipStream_t s)
+{
+    // the deepest levels that fit in kTailLds bytes of LDS
+    int from = last + 1;
+    while (from - 1 >= top && tail_lds_bytes(nodes, top, from - 1, last) <= kTailLds) --from;
+    const size_t bytes = from <= last ? tail_lds_bytes(nodes, top, from, last) : 0;
+    dispatch<true>(law, dim, TailLaunch{args_dev, top, last, law, st, nu1, nu2, nuc, from, bytes, s});
 }
 
 void launch_interp(const Geo &gf, const Geo &gc, const double *psi_c, double *psi_f, hipStream_t s)

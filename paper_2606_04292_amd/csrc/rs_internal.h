@@ -94,8 +94,11 @@ struct TailArgs {
 // ---------------------------------------------------------------------------
 // The V-cycle from level top (all of whose levels hold at most kTailNodes
 // nodes) down to level last and back, in one work-group.
+// nodes[l]: node count of level l (sizes the LDS copy of the deepest levels).
 void launch_vcycle_tail(const TailArgs *args_dev, int top, int last, const Law &law,
-                        const Step &st, int nu1, int nu2, int nuc, int dim, hipStream_t s);
+                        const Step &st, int nu1, int nu2, int nuc, int dim, const long long *nodes,
+                        hipStream_t s);
+constexpr size_t kTailLds = 56 * 1024;   // LDS for the deepest levels of that cycle
 void launch_fill_u64(unsigned long long *p, int n, unsigned long long v, hipStream_t s);
 void launch_setup_kstar(const Geo &g, const Law &law, const Step &st, const double *psi_n,
                         const double *psi_nm1, const double *Ks_field, double *K, double *psi,
