@@ -449,12 +449,16 @@ int read_norm(rs_grid *G, double *out)
     return RS_OK;
 }
 
-// FP64 defect max-norm of the finest level (and the defect vector into d).
-int fine_norm(rs_grid *G, double *out, double *d = nullptr)
+// FP64 defect max-norm of the finest level (and the defect vector into d; or,
+// with mp_start, the start of an FP32 correction: rhs = fl32(defect),
+// psi_b = fl32(psi), delta = 0).
+int fine_norm(rs_grid *G, double *out, double *d = nullptr, bool mp_start = false)
 {
     LevelData &f = G->lev[0];
     launch_fill_u64(G->scratch, 1, 0ull, G->stream);
-    launch_residual(f.geo, G->law, G->step, f.beta, f.K, f.g, f.psi, d, G->scratch, G->stream);
+    MpStart mp{};
+    if (mp_start) mp = MpStart{f.rhs32, f.pb32, f.dl};
+    launch_residual(f.geo, G->law, G->step, f.beta, f.K, f.g, f.psi, d, G->scratch, G->stream, mp);
     HIPCALL(hipGetLastError());
     return read_norm(G, out);
 }
@@ -503,12 +507,13 @@ void vcycle32_level(rs_grid *G, int l, int nu1, int nu2)
     sweep32_level(G, l, nu2);
 }
 
-// One outer defect correction: the FP64 defect is in lev[0].d; FP32 cycles
-// solve the correction equation and psi += delta in FP64.
+// One outer defect correction: the defect kernel has already written the FP32
+// right-hand side fl32(r), the base state fl32(psi) and delta = 0 on the finest
+// level (fine_norm with mp_start); FP32 cycles solve the correction equation
+// and psi += delta in FP64.
 void mp_correction(rs_grid *G, int inner, int nu1, int nu2)
 {
     LevelData &f = G->lev[0];
-    launch_mp_prep(f.geo.N, f.d, f.psi, f.rhs32, f.dl, f.pb32, G->stream);
     for (int l = 1; l < G->nlev; ++l)
         launch_inject32(G->lev[l].geo, G->lev[l - 1].geo, G->lev[l - 1].pb32, G->lev[l].pb32,
                         G->stream);
@@ -882,7 +887,7 @@ int rs_correction_cycle(rs_grid *G, int inner_cycles, int nu1, int nu2, double *
     if (!G->in_step) return fail(RS_ESTATE, "no active step (call rs_begin_step)");
     if (inner_cycles < 1 || nu1 < 0 || nu2 < 0) return fail(RS_EINVAL, "bad cycle counts");
     double r;
-    int e = fine_norm(G, &r, G->lev[0].d);
+    int e = fine_norm(G, &r, nullptr, true);
     if (e) return e;
     mp_correction(G, inner_cycles, nu1, nu2);
     HIPCALL(hipGetLastError());
@@ -947,7 +952,7 @@ int rs_bdf_step(rs_grid *G, double dt, int order, const rs_solve_opts *o, rs_ste
     G->updates = 0.0;
     const bool mixed = G->precision == RS_MIXED;
     if (mixed) {
-        e = fine_norm(G, &r, G->lev[0].d);   // defect vector for the first correction
+        e = fine_norm(G, &r, nullptr, true);   // defect vector for the first correction
         if (e) return e;
     }
     while (std::isfinite(r) && r > o->tol_abs && cycles < o->max_cycles) {
@@ -962,7 +967,7 @@ int rs_bdf_step(rs_grid *G, double dt, int order, const rs_solve_opts *o, rs_ste
         }
         HIPCALL(hipGetLastError());
         double rn;
-        e = fine_norm(G, &rn, mixed ? G->lev[0].d : nullptr);
+        e = fine_norm(G, &rn, nullptr, mixed);
         if (e) return e;
         ++cycles;
         if (nh < 64) hist[nh++] = rn;

@@ -528,7 +528,8 @@ template <int MODEL, bool SINK, int DIM>
 __global__ __launch_bounds__(256) void k_residual_pair(Geo g, Law L, Step st, const double *beta,
                                                        const double *K, const double *gv,
                                                        const double *psi, double *d,
-                                                       unsigned long long *norm_bits, ColourMap cm)
+                                                       unsigned long long *norm_bits, ColourMap cm,
+                                                       MpStart mp)
 {
     double v = 0.0;
     const unsigned long long t =
@@ -602,6 +603,14 @@ __global__ __launch_bounds__(256) void k_residual_pair(Geo g, Law L, Step st, co
         if (d) {
             d[idx0] = r[0];
             if (i0 + 1 < g.n[0]) d[idx0 + 1] = r[1];
+        }
+        if (mp.rhs) {
+            for (int a = 0; a < 2; ++a) {
+                if (i0 + a >= g.n[0]) break;
+                mp.rhs[idx0 + a] = (float)r[a];
+                mp.pb[idx0 + a] = (float)P[1 + a];
+                mp.dl[idx0 + a] = 0.0f;
+            }
         }
         const double a0 = fabs(r[0]), a1 = fabs(r[1]);
         v = (a1 > a0 || a1 != a1) ? a1 : a0;
@@ -813,12 +822,13 @@ struct CoarseRhsLaunch {
 struct ResidualLaunch {
     const Geo &g; const Law &law; const Step &st; const double *beta; const double *K;
     const double *gvec; const double *psi; double *d; unsigned long long *norm_bits; hipStream_t s;
+    MpStart mp;
     template <int M, bool S, int D>
     void go()
     {
         const ColourMap cm = colour_map(g);
         hipLaunchKernelGGL((k_residual_pair<M, S, D>), dim3(xcd_grid((cm.total + 255) / 256)),
-                           dim3(256), 0, s, g, law, st, beta, K, gvec, psi, d, norm_bits, cm);
+                           dim3(256), 0, s, g, law, st, beta, K, gvec, psi, d, norm_bits, cm, mp);
     }
 };
 
@@ -839,9 +849,9 @@ bool fused_sweep_level(const Geo &g)
 
 void launch_residual(const Geo &g, const Law &law, const Step &st, const double *beta,
                      const double *K, const double *gvec, const double *psi, double *d,
-                     unsigned long long *norm_bits, hipStream_t s)
+                     unsigned long long *norm_bits, hipStream_t s, MpStart mp)
 {
-    dispatch<true>(law, g.dim, ResidualLaunch{g, law, st, beta, K, gvec, psi, d, norm_bits, s});
+    dispatch<true>(law, g.dim, ResidualLaunch{g, law, st, beta, K, gvec, psi, d, norm_bits, s, mp});
 }
 
 void launch_restrict(const Geo &gc, const Geo &gf, const double *psi_f, const double *d_f,

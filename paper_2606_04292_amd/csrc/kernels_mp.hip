@@ -102,19 +102,6 @@ __global__ __launch_bounds__(256) void k_coarse_rhs32(Geo g, Law32 L, float a, c
     dl[idx] = dbar[idx];
 }
 
-// Start of an outer correction on the finest level: rhs = fl32(FP64 defect),
-// delta = 0, psi_b = fl32(psi).
-__global__ __launch_bounds__(256) void k_mp_prep(long long N, const double *d64,
-                                                 const double *psi64, float *rhs, float *dl,
-                                                 float *pb)
-{
-    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= N) return;
-    rhs[t] = (float)d64[t];
-    dl[t] = 0.0f;
-    pb[t] = (float)psi64[t];
-}
-
 __global__ __launch_bounds__(256) void k_to_f32(long long N, const double *src, float *dst)
 {
     long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -251,12 +238,6 @@ void launch_prolong32(const Geo &gf, const Geo &gc, const float *dl_c, const flo
 void launch_inject32(const Geo &gc, const Geo &gf, const float *vf, float *vc, hipStream_t s)
 {
     hipLaunchKernelGGL((k_inject_t<float>), node_grid(gc), dim3(kBX, kBY), 0, s, gc, gf, vf, vc);
-}
-
-void launch_mp_prep(long long N, const double *d64, const double *psi64, float *rhs, float *dl,
-                    float *pb, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_mp_prep, dim3(blocks_for(N)), dim3(256), 0, s, N, d64, psi64, rhs, dl, pb);
 }
 
 void launch_to_f32(long long N, const double *src, float *dst, hipStream_t s)

@@ -20,8 +20,6 @@ void launch_restrict32(const Geo &gc, const Geo &gf, const float *dl_f, const fl
 void launch_prolong32(const Geo &gf, const Geo &gc, const float *dl_c, const float *dbar_c,
                       float *dl_f, hipStream_t s);
 void launch_inject32(const Geo &gc, const Geo &gf, const float *vf, float *vc, hipStream_t s);
-void launch_mp_prep(long long N, const double *d64, const double *psi64, float *rhs, float *dl,
-                    float *pb, hipStream_t s);
 void launch_to_f32(long long N, const double *src, float *dst, hipStream_t s);
 void launch_apply_delta(long long N, const float *dl, double *psi64, hipStream_t s);
 

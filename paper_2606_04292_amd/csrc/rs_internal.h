@@ -117,9 +117,14 @@ int launch_sweep_rb(const Geo &g, const Law &law, const Step &st, const double *
 // Levels that get a second psi buffer for the fused sweep.
 constexpr long long kFusedMinNodes = 33LL * 33 * 33;
 bool fused_sweep_level(const Geo &g);
+// Start of an FP32 correction (mixed precision) written by the defect kernel:
+// rhs = fl32(defect), psi_b = fl32(psi), delta = 0 on every node.
+struct MpStart {
+    float *rhs, *pb, *dl;
+};
 void launch_residual(const Geo &g, const Law &law, const Step &st, const double *beta,
                      const double *K, const double *gvec, const double *psi, double *d,
-                     unsigned long long *norm_bits, hipStream_t s);
+                     unsigned long long *norm_bits, hipStream_t s, MpStart mp = {});
 void launch_restrict(const Geo &gc, const Geo &gf, const double *psi_f, const double *d_f,
                      double *psibar_c, double *g_c, hipStream_t s);
 void launch_coarse_rhs(const Geo &gc, const Law &law, const Step &st, const double *beta,
