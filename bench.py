@@ -299,7 +299,8 @@ def paper_2d_table(args):
     ||r||_inf <= 1e-10 or the rounding floor: the Gardner infiltration
     (129^2, tau 0.1 day, 3 days, V(5,5)) whose CPU time the paper prints
     (context only: unstated hardware), and the two-layer vGM medium (257^2,
-    tau 0.01 day, to 1.75 days, an FMG(10,10) cycle then V(10,10) cycles)."""
+    tau 0.01 day, to 1.75 days, an FMG(10,10) cycle then V(10,10) cycles); each
+    also with GS(100), 100 red-black sweeps per step, against the multigrid result."""
     import torch
     import paper_2606_04292_amd as rsl
     from paper_2606_04292_amd import workloads as W
@@ -331,6 +332,22 @@ def paper_2d_table(args):
         if ctx is not None:
             out[key]["paper_cpu_seconds_context"] = ctx
         log("%s: %.2f s, %.2f cycles/step" % (key, el, cyc / w.steps))
+        ref = G.get_state()[0].cpu().numpy()
+        G.close()
+        # the paper's GS(k) comparison: k = 100 red-black sweeps per step
+        G = rsl.Grid(w, device="cuda:0")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(w.steps):
+            G.begin_step()
+            G.sweep(100)
+            G.end_step()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        gs = G.get_state()[0].cpu().numpy()
+        out[key]["GS(100)"] = {"seconds": round(el, 3),
+                               "max_diff_vs_multigrid": float(abs(gs - ref).max() / abs(ref).max())}
+        log("%s GS(100): %.2f s" % (key, el))
         G.close()
     return out
 
