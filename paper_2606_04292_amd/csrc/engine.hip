@@ -270,7 +270,7 @@ __global__ __launch_bounds__(256) void e_defect(const EList *FL, const ESlot *sl
         double r = 0.0;
         if (!dirichlet_at(L0.geo, i, j, k, nullptr)) {
             law_dim(S.law.model, L0.geo.dim, [&](auto M, auto Dm) {
-                r = S.g[t] - apply_N_t<decltype(M)::value, false, decltype(Dm)::value>(
+                r = S.g[t] - apply_N_t<decltype(M)::value, false, decltype(Dm)::value, true>(
                                  L0.geo, S.law, a, nullptr, S.K, S.psi, i, j, k, (long long)t);
             });
         }
@@ -382,7 +382,7 @@ __global__ __launch_bounds__(256) void e_sweep32(const EList *DL, const ESlot *s
         if (dirichlet_at(Lv.geo, i, j, k, nullptr)) return;
         const float a = (float)dyn[s].a;
         law_dim(S.law.model, Lv.geo.dim, [&](auto M, auto Dm) {
-            ngs_cell32<decltype(M)::value, false, decltype(Dm)::value>(
+            ngs_cell32<decltype(M)::value, false, decltype(Dm)::value, true>(
                 Lv.geo, S.law32, a, nullptr, 0.0f, Lv.K32, Lv.rhs, Lv.pb, Lv.dl, i, j, k, colour);
         });
     }, NoFlush{});
@@ -668,6 +668,8 @@ CtrlLayout ctrl_layout(const rs_engine_opts &o)
     return c;
 }
 
+constexpr size_t kReqPad = 256;
+
 struct ReqPlan {
     int nlev, wide;
     Geo geo[kEngMaxLevels];
@@ -698,17 +700,20 @@ int plan_request(const rs_engine_opts &o, const rs_grid_desc *d, ReqPlan *p)
     if (p->wide > o.max_wide_levels)
         return fail(RS_EINVAL, "request has %d levels above tail_nodes; the engine runs %d",
                     p->wide, o.max_wide_levels);
+    // every array with kReqPad zeroed bytes before and after it (the region is
+    // cleared at admission), so the wide-level stencils can load the row
+    // neighbours idx -/+ 1 unconditionally
     size_t off = 0;
+    auto place = [&](size_t bytes) {
+        off = align_up(off + kReqPad);
+        const size_t at = off;
+        off = align_up(off + bytes + kReqPad);
+        return at;
+    };
     const size_t N0 = (size_t)p->geo[0].N;
-    for (int a = 0; a < 5; ++a) {
-        p->fine_off[a] = off;
-        off = align_up(off + sizeof(double) * N0);
-    }
+    for (int a = 0; a < 5; ++a) p->fine_off[a] = place(sizeof(double) * N0);
     for (int l = 0; l < p->nlev; ++l)
-        for (int a = 0; a < 6; ++a) {
-            p->lev_off[l][a] = off;
-            off = align_up(off + sizeof(float) * (size_t)p->geo[l].N);
-        }
+        for (int a = 0; a < 6; ++a) p->lev_off[l][a] = place(sizeof(float) * (size_t)p->geo[l].N);
     p->bytes = off;
     return RS_OK;
 }
@@ -1073,6 +1078,8 @@ int rs_engine_submit(rs_engine *E, const rs_grid_desc *d, const rs_constitutive 
     D.order_eff = 1;
     D.a = 1.0 / dt;
     const size_t nb = sizeof(double) * (size_t)P.geo[0].N;
+    // zero padding around every array (and the arrays themselves)
+    HIPCALL(hipMemsetAsync(mem, 0, P.bytes, E->stream));
     HIPCALL(hipMemcpyAsync(S.psi_n, psi0_dev, nb, hipMemcpyDeviceToDevice, E->stream));
     HIPCALL(hipMemcpyAsync(S.psi_nm1, psi0_dev, nb, hipMemcpyDeviceToDevice, E->stream));
     HIPCALL(hipMemcpyAsync(E->d_slots + s, &S, sizeof S, hipMemcpyHostToDevice, E->stream));

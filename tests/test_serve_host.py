@@ -32,7 +32,8 @@ def test_request_footprint_is_fine_fp64_plus_fp32_levels():
             n = [(m - 1) // 2 + 1 for m in n]
             shapes.append(n)
         N = [int(__import__("numpy").prod(s)) for s in shapes]
-        want = 5 * align(8 * N[0]) + sum(6 * align(4 * m) for m in N)
+        # each array is placed with 256 zeroed bytes before and after it
+        want = 5 * (align(8 * N[0]) + 512) + sum(6 * (align(4 * m) + 512) for m in N)
         assert nb == want
 
 
