@@ -81,7 +81,8 @@ int rs_engine_control_bytes(const rs_engine_opts *o, size_t *out);
 
 /* Arena bytes one request of grid d occupies while resident: fine-level FP64
  * psi, psi^n, psi^{n-1}, K*, g and six FP32 arrays per level, each 256-byte
- * aligned.  Admission compares this against the arena's free space. */
+ * aligned with 256 zeroed bytes before and after it.  Admission compares this
+ * against the arena's free space. */
 int rs_engine_request_bytes(const rs_engine_opts *o, const rs_grid_desc *d, size_t *out);
 
 /* Create an engine over the caller's device arena (arena_dev, arena_bytes,
