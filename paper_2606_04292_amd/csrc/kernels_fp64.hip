@@ -487,42 +487,10 @@ __global__ __launch_bounds__(512) void k_vcycle_tail(const TailArgs *A, int top,
 // Defect d = g - N(psi) and its max-norm (step 2 of the FAS algorithm)
 // ---------------------------------------------------------------------------
 
-// One node per thread (work-groups numbered per XCD); the block maximum goes
-// to the running maximum.
-template <int MODEL, bool SINK, int DIM>
-__global__ __launch_bounds__(256) void k_residual(Geo g, Law L, Step st, const double *beta,
-                                                  const double *K, const double *gv,
-                                                  const double *psi, double *d,
-                                                  unsigned long long *norm_bits, NodeMap nm)
-{
-    double v = 0.0;
-    const unsigned long long t =
-        (unsigned long long)xcd_block(gridDim.x / 8u) * blockDim.x + threadIdx.x;
-    if (t < (unsigned long long)g.N) {
-        int i, j, k;
-        node_ijk(nm, t, i, j, k);
-        double r = 0.0;
-        if (!dirichlet_at(g, i, j, k, nullptr))
-            r = gv[t] - apply_N_t<MODEL, SINK, DIM, true>(g, L, st.a, beta, K, psi, i, j, k, (long long)t);
-        if (d) d[t] = r;
-        v = fabs(r);
-    }
-    if (norm_bits) {
-        v = block_max(v);
-        if (threadIdx.x == 0) {
-            // the bits of non-negative doubles (and NaN) order like their values;
-            // most groups do not raise the running max and skip the atomic
-            const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
-            if (bits > __hip_atomic_load(norm_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-                atomicMax(norm_bits, bits);
-        }
-    }
-}
-
-// The same defect for two neighbouring nodes of a row per thread (i = 2 ih,
-// 2 ih + 1): both stencils are loaded as pairs of adjacent values, so a row
-// window of four values and every off-row pair become wide loads, and the two
-// theta chains overlap.  Each node's arithmetic is that of apply_N_t with
+// Two neighbouring nodes of a row per thread (i = 2 ih, 2 ih + 1): both
+// stencils are loaded as pairs of adjacent values, so a row window of four
+// values and every off-row pair become wide loads, and the two theta chains
+// overlap.  Each node's arithmetic is that of apply_N_t with
 // XPAD.  Slots are those of the colour packing (H = (n0 + 1) / 2 per row).
 template <int MODEL, bool SINK, int DIM>
 __global__ __launch_bounds__(256) void k_residual_pair(Geo g, Law L, Step st, const double *beta,
