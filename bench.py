@@ -352,6 +352,49 @@ def paper_2d_table(args):
     return out
 
 
+def paper_order(args):
+    """The paper's temporal-order study of the 1-D infiltration (section 4.1):
+    N = 1024 with tau = 0.1 / 2^k, k = 0..5, against a reference on N = 2048
+    with tau = 1e-4, at t = args.order_t seconds; L-infinity errors on the
+    common nodes and the observed orders log2(e_k / e_{k+1}).  Each step
+    V(5,5) cycles to ||r||_inf <= 1e-10 or the rounding floor."""
+    import dataclasses
+    import math
+    import numpy as np
+    import torch
+    import paper_2606_04292_amd as rsl
+    from paper_2606_04292_amd import workloads as W
+
+    def run(n, dt):
+        steps = int(round(args.order_t / dt))
+        w = dataclasses.replace(W.celia_column(n), dt=dt, steps=steps)
+        G = rsl.Grid(w, device="cuda:0")
+        opts = rsl.solve_opts(5, 5, 32, max_cycles=100, tol_abs=1e-10, stagnation=1)
+        for _ in range(steps):
+            code, _ = G.bdf_step(opts=opts)
+            if code != rsl.RS_OK:
+                raise SystemExit("order study step failed: " + rsl.lib().rs_last_error().decode())
+        psi = G.get_state()[0].cpu().numpy()
+        G.close()
+        return psi, steps
+
+    t0 = time.perf_counter()
+    ref, nref = run(2049, 1e-4)
+    log("order study reference: %d steps, %.1f s" % (nref, time.perf_counter() - t0))
+    out = {"workload": "celia_column: N = 1024 vs N = 2048 reference (tau 1e-4), t = %g s" % args.order_t,
+           "tau": [], "linf_error": [], "observed_order": []}
+    for k in range(6):
+        dt = 0.1 / 2 ** k
+        psi, _ = run(1025, dt)
+        out["tau"].append(dt)
+        out["linf_error"].append(float(np.abs(psi - ref[::2]).max()))
+        log("order study tau %.5f: error %.3e" % (dt, out["linf_error"][-1]))
+    e = out["linf_error"]
+    out["observed_order"] = [math.log2(e[k] / e[k + 1]) for k in range(len(e) - 1)]
+    out["seconds"] = round(time.perf_counter() - t0, 1)
+    return out
+
+
 def cpu_baseline(args, n):
     import numpy as np
     import oracle
@@ -400,6 +443,9 @@ def main():
     ap.add_argument("--paper-2d", action="store_true",
                     help="run only the paper's 2-D cases (Gardner infiltration, two-layer medium)")
     ap.add_argument("--paper-2d-steps", type=int, default=175)
+    ap.add_argument("--paper-order", action="store_true",
+                    help="run only the paper's temporal-order study of the 1-D infiltration")
+    ap.add_argument("--order-t", type=float, default=10.0, help="final time of the order study (s)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 512 MiB device copy first (counter calibration)")
     args = ap.parse_args()
@@ -416,6 +462,9 @@ def main():
         return
     if args.paper_2d:
         print(json.dumps({"paper_2d_table": paper_2d_table(args)}), flush=True)
+        return
+    if args.paper_order:
+        print(json.dumps({"paper_order_study": paper_order(args)}), flush=True)
         return
     r = gpu_run(args)
     w = r["w"]
