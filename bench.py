@@ -285,6 +285,22 @@ def paper_1d_table(args):
     el = time.perf_counter() - t0
     gs = G.get_state()[0].cpu().numpy()
     out["GS(100)"] = {"seconds": round(el, 3)}
+    # the layered column of the same section (Gardner / Haverkamp / vGM zones)
+    wc = W.celia_composite(2049)
+    G2 = rsl.Grid(wc, device="cuda:0")
+    opts = rsl.solve_opts(5, 5, 32, max_cycles=60, tol_abs=1e-12, stagnation=0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    cyc = 0
+    for _ in range(steps):
+        code, st = G2.bdf_step(opts=opts)
+        if code != rsl.RS_OK:
+            raise SystemExit("composite step failed: " + rsl.lib().rs_last_error().decode())
+        cyc += st.cycles
+    torch.cuda.synchronize()
+    out["V-cycle(5,5), layered column"] = {"seconds": round(time.perf_counter() - t1, 3),
+                                            "cycles_per_step": round(cyc / steps, 2)}
+    G2.close()
     ref = finals["V-cycle(5,5)"]
     scale = float(abs(ref).max())
     out["max_diff_vs_vcycle"] = {"FMG(5,5)": float(abs(finals["FMG(5,5)"] - ref).max()) / scale,
