@@ -101,63 +101,15 @@ __global__ __launch_bounds__(256) void k_lambda_u(Geo g, const double *K, unsign
 // Red-black NGS (eq. iterative / eq. point-update)
 // ---------------------------------------------------------------------------
 
-// New value of unknown (i, j, k) from eq. point-update: f_i = g_i +
-// sum_j m_ij psi_j + kappa_i psi_i, c_i = xi + kappa_i + m_ii, then the
-// safeguarded Newton solve.  nbv(jdx, axis, side) supplies the current value of
-// each neighbour (the previous colour's new values, the other colour's old).
-template <int MODEL, bool SINK, int DIM, typename NbVal>
-__device__ __forceinline__ double ngs_value(const Geo &g, const Law &L, double a,
-                                            const double *beta, double lambdaU, const double *K,
-                                            const double *gv, int i, int j, int k, long long idx,
-                                            int colour, double x0, NbVal &&nbv)
-{
-    const double Ki = K[idx];
-    double f = gv[idx];
-    double mii = 0.0, usum = 0.0;
-    const bool remark = (L.kappa_rule == kKappaRemark) && colour == 0;
-    for_nb<DIM>(g, i, j, k, idx, [&](long long jn, double cf, int l, int side) {
-        double m = cf * (Ki + K[jn]);
-        mii += m;
-        f += m * nbv(jn, l, side);
-        if (remark) {
-            int d[3] = {i, j, k};
-            d[l] += side;
-            if (!dirichlet_at(g, d[0], d[1], d[2], nullptr)) usum += m;
-        }
-    });
-    double kap;
-    if (L.kappa_rule == kKappaConst) kap = L.kappa;
-    else if (L.kappa_rule == kKappaRel) kap = L.kappa * mii;
-    else kap = (colour == 0) ? lambdaU - usum : lambdaU;
-    f += kap * x0;
-    const double cc = L.xi + kap + mii;
-    const int vk = (DIM == 1) ? i : (DIM == 2 ? j : k);
-    const double b = SINK ? beta[vk] : 0.0;
-    if constexpr (MODEL == kMulti) {
-        const Law &Ls = L.soils[g.soil[idx]];
-        if (L.newton == 3) return local_solve_soil<SINK, 3>(Ls, a, b, cc, f, x0);
-        return local_solve_soil<SINK, 0>(Ls, a, b, cc, f, x0);
-    }
-    if (L.newton == 3) return local_solve_t<MODEL, SINK, 3>(L, a, b, cc, f, x0);
-    return local_solve_t<MODEL, SINK, 0>(L, a, b, cc, f, x0);
-}
-
+// New value of unknown (i, j, k) from gathered values (eq. point-update): the
+// stencil, K*_i, g_i, the old value x0 and the K* and current psi of the 2 DIM
+// neighbours (outside the domain: zero coefficient, any finite value).
 template <int MODEL, bool SINK, int DIM>
-__device__ __forceinline__ void ngs_cell(const Geo &g, const Law &L, double a, const double *beta,
-                                         double lambdaU, const double *K, const double *gv,
-                                         double *psi, int i, int j, int k, int colour)
+__device__ __forceinline__ double ngs_point(const Geo &g, const Law &L, double a, const double *beta,
+                                            double lambdaU, const Stencil<DIM> &st, double Ki,
+                                            const double *Kn, const double *pn, double f, double x0,
+                                            int i, int j, int k, long long idx, int colour)
 {
-    const long long idx = i + (long long)j * g.stride[1] + (long long)k * g.stride[2];
-    const Stencil<DIM> st = stencil<DIM, true>(g, i, j, k, idx);   // workspace arrays are padded
-    const double Ki = K[idx];
-    const double x0 = psi[idx];
-    double f = gv[idx];
-    double Kn[2 * DIM], pn[2 * DIM];
-#pragma unroll
-    for (int q = 0; q < 2 * DIM; ++q) {
-        Kn[q] = K[st.jn[q]];
-        pn[q] = psi[st.jn[q]];
-    }
     double mii = 0.0;
 #pragma unroll
     for (int q = 0; q < 2 * DIM; ++q) {
@@ -189,114 +141,148 @@ __device__ __forceinline__ void ngs_cell(const Geo &g, const Law &L, double a, c
     const double b = SINK ? beta[vk] : 0.0;
     if constexpr (MODEL == kMulti) {
         const Law &Ls = L.soils[g.soil[idx]];
-        psi[idx] = (L.newton == 3) ? local_solve_soil<SINK, 3>(Ls, a, b, cc, f, x0)
-                                   : local_solve_soil<SINK, 0>(Ls, a, b, cc, f, x0);
+        return (L.newton == 3) ? local_solve_soil<SINK, 3>(Ls, a, b, cc, f, x0)
+                               : local_solve_soil<SINK, 0>(Ls, a, b, cc, f, x0);
     } else {
-        psi[idx] = (L.newton == 3) ? local_solve_t<MODEL, SINK, 3>(L, a, b, cc, f, x0)
-                                   : local_solve_t<MODEL, SINK, 0>(L, a, b, cc, f, x0);
+        return (L.newton == 3) ? local_solve_t<MODEL, SINK, 3>(L, a, b, cc, f, x0)
+                               : local_solve_t<MODEL, SINK, 0>(L, a, b, cc, f, x0);
     }
 }
 
+template <int MODEL, bool SINK, int DIM>
+__device__ __forceinline__ void ngs_cell(const Geo &g, const Law &L, double a, const double *beta,
+                                         double lambdaU, const double *K, const double *gv,
+                                         double *psi, int i, int j, int k, int colour)
+{
+    const long long idx = i + (long long)j * g.stride[1] + (long long)k * g.stride[2];
+    const Stencil<DIM> st = stencil<DIM, true>(g, i, j, k, idx);   // workspace arrays are padded
+    const double Ki = K[idx];
+    const double x0 = psi[idx];
+    const double f = gv[idx];
+    double Kn[2 * DIM], pn[2 * DIM];
+#pragma unroll
+    for (int q = 0; q < 2 * DIM; ++q) {
+        Kn[q] = K[st.jn[q]];
+        pn[q] = psi[st.jn[q]];
+    }
+    psi[idx] = ngs_point<MODEL, SINK, DIM>(g, L, a, beta, lambdaU, st, Ki, Kn, pn, f, x0, i, j, k,
+                                           idx, colour);
+}
+
 // ---------------------------------------------------------------------------
-// Fused red-black sweep for 3-D levels.  A work-group owns a tile
-// [X0,X1) x [Y0,Y1) of a z-chunk [Z0,Z1) and marches up it: at plane k it
-// computes the red values of plane k on the tile and a one-node ring around
-// it (the ring is recomputed by the neighbouring tiles too), keeping them in a
-// three-plane LDS ring, then the black values of plane k-1 on the tile from
-// those red values.  Red updates read the old values from pin, the new values
-// go to pout; every node of the level is written exactly once by its owner, so
-// there is no inter-group ordering and a sweep reads psi, K* and g once.
-// Work-groups are numbered so that each XCD gets a contiguous z-slab.
+// Fused red-black sweep for 3-D levels, marching along z.  Lane (lx, ly) of a
+// work-group owns the node pair x = 2p, 2p+1 of row y and walks up the
+// group's z-chunk; at plane z its active column c is the red one
+// (c + y + z even).  Step z computes the red value at (c, y, z) from old values,
+// then the black value at (c, y, z-1), whose neighbours are all new red values:
+// those of plane z-1 from LDS (written in the previous step by the lanes that
+// own them), and the lane's own red values of planes z-2 and z.  A ring of
+// lanes around the tile recomputes the red values that the tile's black nodes
+// need from the neighbouring tiles, and the first step of a chunk recomputes
+// the red plane below it; these are not stored.  Old values come from pin and
+// new ones go to pout, each node written once by the tile that owns it: no
+// ordering between work-groups, and a sweep reads psi, K* and g once (plus the
+// halo).  The per-node arithmetic is that of the two-pass sweep (ngs_point),
+// so the two agree to rounding (the compiler may fuse multiply-adds
+// differently in the two kernels).
 // ---------------------------------------------------------------------------
 
 struct FusedMap {
-    int TX, TY, ZC;      // base tile extent (the last tile on an axis takes the remainder)
+    int LX, LY, ZC;      // lane grid (pairs x rows, ring included), planes per chunk
     int ntx, nty, ntz;
     int nwg, per;        // work-groups, logical groups per XCD
-    int P, Hs;           // LDS plane pitch and rows
 };
 
 template <int MODEL, bool SINK>
-__global__ __launch_bounds__(256) void k_sweep_fused(Geo g, Law L, Step st, const double *beta,
+__global__ __launch_bounds__(512) void k_sweep_fused(Geo g, Law L, Step st, const double *beta,
                                                      double lambdaU, const double *K,
                                                      const double *gv, const double *pin,
                                                      double *pout, FusedMap fm)
 {
-    extern __shared__ double red[];
-    const unsigned b = (blockIdx.x % 8u) * (unsigned)fm.per + blockIdx.x / 8u;
+    extern __shared__ double red[];   // two planes of LX pairs x LY rows
+    const unsigned b = xcd_block((unsigned)fm.per);
     if ((int)b >= fm.nwg) return;
     const int bx = (int)b % fm.ntx;
     const int rest = (int)b / fm.ntx;
     const int by = rest % fm.nty;
     const int bz = rest / fm.nty;
     const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
-    const int X0 = bx * fm.TX, X1 = (bx == fm.ntx - 1) ? n0 : X0 + fm.TX;
-    const int Y0 = by * fm.TY, Y1 = (by == fm.nty - 1) ? n1 : Y0 + fm.TY;
-    const int Z0 = bz * fm.ZC, Z1 = (bz == fm.ntz - 1) ? n2 : Z0 + fm.ZC;
-    const int EX0 = X0 > 0 ? X0 - 1 : 0, EX1 = X1 < n0 ? X1 + 1 : n0;
-    const int EY0 = Y0 > 0 ? Y0 - 1 : 0, EY1 = Y1 < n1 ? Y1 + 1 : n1;
-    const int slot_sz = fm.P * fm.Hs;
-    const long long s1 = g.stride[1], s2 = g.stride[2];
+    const int IX = fm.LX - 2, IY = fm.LY - 2;
+    const int P0 = bx * IX, Y0 = by * IY, Z0 = bz * fm.ZC;
+    const int X0 = 2 * P0;
+    const int X1 = min(2 * (P0 + IX), n0), Y1 = min(Y0 + IY, n1), Z1 = min(Z0 + fm.ZC, n2);
     const int tid = threadIdx.x;
-    const int kfirst = Z0 > 0 ? Z0 - 1 : 0;
-    const int klast = Z1 < n2 ? Z1 : n2 - 1;
+    const int lx = tid % fm.LX, ly = tid / fm.LX;
+    const int p = P0 - 1 + lx, y = Y0 - 1 + ly;
+    const int W = 2 * fm.LX, slot = W * fm.LY;
+    for (int q = tid; q < 2 * slot; q += blockDim.x) red[q] = 0.0;
 
-    for (int k = kfirst; k <= Z1; ++k) {
-        if (k <= klast) {
-            // red nodes of plane k: tile plus ring inside the chunk, tile only
-            // on the extra planes below and above it
-            const bool inner = (k >= Z0 && k < Z1);
-            const int rx0 = inner ? EX0 : X0, rx1 = inner ? EX1 : X1;
-            const int ry0 = inner ? EY0 : Y0, ry1 = inner ? EY1 : Y1;
-            const int ps = (rx1 - rx0 + 1) >> 1;
-            const int nq = ps * (ry1 - ry0);
-            double *slot = red + (k % 3) * slot_sz;
-            for (int q = tid; q < nq; q += blockDim.x) {
-                const int r = q / ps;
-                const int y = ry0 + r;
-                const int x = rx0 + ((rx0 + y + k) & 1) + 2 * (q - r * ps);
-                if (x >= rx1) continue;
-                const long long idx = x + y * s1 + k * s2;
-                const double old = pin[idx];
-                double v = old;
-                if (!dirichlet_at(g, x, y, k, nullptr))
-                    v = ngs_value<MODEL, SINK, 3>(g, L, st.a, beta, lambdaU, K, gv, x, y, k, idx, 0,
-                                                  old,
-                                                  [&](long long jn, int, int) { return pin[jn]; });
-                slot[(y - EY0) * fm.P + (x - EX0)] = v;
-                if (inner && x >= X0 && x < X1 && y >= Y0 && y < Y1) pout[idx] = v;
-            }
-        }
-        __syncthreads();
-        const int kb = k - 1;
-        if (kb >= Z0 && kb < Z1) {
-            // black nodes of plane kb on the tile, red neighbours from LDS
-            const double *sl_m = red + ((kb + 2) % 3) * slot_sz;   // plane kb-1
-            const double *sl_0 = red + (kb % 3) * slot_sz;         // plane kb
-            const double *sl_p = red + ((kb + 1) % 3) * slot_sz;   // plane kb+1
-            const int ps = (X1 - X0 + 1) >> 1;
-            const int nq = ps * (Y1 - Y0);
-            for (int q = tid; q < nq; q += blockDim.x) {
-                const int r = q / ps;
-                const int y = Y0 + r;
-                const int x = X0 + ((X0 + y + kb + 1) & 1) + 2 * (q - r * ps);
-                if (x >= X1) continue;
-                const long long idx = x + y * s1 + kb * s2;
-                const double old = pin[idx];
-                double v = old;
-                if (!dirichlet_at(g, x, y, kb, nullptr)) {
-                    const int c = (y - EY0) * fm.P + (x - EX0);
-                    v = ngs_value<MODEL, SINK, 3>(
-                        g, L, st.a, beta, lambdaU, K, gv, x, y, kb, idx, 1, old,
-                        [&](long long, int l, int side) {
-                            if (l == 0) return sl_0[c + side];
-                            if (l == 1) return sl_0[c + side * fm.P];
-                            return side < 0 ? sl_m[c] : sl_p[c];
-                        });
+    const bool in_x = lx >= 1 && lx <= IX && 2 * p < n0;
+    const bool in_y = ly >= 1 && ly <= IY && y < n1;
+    const bool interior = in_x && in_y;
+    // ring lanes: the column left or right of the tile, or the row below or
+    // above it (ring_col < 0: whichever column of the pair is red)
+    bool ring = false;
+    int ring_col = -1;
+    if (in_y && lx == 0 && X0 > 0) { ring = true; ring_col = X0 - 1; }
+    if (in_y && lx == IX + 1 && X1 < n0) { ring = true; ring_col = X1; }
+    if (in_x && ((ly == 0 && Y0 > 0) || (ly == IY + 1 && Y1 < n1))) ring = true;
+    const long long s1 = g.stride[1], s2 = g.stride[2];
+    const int xo = ly * W - (X0 - 2);   // LDS offset of (x, y) is xo + x
+    __syncthreads();
+
+    double r1 = 0.0, r2 = 0.0;   // own red values of the last two steps
+    for (int z = (Z0 > 0 ? Z0 - 1 : 0); z <= Z1; ++z) {
+        const int c = 2 * p + ((y + z) & 1);
+        double rz = 0.0;
+        const bool do_red = z < n2 && c < n0 &&
+                            (interior || (ring && z >= Z0 && z < Z1 && (ring_col < 0 || ring_col == c)));
+        if (do_red) {
+            const long long idx = c + y * s1 + z * s2;
+            const double x0 = pin[idx];
+            rz = x0;
+            if (!dirichlet_at(g, c, y, z, nullptr)) {
+                const Stencil<3> sn = stencil<3, true>(g, c, y, z, idx);
+                const double Ki = K[idx];
+                const double f = gv[idx];
+                double Kn[6], pn[6];
+#pragma unroll
+                for (int q = 0; q < 6; ++q) {
+                    Kn[q] = K[sn.jn[q]];
+                    pn[q] = pin[sn.jn[q]];
                 }
-                pout[idx] = v;
+                rz = ngs_point<MODEL, SINK, 3>(g, L, st.a, beta, lambdaU, sn, Ki, Kn, pn, f, x0, c,
+                                               y, z, idx, 0);
             }
+            red[(z & 1) * slot + xo + c] = rz;
+            if (interior && z >= Z0 && z < Z1) pout[idx] = rz;
         }
+        const int zb = z - 1;
+        if (interior && zb >= Z0 && zb < Z1 && c < n0) {
+            const long long idx = c + y * s1 + zb * s2;
+            const double x0 = pin[idx];
+            double v = x0;
+            if (!dirichlet_at(g, c, y, zb, nullptr)) {
+                const Stencil<3> sn = stencil<3, true>(g, c, y, zb, idx);
+                const double Ki = K[idx];
+                const double f = gv[idx];
+                double Kn[6], pn[6];
+#pragma unroll
+                for (int q = 0; q < 6; ++q) Kn[q] = K[sn.jn[q]];
+                const double *sl = red + (zb & 1) * slot + xo + c;
+                pn[0] = sl[-1];
+                pn[1] = sl[1];
+                pn[2] = sl[-W];
+                pn[3] = sl[W];
+                pn[4] = r2;
+                pn[5] = rz;
+                v = ngs_point<MODEL, SINK, 3>(g, L, st.a, beta, lambdaU, sn, Ki, Kn, pn, f, x0, c,
+                                              y, zb, idx, 1);
+            }
+            pout[idx] = v;
+        }
+        r2 = r1;
+        r1 = rz;
         __syncthreads();
     }
 }
@@ -706,15 +692,15 @@ void launch_lambda_u(const Geo &g, const double *K, unsigned long long *out, hip
     hipLaunchKernelGGL(k_lambda_u, node_grid(g), dim3(kBX, kBY), 0, s, g, K, out);
 }
 
-// Tile extents of the fused sweep (x, y, z-chunk); RS_FUSED_TILE="tx,ty,zc"
-// overrides them for tuning.
-void fused_tile(int *tx, int *ty, int *zc)
+// Lane grid and chunk depth of the fused sweep (pairs x rows including the
+// one-lane ring, planes per chunk); RS_FUSED_TILE="lx,ly,zc" overrides them.
+void fused_tile(int *lx, int *ly, int *zc)
 {
-    *tx = 64; *ty = 16; *zc = 16;
+    *lx = 16; *ly = 16; *zc = 16;
     if (const char *e = getenv("RS_FUSED_TILE")) {
         int a, b, c;
-        if (sscanf(e, "%d,%d,%d", &a, &b, &c) == 3 && a >= 1 && b >= 1 && c >= 1) {
-            *tx = a; *ty = b; *zc = c;
+        if (sscanf(e, "%d,%d,%d", &a, &b, &c) == 3 && a >= 3 && b >= 3 && c >= 1 && a * b <= 512) {
+            *lx = a; *ly = b; *zc = c;
         }
     }
 }
@@ -729,17 +715,13 @@ bool fused_enabled()
 FusedMap fused_map(const Geo &g)
 {
     FusedMap m;
-    fused_tile(&m.TX, &m.TY, &m.ZC);
-    m.TX = m.TX < g.n[0] ? m.TX : g.n[0];
-    m.TY = m.TY < g.n[1] ? m.TY : g.n[1];
-    m.ZC = m.ZC < g.n[2] ? m.ZC : g.n[2];
-    m.ntx = g.n[0] / m.TX;
-    m.nty = g.n[1] / m.TY;
-    m.ntz = g.n[2] / m.ZC;
+    fused_tile(&m.LX, &m.LY, &m.ZC);
+    const int pairs = (g.n[0] + 1) / 2;
+    m.ntx = (pairs + m.LX - 3) / (m.LX - 2);
+    m.nty = (g.n[1] + m.LY - 3) / (m.LY - 2);
+    m.ntz = (g.n[2] + m.ZC - 1) / m.ZC;
     m.nwg = m.ntx * m.nty * m.ntz;
     m.per = (m.nwg + 7) / 8;
-    m.P = m.TX + (g.n[0] - m.ntx * m.TX) + 2;
-    m.Hs = m.TY + (g.n[1] - m.nty * m.TY) + 2;
     return m;
 }
 
@@ -756,9 +738,10 @@ struct SweepLaunch {
         }
         if (D == 3 && psi_alt && *psi_alt && fused_enabled()) {
             FusedMap fm = fused_map(g);
-            size_t lds = sizeof(double) * 3 * (size_t)fm.P * fm.Hs;
+            const size_t lds = sizeof(double) * 4 * (size_t)fm.LX * fm.LY;
             for (int sw = 0; sw < nsweeps; ++sw) {
-                hipLaunchKernelGGL((k_sweep_fused<M, S>), dim3(8 * fm.per), dim3(256), lds, s, g,
+                hipLaunchKernelGGL((k_sweep_fused<M, S>), dim3(8 * fm.per), dim3(fm.LX * fm.LY),
+                                   lds, s, g,
                                    law, st, beta, lambdaU, K, gvec, *psi, *psi_alt, fm);
                 double *t = *psi;
                 *psi = *psi_alt;
