@@ -436,6 +436,77 @@ def cpu_baseline(args, n):
                       "(red-black, OpenMP) with a residual norm after each, %.1f s" % (n, cycles, el)}
 
 
+def shard_share(args):
+    """One GPU's share of the 257^3 block split into eight z-slabs (the
+    decomposition a several-GPU run would use): 257 x 257 x 33 nodes, i.e. the
+    31 owned planes of slab s plus its halo planes 32 s and 32 s + 32, held
+    as Dirichlet faces with the current state (what a halo plane is during
+    one colour pass).  On the state of the timed 257^3 steps, times the
+    finest sweep (HIP events per colour launch) and the defect on every
+    share and on the whole grid; the slowest share sets the time of a
+    several-GPU step."""
+    import dataclasses
+    import torch
+    import paper_2606_04292_amd as rsl
+    from paper_2606_04292_amd import workloads as W
+
+    def timed(G, d, reps=10):
+        G.profile_enable(True)
+        G.profile_read(reset=True)
+        G.sweep(reps)
+        torch.cuda.synchronize()
+        ms, n, _ = G.profile_read(reset=True)
+        G.profile_enable(False)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(G.stream)
+        for _ in range(reps):
+            rsl.check(rsl.lib().rs_residual(G.h, G._dev(d)))
+        e1.record(G.stream)
+        torch.cuda.synchronize()
+        return ms * 1e3 / n, e0.elapsed_time(e1) * 1e3 / reps
+
+    w = W.config3(257)
+    G = rsl.Grid(w, device="cuda:0")
+    opts = rsl.solve_opts(w.nu1, w.nu2, w.nu_coarse, max_cycles=args.max_cycles, tol_abs=args.tol,
+                          stagnation=1)
+    for _ in range(args.warmup + 1):
+        code, _ = G.bdf_step(opts=opts)
+        if code != rsl.RS_OK:
+            raise SystemExit("step failed: " + rsl.lib().rs_last_error().decode())
+    pn, pm, nstep, t = G.get_state()
+    G.begin_step()
+    full_sweep, full_res = timed(G, G.empty())
+    G.close()
+    out = {"workload": "257^3 Haverkamp block after %d BDF2 steps; share = 257 x 257 x 33 nodes "
+                       "(31 owned planes and two halo planes as state-valued Dirichlet faces)"
+                       % (args.warmup + 1),
+           "whole_grid": {"sweep_us_per_colour": round(full_sweep, 2), "defect_us": round(full_res, 2),
+                          "nodes": 257 ** 3},
+           "shares": []}
+    g = dataclasses.replace(w.grid, n=[257, 257, 33], L=[1.0, 1.0, 32.0 / 256.0],
+                            face_bc=[W.BC_NOFLUX] * 4 + [W.BC_DIRICHLET_STATE] * 2,
+                            face_value=[0.0] * 6)
+    for sl in range(8):
+        k0 = 32 * sl
+        a = pn[k0:k0 + 33].contiguous()
+        b = pm[k0:k0 + 33].contiguous()
+        ws = dataclasses.replace(w, name="block3d_share%d" % sl, grid=g, psi0=a.cpu().numpy())
+        H = rsl.Grid(ws, device="cuda:0")
+        H.set_state(a, b, nstep, t)
+        H.begin_step()
+        sw, rs = timed(H, H.empty())
+        H.close()
+        out["shares"].append({"planes": [k0, k0 + 32], "sweep_us_per_colour": round(sw, 2),
+                              "defect_us": round(rs, 2)})
+        log("share %d: sweep %.2f us/colour, defect %.2f us" % (sl, sw, rs))
+    worst = max(x["sweep_us_per_colour"] for x in out["shares"])
+    out["slowest_share_sweep_us"] = worst
+    out["halo_plane_bytes"] = 257 * 257 * 8
+    out["halo_us_at_153GBps"] = round(257 * 257 * 8 / 153e9 * 1e6, 2)
+    out["sweep_speedup_8_shares_vs_whole"] = round(full_sweep / worst, 2)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -462,6 +533,8 @@ def main():
     ap.add_argument("--paper-order", action="store_true",
                     help="run only the paper's temporal-order study of the 1-D infiltration")
     ap.add_argument("--order-t", type=float, default=10.0, help="final time of the order study (s)")
+    ap.add_argument("--shard-share", action="store_true",
+                    help="time the sweep and defect on one GPU's share of an eight-slab split")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 512 MiB device copy first (counter calibration)")
     args = ap.parse_args()
@@ -481,6 +554,9 @@ def main():
         return
     if args.paper_order:
         print(json.dumps({"paper_order_study": paper_order(args)}), flush=True)
+        return
+    if args.shard_share:
+        print(json.dumps({"shard_share": shard_share(args)}), flush=True)
         return
     r = gpu_run(args)
     w = r["w"]
