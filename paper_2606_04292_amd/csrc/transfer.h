@@ -11,8 +11,11 @@ namespace rs {
 // psibar_H = FW(psi_h), d_H = FW(d_h) stored in g_H (Dirichlet coarse nodes:
 // injection of psi, zero defect).  FW: tensor (1/4, 1/2, 1/4) around fine node
 // 2I, missing neighbours mirrored at the domain boundary.  The taps are summed
-// axis 2 outermost, axis 0 innermost, with weight (w0 w1) w2.
-template <int DIM, typename T>
+// axis 2 outermost, axis 0 innermost, with weight (w0 w1) w2.  XPAD (arrays
+// with finite padding around them, as in a grid workspace): the three axis-0
+// taps are loaded as the window 2I0-1 .. 2I0+1 and mirrored in registers, so
+// their loads merge into wide ones; the sums are the same.
+template <int DIM, typename T, bool XPAD = false>
 __device__ __forceinline__ void restrict_at(const Geo &gc, const Geo &gf, const T *psi_f,
                                             const T *d_f, T *psibar_c, T *g_c, int I0, int I1,
                                             int I2)
@@ -46,12 +49,27 @@ __device__ __forceinline__ void restrict_at(const Geo &gc, const Geo &gf, const 
         for (int o1 = 0; o1 < (DIM > 1 ? 3 : 1); ++o1) {
             const T w1 = DIM > 1 ? wt[o1] : T(1);
             const long long b1 = b2 + (DIM > 1 ? off[1][o1] : 0);
+            if constexpr (XPAD) {
+                const long long fc = b1 + F[0];
+                const T pl = psi_f[fc - 1], pc = psi_f[fc], pr = psi_f[fc + 1];
+                const T dl = d_f[fc - 1], dc = d_f[fc], dr = d_f[fc + 1];
+                const bool first = F[0] == 0, last = F[0] == gf.n[0] - 1;
+                const T P3[3] = {first ? pr : pl, pc, last ? pl : pr};
+                const T D3[3] = {first ? dr : dl, dc, last ? dl : dr};
 #pragma unroll
-            for (int o0 = 0; o0 < 3; ++o0) {
-                const T w = wt[o0] * w1 * w2;
-                const long long fi = b1 + off[0][o0];
-                sp += w * psi_f[fi];
-                sd += w * d_f[fi];
+                for (int o0 = 0; o0 < 3; ++o0) {
+                    const T w = wt[o0] * w1 * w2;
+                    sp += w * P3[o0];
+                    sd += w * D3[o0];
+                }
+            } else {
+#pragma unroll
+                for (int o0 = 0; o0 < 3; ++o0) {
+                    const T w = wt[o0] * w1 * w2;
+                    const long long fi = b1 + off[0][o0];
+                    sp += w * psi_f[fi];
+                    sd += w * d_f[fi];
+                }
             }
         }
     }
@@ -112,7 +130,7 @@ __global__ __launch_bounds__(256) void k_restrict(Geo gc, Geo gf, const T *psi_f
     const int i = (int)(t - (unsigned long long)row * nm.n0);
     const int k = (int)udiv(row, nm.d1);
     const int j = (int)row - k * (int)nm.n1;
-    restrict_at<DIM, T>(gc, gf, psi_f, d_f, psibar_c, g_c, i, j, k);
+    restrict_at<DIM, T, true>(gc, gf, psi_f, d_f, psibar_c, g_c, i, j, k);   // workspace arrays are padded
 }
 
 // Prolongation by coarse cell: the thread of coarse node I loads psi_H - psibar_H
