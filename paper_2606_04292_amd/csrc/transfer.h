@@ -137,7 +137,9 @@ __global__ __launch_bounds__(256) void k_restrict(Geo gc, Geo gf, const T *psi_f
 // on the 2^DIM corners I + {0,1}^DIM once and updates the fine nodes 2I + {0,1}^DIM
 // (those inside the grid), each with the sum of prolong_at in the same order.
 // FULL: interpolate psi_H itself and assign it (the FMG interpolation;
-// psibar_c unused).
+// psibar_c unused).  The arrays are padded workspace arrays: the two axis-0
+// corners and the two axis-0 fine nodes are loaded as pairs without a bound
+// check (a value past the end of a row has weight 0 or is not stored).
 template <int DIM, typename T, bool FULL = false>
 __global__ __launch_bounds__(256) void k_prolong(Geo gf, Geo gc, const T *psi_c, const T *psibar_c,
                                                  T *psi_f, NodeMap nmc)
@@ -149,11 +151,12 @@ __global__ __launch_bounds__(256) void k_prolong(Geo gf, Geo gc, const T *psi_c,
     int Ic[3] = {(int)(t - (unsigned long long)row * nmc.n0), 0, 0};
     Ic[2] = (int)udiv(row, nmc.d1);
     Ic[1] = (int)row - Ic[2] * (int)nmc.n1;
-    // corner offsets (the upper corner clamped at the last coarse node: its
-    // weight is 0 there or the fine node lies outside the grid)
+    // corner offsets along axes 1 and 2 (the upper corner clamped at the last
+    // coarse node: its weight is 0 there or the fine node lies outside the
+    // grid); along axis 0 the pair I0, I0 + 1 is loaded as it is
     long long co[3][2];
 #pragma unroll
-    for (int l = 0; l < 3; ++l) {
+    for (int l = 1; l < 3; ++l) {
         const int lo = Ic[l];
         const int hi = lo + 1 < gc.n[l] ? lo + 1 : lo;
         co[l][0] = (long long)lo * gc.stride[l];
@@ -165,11 +168,12 @@ __global__ __launch_bounds__(256) void k_prolong(Geo gf, Geo gc, const T *psi_c,
     for (int q2 = 0; q2 < N2; ++q2)
 #pragma unroll
         for (int q1 = 0; q1 < N1; ++q1)
-#pragma unroll
-            for (int q0 = 0; q0 < 2; ++q0) {
-                const long long J = (DIM > 2 ? co[2][q2] : 0) + (DIM > 1 ? co[1][q1] : 0) + co[0][q0];
-                E[q2][q1][q0] = FULL ? psi_c[J] : psi_c[J] - psibar_c[J];
-            }
+        {
+            const long long J = (DIM > 2 ? co[2][q2] : 0) + (DIM > 1 ? co[1][q1] : 0) + Ic[0];
+            const T c0 = psi_c[J], c1 = psi_c[J + 1];
+            E[q2][q1][0] = FULL ? c0 : c0 - psibar_c[J];
+            E[q2][q1][1] = FULL ? c1 : c1 - psibar_c[J + 1];
+        }
 #pragma unroll
     for (int a2 = 0; a2 < N2; ++a2) {
         const int f2 = 2 * Ic[2] + a2;
@@ -178,6 +182,12 @@ __global__ __launch_bounds__(256) void k_prolong(Geo gf, Geo gc, const T *psi_c,
         for (int a1 = 0; a1 < N1; ++a1) {
             const int f1 = 2 * Ic[1] + a1;
             if (f1 >= gf.n[1]) continue;
+            const long long fr = 2LL * Ic[0] + (long long)f1 * gf.stride[1] + (long long)f2 * gf.stride[2];
+            T old[2] = {T(0), T(0)};
+            if (!FULL) {
+                old[0] = psi_f[fr];
+                old[1] = psi_f[fr + 1];
+            }
 #pragma unroll
             for (int a0 = 0; a0 < 2; ++a0) {
                 const int f0 = 2 * Ic[0] + a0;
@@ -197,9 +207,7 @@ __global__ __launch_bounds__(256) void k_prolong(Geo gf, Geo gc, const T *psi_c,
                         for (int q0 = 0; q0 < 2; ++q0)
                             e += w0[q0] * (DIM > 1 ? w1[q1] : T(1)) * (DIM > 2 ? w2[q2] : T(1)) *
                                  E[q2][q1][q0];
-                const long long fi = f0 + (long long)f1 * gf.stride[1] + (long long)f2 * gf.stride[2];
-                if (FULL) psi_f[fi] = e;
-                else psi_f[fi] += e;
+                psi_f[fr + a0] = FULL ? e : old[a0] + e;
             }
         }
     }
