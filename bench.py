@@ -32,6 +32,7 @@ def log(*a):
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "sweep_fp64_block3d_haverkamp_257_traffic.md")
+COUNTERS_PROFILE = os.path.join(ROOT, "profiles", "sweep_fp64_block3d_haverkamp_257_counters.md")
 
 
 # The translation unit of the FP64 sweep kernel: the traffic counters stay
@@ -51,19 +52,30 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def profiled_traffic():
-    """Calibrated HBM bytes (read + write) per finest-level sweep launch from
-    the committed counter summary, or None once the kernel sources changed
-    since the counters were taken."""
+def profiled_value(path, key):
+    """The number recorded as `key=value kernel_sources_sha256=...` in a
+    committed counter summary, or None when the summary is missing or the
+    kernel sources changed since the counters were taken."""
     import re
     try:
-        with open(TRAFFIC_PROFILE) as f:
-            m = re.search(r"sweep_traffic_bytes=(\d+) kernel_sources_sha256=([0-9a-f]+)", f.read())
+        with open(path) as f:
+            m = re.search(key + r"=([0-9.]+) kernel_sources_sha256=([0-9a-f]+)", f.read())
     except OSError:
         return None
     if not m or m.group(2) != kernel_sources_sha256():
         return None
-    return int(m.group(1))
+    return float(m.group(1))
+
+
+def profiled_traffic():
+    """Calibrated HBM bytes (read + write) per finest-level sweep launch."""
+    v = profiled_value(TRAFFIC_PROFILE, "sweep_traffic_bytes")
+    return None if v is None else int(v)
+
+
+def profiled_valu_busy():
+    """VALUBusy (%) of the finest-level sweep launches."""
+    return profiled_value(COUNTERS_PROFILE, "sweep_valu_busy_pct")
 
 
 def gpu_run(args):
@@ -146,7 +158,9 @@ def gpu_run(args):
                   "traffic_per_algorithmic": (round(traffic / bytes_per_launch, 3)
                                               if traffic else None),
                   "traffic_source": os.path.relpath(TRAFFIC_PROFILE, ROOT),
-                  "kernel": "k_sweep_colour (finest level, one colour per launch)",
+                  "valu_busy_pct": profiled_valu_busy(),
+                  "counters_source": os.path.relpath(COUNTERS_PROFILE, ROOT),
+                  "kernel": "k_sweep (finest level, one colour per launch)",
                   "avg_launch_us": round(avg_launch_s * 1e6, 2),
                   "bytes_per_launch": bytes_per_launch, "launches": launches,
                   "sweep_updates_per_s": sweep_cells / (sweep_ms * 1e-3)},

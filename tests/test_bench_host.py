@@ -1,5 +1,6 @@
 """Host-side checks of bench.py: the one-GPU guard and the rule that the
-profiled traffic is reported only for the kernel sources it was taken on."""
+profiled traffic and VALU figures are reported only for the kernel sources
+they were taken on."""
 import os
 import subprocess
 import sys
@@ -33,6 +34,17 @@ def test_traffic_is_tied_to_the_kernel_sources(tmp_path, monkeypatch, matching):
 def test_missing_traffic_profile_reads_as_unmeasured(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(tmp_path / "absent.md"))
     assert bench.profiled_traffic() is None
+
+
+@pytest.mark.parametrize("matching", [True, False])
+def test_valu_busy_is_tied_to_the_kernel_sources(tmp_path, monkeypatch, matching):
+    sha = bench.kernel_sources_sha256()
+    if not matching:
+        sha = ("0" if sha[0] != "0" else "1") + sha[1:]
+    p = tmp_path / "counters.md"
+    p.write_text("table\n\nsweep_valu_busy_pct=45.0 kernel_sources_sha256=%s\n" % sha)
+    monkeypatch.setattr(bench, "COUNTERS_PROFILE", str(p))
+    assert bench.profiled_valu_busy() == (45.0 if matching else None)
 
 
 def test_kernel_hash_covers_every_sweep_source():
