@@ -523,8 +523,8 @@ __global__ __launch_bounds__(256) void k_residual_pair(Geo g, Law L, Step st, co
             cfo[q] = ok ? ((cl == 0 || cl == g.n[l] - 1) ? 1.0 : 0.5) * g.ih2[l] : 0.0;
         }
         const double g0 = gv[idx0], g1 = gv[idx0 + 1];
-        double bz = 0.0;
-        if (SINK) bz = beta[(DIM == 1) ? i0 : (DIM == 2 ? j : k)];
+        double bz = 0.0;   // root density of the row (2-D, 3-D)
+        if (SINK && DIM > 1) bz = beta[DIM == 2 ? j : k];
         double r[2] = {0.0, 0.0};
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
@@ -535,9 +535,10 @@ __global__ __launch_bounds__(256) void k_residual_pair(Geo g, Law L, Step st, co
             if constexpr (MODEL == kMulti) s = st.a * theta_only(L.soils[g.soil[idx0 + a]], x);
             else s = st.a * theta_only_t<MODEL>(L, x);
             if (SINK) {
+                // in 1-D the row is the vertical axis: each node has its own root density
                 double fa, dfa;
                 feddes(L, x, fa, dfa);
-                s += bz * fa;
+                s += ((DIM == 1) ? beta[i] : bz) * fa;
             }
             // neighbours in the order of stencil(): axis 0 low/high, then the others
             const double cx = ((i == 0 || i == g.n[0] - 1) ? 1.0 : 0.5) * g.ih2[0];

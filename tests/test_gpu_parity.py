@@ -54,6 +54,11 @@ def cases():
     w = W.shrink(W.config2(), 33)
     out["c2_const_xi33"] = dataclasses.replace(
         w, law=dataclasses.replace(w.law, kappa_rule=W.KAPPA_CONST, kappa=1e-4, xi=1e-5))
+    # root uptake in a 1-D column: the vertical axis is the row axis, so every
+    # node carries its own root density
+    g1 = W.GridSpec(dim=1, n=[65], L=[0.5], face_bc=[W.BC_NOFLUX, W.BC_NOFLUX], face_value=[0.0, 0.0])
+    out["c4_col_sink65"] = W.Workload("root_column65", g1, W.config4(5, 5).law, np.full(g1.shape, -1.0),
+                                      dt=300.0, steps=3, order=2)
     # layered media and the Gardner law (section 4)
     out["lay_celia129"] = W.celia_composite(129)
     out["lay_2layer33"] = W.two_layer_vg(33)
@@ -163,8 +168,12 @@ def test_vcycle_parity(torch_cuda, name):
         say("  cycle", c, "rel", e)
         assert e <= TOL_SWEEP, (c, e)
     rg = G.residual_norm()
-    ro = S.residual()
+    ro, do = S.residual(want_vector=True)
     assert abs(rg - ro) <= 1e-9 * max(ro, 1e-30) + 1e-13 * S.a
+    # the defect vector itself, node by node (the fine-level defect kernel,
+    # also where the cycle's coarse levels run in one work-group)
+    dg = np_(G.residual())
+    assert np.abs(dg - do).max() <= 1e-9 * max(ro, 1e-30) + 1e-13 * S.a
 
 
 @pytest.mark.parametrize("name", NAMES)
