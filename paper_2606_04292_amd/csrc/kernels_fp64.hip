@@ -22,12 +22,7 @@ namespace rs {
 
 namespace {
 
-__device__ __forceinline__ double sink_beta(const Law &L, const double *beta, const int c[3], int vert)
-{
-    return (L.sink == kSinkFeddes) ? beta[c[vert]] : 0.0;
-}
-
-// N(psi)_i = a theta(psi_i) + beta a_F(psi_i) + xi psi_i + (M psi)_i  (eq. Nh-def)
+// p[0..n) = v (clears the norm words with a kernel rather than a memset)
 __global__ void k_fill_u64(unsigned long long *p, int n, unsigned long long v)
 {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
