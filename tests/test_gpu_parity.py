@@ -56,9 +56,13 @@ def cases():
         w, law=dataclasses.replace(w.law, kappa_rule=W.KAPPA_CONST, kappa=1e-4, xi=1e-5))
     # root uptake in a 1-D column: the vertical axis is the row axis, so every
     # node carries its own root density
-    g1 = W.GridSpec(dim=1, n=[65], L=[0.5], face_bc=[W.BC_NOFLUX, W.BC_NOFLUX], face_value=[0.0, 0.0])
-    out["c4_col_sink65"] = W.Workload("root_column65", g1, W.config4(5, 5).law, np.full(g1.shape, -1.0),
-                                      dt=300.0, steps=3, order=2)
+    for n in (65, 4097):
+        g1 = W.GridSpec(dim=1, n=[n], L=[0.5], face_bc=[W.BC_NOFLUX, W.BC_NOFLUX], face_value=[0.0, 0.0])
+        out["c4_col_sink%d" % n] = W.Workload("root_column%d" % n, g1, W.config4(5, 5).law,
+                                              np.full(g1.shape, -1.0), dt=300.0, steps=3, order=2)
+    # a column longer than the one-work-group tail (2049 nodes): its fine
+    # levels run the multi-launch 1-D kernels
+    out["c1_col4097"] = W.config1(4097)
     # layered media and the Gardner law (section 4)
     out["lay_celia129"] = W.celia_composite(129)
     out["lay_2layer33"] = W.two_layer_vg(33)
@@ -171,9 +175,12 @@ def test_vcycle_parity(torch_cuda, name):
     ro, do = S.residual(want_vector=True)
     assert abs(rg - ro) <= 1e-9 * max(ro, 1e-30) + 1e-13 * S.a
     # the defect vector itself, node by node (the fine-level defect kernel,
-    # also where the cycle's coarse levels run in one work-group)
+    # also where the cycle's coarse levels run in one work-group); each entry
+    # is a difference of terms as large as g and a psi, rounded differently
+    # on the two sides
     dg = np_(G.residual())
-    assert np.abs(dg - do).max() <= 1e-9 * max(ro, 1e-30) + 1e-13 * S.a
+    scale = np.abs(S.get(oracle.FIELD_G)).max() + S.a * np.abs(S.psi()).max()
+    assert np.abs(dg - do).max() <= 1e-9 * max(ro, 1e-30) + 1e-11 * scale
 
 
 @pytest.mark.parametrize("name", NAMES)
