@@ -1,6 +1,7 @@
 """Seeded random grids against the oracle: anisotropic shapes of 3 to 33 nodes
-per axis in one to three dimensions, random face conditions (Dirichlet,
-no-flux, free drainage at the bottom), four laws and non-smooth start states.
+per axis in one to three dimensions, random face conditions (Dirichlet with a
+fixed value or with the state's values, no-flux, free drainage at the
+bottom), five laws (one with root uptake) and non-smooth start states.
 Two FP64 V-cycles match the oracle's red-black cycles to the sweep bar, and a
 mixed-precision step iterated to the rounding floor matches the oracle's step
 solution to the converged bar.  Axes of 3 nodes (one interior node) and rows
@@ -17,7 +18,7 @@ from tests.test_gpu_parity import FLOOR_CYCLES, TOL_CONV, TOL_SWEEP, rel, np_, s
 
 pytestmark = pytest.mark.gpu
 
-NCASES = 12
+NCASES = 15
 
 
 def random_case(k):
@@ -30,7 +31,7 @@ def random_case(k):
     L = [float(rng.uniform(0.5, 2.0)) for _ in range(dim)]
     bc, val = [], []
     for f in range(2 * dim):
-        choices = [W.BC_NOFLUX, W.BC_DIRICHLET]
+        choices = [W.BC_NOFLUX, W.BC_DIRICHLET, W.BC_DIRICHLET_STATE]
         if f == 2 * (dim - 1):   # bottom face of the vertical (last) axis
             choices.append(W.BC_FREEDRAIN)
         bc.append(int(rng.choice(choices)))
@@ -38,7 +39,7 @@ def random_case(k):
     g = W.GridSpec(dim=dim, n=n, L=L, face_bc=bc, face_value=val)
     laws = [W.config1(5).law, W.config3(5).law,
             W.LawSpec(model=W.MODEL_LINEAR, theta_s=0.4, theta_r=0.1, Ks=1e-4, lin_c=0.01),
-            W.config2(5).law]
+            W.config2(5).law, W.config4(5, 5).law]
     law = laws[k % len(laws)]
     law = dataclasses.replace(law, xi=max(law.xi, 1e-5))
     psi0 = -0.2 - 0.6 * rng.random(g.shape)
@@ -54,6 +55,8 @@ def test_the_draw_covers_the_edge_shapes():
     assert {1, 2, 3} <= {len(s) for s in shapes}
     assert any(3 in s for s in shapes)
     assert any(c.grid.face_bc[2 * (c.grid.dim - 1)] == W.BC_FREEDRAIN for c in CASES)
+    assert any(W.BC_DIRICHLET_STATE in c.grid.face_bc for c in CASES)
+    assert {c.grid.dim for c in CASES if c.law.sink != W.SINK_NONE} == {1, 2, 3}
 
 
 @pytest.fixture(scope="module")
