@@ -329,7 +329,8 @@ def paper_2d_table(args):
     ||r||_inf <= 1e-10 or the rounding floor: the Gardner infiltration
     (129^2, tau 0.1 day, 3 days, V(5,5)) whose CPU time the paper prints
     (context only: unstated hardware), and the two-layer vGM medium (257^2,
-    tau 0.01 day, to 1.75 days, an FMG(10,10) cycle then V(10,10) cycles); each
+    tau 0.01 day, to 1.75 days, an FMG(10,10) cycle then V(10,10) cycles; the
+    paper prints a total CPU time without stating the run length); each
     also with GS(100), 100 red-black sweeps per step, against the multigrid result."""
     import torch
     import paper_2606_04292_amd as rsl
@@ -338,7 +339,7 @@ def paper_2d_table(args):
     out = {}
     for key, w, fmg, ctx in (
             ("gardner_2d", W.gardner_2d(129), 0, 2.216),
-            ("two_layer_vg", W.two_layer_vg(257, steps=args.paper_2d_steps), 1, None)):
+            ("two_layer_vg", W.two_layer_vg(257, steps=args.paper_2d_steps), 1, 2320.0)):
         G = rsl.Grid(w, device="cuda:0")
         opts = rsl.solve_opts(w.nu1, w.nu2, w.nu_coarse, max_cycles=200, tol_abs=1e-10,
                               stagnation=1, fmg=fmg)
