@@ -791,7 +791,7 @@ int launch_sweep_rb(const Geo &g, const Law &law, const Step &st, const double *
 
 bool fused_sweep_level(const Geo &g)
 {
-    return g.dim == 3 && g.N >= kFusedMinNodes;
+    return g.dim == 3 && g.N >= kFusedMinNodes && fused_enabled();
 }
 
 void launch_residual(const Geo &g, const Law &law, const Step &st, const double *beta,

@@ -114,7 +114,9 @@ void launch_lambda_u(const Geo &g, const double *K, unsigned long long *out, hip
 int launch_sweep_rb(const Geo &g, const Law &law, const Step &st, const double *beta,
                     double lambdaU, const double *K, const double *gvec, double **psi,
                     double **psi_alt, int nsweeps, hipStream_t s);
-// Levels that get a second psi buffer for the fused sweep.
+// Levels that get a second psi buffer for the fused sweep (3-D levels of at
+// least kFusedMinNodes nodes, when the fused sweep is selected at grid
+// creation).
 constexpr long long kFusedMinNodes = 33LL * 33 * 33;
 bool fused_sweep_level(const Geo &g);
 // Start of an FP32 correction (mixed precision) written by the defect kernel:

@@ -1,5 +1,5 @@
 """The largest grid the library takes: the 3-D Haverkamp block at 1025^3
-nodes (1.077e9 nodes, just under the 2^31-node limit; a ~90 GB workspace),
+nodes (1.077e9 nodes, just under the 2^31-node limit; a 76 GB workspace),
 started unsaturated (psi0 = -0.3 - 0.7 z m) and moved by one V-cycle.
 Step set-up and one red-black sweep are checked on sampled nodes: K* and g
 against the oracle's laws, and every sampled update against the oracle's
