@@ -1,7 +1,8 @@
 """Seeded random grids against the oracle: anisotropic shapes of 3 to 33 nodes
 per axis in one to three dimensions, random face conditions (Dirichlet with a
 fixed value or with the state's values, no-flux, free drainage at the
-bottom), five laws (one with root uptake) and non-smooth start states.
+bottom), Dirichlet rectangles on the top face, five laws (one with root
+uptake) and non-smooth start states.
 Two FP64 V-cycles match the oracle's red-black cycles to the sweep bar, and a
 mixed-precision step iterated to the rounding floor matches the oracle's step
 solution to the converged bar.  Axes of 3 nodes (one interior node) and rows
@@ -36,7 +37,19 @@ def random_case(k):
             choices.append(W.BC_FREEDRAIN)
         bc.append(int(rng.choice(choices)))
         val.append(float(rng.uniform(-1.0, -0.1)))
-    g = W.GridSpec(dim=dim, n=n, L=L, face_bc=bc, face_value=val)
+    patch = {}
+    if dim >= 2 and rng.random() < 0.6:
+        # a Dirichlet rectangle on the top face (tangential index ranges)
+        lo, hi = [], []
+        for l in range(dim - 1):
+            a, b = sorted(int(v) for v in rng.integers(0, n[l], size=2))
+            lo.append(a)
+            hi.append(b)
+        lo += [0] * (2 - len(lo))
+        hi += [0] * (2 - len(hi))
+        patch = dict(patch_face=2 * (dim - 1) + 1, patch_lo=tuple(lo), patch_hi=tuple(hi),
+                     patch_value=float(rng.uniform(-0.3, 0.0)))
+    g = W.GridSpec(dim=dim, n=n, L=L, face_bc=bc, face_value=val, **patch)
     laws = [W.config1(5).law, W.config3(5).law,
             W.LawSpec(model=W.MODEL_LINEAR, theta_s=0.4, theta_r=0.1, Ks=1e-4, lin_c=0.01),
             W.config2(5).law, W.config4(5, 5).law]
@@ -56,6 +69,7 @@ def test_the_draw_covers_the_edge_shapes():
     assert any(3 in s for s in shapes)
     assert any(c.grid.face_bc[2 * (c.grid.dim - 1)] == W.BC_FREEDRAIN for c in CASES)
     assert any(W.BC_DIRICHLET_STATE in c.grid.face_bc for c in CASES)
+    assert any(c.grid.patch_face >= 0 and c.grid.dim == 3 for c in CASES)
     assert {c.grid.dim for c in CASES if c.law.sink != W.SINK_NONE} == {1, 2, 3}
 
 
