@@ -21,6 +21,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 ORDER_LEX = 0
 ORDER_RB = 1
 FIELD_PSI, FIELD_KSTAR, FIELD_G, FIELD_PSIBAR, FIELD_PSI_N, FIELD_PSI_NM1 = range(6)
+COARSE_INJECT, COARSE_FW = 0, 1
 
 
 def build(force: bool = True) -> str:
@@ -49,7 +50,7 @@ class Params(C.Structure):
                 ("h1", C.c_double), ("h2", C.c_double), ("h3", C.c_double),
                 ("h4", C.c_double), ("xi", C.c_double), ("kappa_rule", C.c_int),
                 ("kappa", C.c_double), ("newton_iters", C.c_int), ("lag_extrap", C.c_int),
-                ("newton_tol", C.c_double), ("gd_alpha", C.c_double)]
+                ("newton_tol", C.c_double), ("gd_alpha", C.c_double), ("coarse_k", C.c_int)]
 
 
 _lib = None

@@ -58,6 +58,12 @@
 #define ORC_KAPPA_REL 2
 #define ORC_KAPPA_REMARK 3
 
+/* Coarse-level K* (the paper defines the coarse operator only by analogy with
+ * the fine one): the fine value at the coinciding node, or the full-weighting
+ * average of the fine K* around it. */
+#define ORC_COARSE_INJECT 0
+#define ORC_COARSE_FW 1
+
 #define ORC_ORDER_LEX 0
 #define ORC_ORDER_RB 1
 
@@ -97,6 +103,7 @@ typedef struct {
     int lag_extrap;
     double newton_tol;  /* stop once a Newton step moves x by <= newton_tol |x| (0: never early) */
     double gd_alpha;    /* Gardner exponent (per law unit of psi) */
+    int coarse_k;       /* ORC_COARSE_INJECT or ORC_COARSE_FW: coarse-level K* */
 } orc_params;
 
 typedef struct {
@@ -845,7 +852,8 @@ void orc_fmg(orc_solver *S, int nu1, int nu2)
  * extrapolation 2 psi^n - psi^{n-1}; the first step is BDF1.  K* = K(psi*) at every
  * node (Dirichlet nodes take their boundary value as lagged state), and
  * g = history + xi psi* - (M z) - free-drainage outflow (eq. Nh-def).  Coarse
- * levels take K* by injection.  The iterate starts from psi^n. */
+ * levels take K* by injection, or as the full-weighting average of the finer
+ * level's K* (coarse_k = ORC_COARSE_FW).  The iterate starts from psi^n. */
 void orc_begin_step(orc_solver *S, double dt, int order)
 {
     orc_level *f0 = &S->lev[0];
@@ -895,7 +903,8 @@ void orc_begin_step(orc_solver *S, double dt, int order)
             int II[3];
             coords(cl, I, II);
             int jj[3] = {2 * II[0], 2 * II[1], 2 * II[2]};
-            cl->Kstar[I] = fl->Kstar[index_of(fl, jj)];
+            cl->Kstar[I] = (S->p.coarse_k == ORC_COARSE_FW) ? fw_at(fl, fl->Kstar, II, S->grid.dim)
+                                                             : fl->Kstar[index_of(fl, jj)];
         }
     }
     for (int l = 0; l < S->nlev; l++) {

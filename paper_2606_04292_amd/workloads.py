@@ -44,6 +44,8 @@ SINK_FEDDES_EXP = 1   # Feddes-type a(psi) times an exponential root density
 KAPPA_CONST = 1       # kappa_i = kappa
 KAPPA_REL = 2         # kappa_i = kappa * m_ii
 KAPPA_REMARK = 3      # kappa_i = max row sum of U minus row sum of U (Remark after the theorem)
+COARSE_INJECT = 0     # coarse K* = fine K* at the coinciding node
+COARSE_FW = 1         # coarse K* = full-weighting average of the finer level's K*
 
 SEED_ROOT = 260604292
 
@@ -107,6 +109,7 @@ class LawSpec:
     lag_extrap: int = 0               # BDF2 lag: 0 psi^n, 1 2 psi^n - psi^{n-1}
     newton_tol: float = 1e-10         # ... ending after a Newton step <= newton_tol |psi|
     gd_alpha: float = 0.0             # MODEL_GARDNER exponent (per law unit of psi)
+    coarse_k: int = 0                 # COARSE_INJECT or COARSE_FW: K* on the coarse levels
 
 
 @dataclasses.dataclass
