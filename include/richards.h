@@ -103,6 +103,14 @@ typedef struct rs_grid_desc {
     double patch_value;
 } rs_grid_desc;
 
+/* K* on the coarse levels (the coarse operator of section 3.2 is defined by
+ * analogy with the fine one): the fine value at the coinciding node, or the
+ * full-weighting average (1/4, 1/2, 1/4 per axis, mirrored at the ends) of the
+ * finer level's K*, which keeps the cycle convergent where K* jumps between
+ * neighbouring nodes.  Both converge to the same step solution. */
+#define RS_COARSE_INJECT 0
+#define RS_COARSE_FW 1
+
 /* Soil law, sink and smoother parameters (Table tab:models; eq. fully-bdf1
  * for xi; Lemma lem:decompos for kappa; eq. point-update for the Newton
  * count).  psi_unit scales psi before the Haverkamp law (100: law in cm).
@@ -153,6 +161,7 @@ typedef struct rs_constitutive {
     int n_soils;                  /* 0: the law above everywhere */
     const rs_soil *soils;         /* HOST, n_soils entries */
     const unsigned char *soil_id; /* HOST, one per fine node */
+    int coarse_kstar;             /* RS_COARSE_INJECT (0) or RS_COARSE_FW; the engine takes RS_COARSE_INJECT */
 } rs_constitutive;
 
 /* V-cycle parameters (nu_1, nu_2, nu_H of section 3.2) and stopping test

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "librichards.so")
 
 RS_OK, RS_EINVAL, RS_ENOMEM, RS_EHIP, RS_ESTATE, RS_ENONFINITE, RS_ENOTCONV, RS_EBUSY = range(8)
 RS_FP64, RS_MIXED = 0, 1
+RS_COARSE_INJECT, RS_COARSE_FW = 0, 1
 FIELD_PSI, FIELD_KSTAR, FIELD_G, FIELD_PSIBAR = 0, 1, 2, 3
 
 EXPORTS = [
@@ -67,7 +68,8 @@ class Constitutive(C.Structure):
                 ("kappa_rule", C.c_int), ("kappa", C.c_double), ("newton_iters", C.c_int),
                 ("lag_extrap", C.c_int), ("newton_tol", C.c_double),
                 ("Ks_field", C.POINTER(C.c_double)), ("gd_alpha", C.c_double),
-                ("n_soils", C.c_int), ("soils", C.POINTER(Soil)), ("soil_id", C.c_void_p)]
+                ("n_soils", C.c_int), ("soils", C.POINTER(Soil)), ("soil_id", C.c_void_p),
+                ("coarse_kstar", C.c_int)]
 
 
 class SolveOpts(C.Structure):
@@ -151,9 +153,10 @@ def constitutive(law: "workloads.LawSpec", ks_field=None, soils=None, soil_id=No
     c = Constitutive()
     c.struct_size = C.sizeof(Constitutive)
     for name, _ in Constitutive._fields_:
-        if name in ("struct_size", "Ks_field", "n_soils", "soils", "soil_id"):
+        if name in ("struct_size", "Ks_field", "n_soils", "soils", "soil_id", "coarse_kstar"):
             continue
         setattr(c, name, getattr(law, name))
+    c.coarse_kstar = law.coarse_k
     keep = []
     if ks_field is not None:
         ks = np.ascontiguousarray(ks_field, dtype=np.float64)

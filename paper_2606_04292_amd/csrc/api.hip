@@ -250,6 +250,7 @@ struct rs_grid {
     LevelData lev[kMaxLevels];
     double *psi_n, *psi_nm1, *ks;
     bool has_ks;
+    int coarse_k;                     // RS_COARSE_INJECT or RS_COARSE_FW
     unsigned long long *scratch;
     unsigned long long *host_bits;   // pinned readback
     Law *soil_tab;                    // device table of per-soil laws (layered media)
@@ -342,6 +343,8 @@ int validate_law(const rs_constitutive *c)
     if (c->struct_size != sizeof(rs_constitutive))
         return fail(RS_EINVAL, "rs_constitutive.struct_size %zu != %zu", c->struct_size,
                     sizeof(rs_constitutive));
+    if (c->coarse_kstar != RS_COARSE_INJECT && c->coarse_kstar != RS_COARSE_FW)
+        return fail(RS_EINVAL, "coarse_kstar must be RS_COARSE_INJECT or RS_COARSE_FW");
     if (c->n_soils != 0) {
         if (c->n_soils < 0 || c->n_soils > RS_MAX_SOILS)
             return fail(RS_EINVAL, "n_soils must be in 0..%d", RS_MAX_SOILS);
@@ -651,6 +654,7 @@ int rs_create_grid(const rs_grid_desc *d, int precision, void *ws_dev, size_t ws
     G->nstep = 0;
     G->t = 0.0;
     G->nu_coarse = 32;
+    G->coarse_k = RS_COARSE_INJECT;
     G->updates = 0.0;
     G->prof_on = false;
     G->prof_used = 0;
@@ -752,6 +756,7 @@ int rs_set_constitutive(rs_grid *G, const rs_constitutive *c)
     if (c->n_soils > 0) G->law.soils = G->soil_tab;
     G->law32 = make_law32(G->law);
     G->step.lag_extrap = c->lag_extrap ? 1 : 0;
+    G->coarse_k = c->coarse_kstar;
     if (c->Ks_field) {
         size_t bytes = sizeof(double) * (size_t)G->lev[0].geo.N;
         HIPCALL(hipMemcpyAsync(G->ks, c->Ks_field, bytes, hipMemcpyHostToDevice, G->stream));
@@ -816,8 +821,12 @@ int rs_begin_step(rs_grid *G, double dt, int order)
     launch_setup_kstar(f.geo, G->law, G->step, G->psi_n, G->psi_nm1, G->has_ks ? G->ks : nullptr,
                        f.K, f.psi, G->stream);
     launch_setup_g(f.geo, G->law, G->step, G->psi_n, G->psi_nm1, f.K, f.g, G->stream);
-    for (int l = 1; l < G->nlev; ++l)
-        launch_inject(G->lev[l].geo, G->lev[l - 1].geo, G->lev[l - 1].K, G->lev[l].K, G->stream);
+    for (int l = 1; l < G->nlev; ++l) {
+        if (G->coarse_k == RS_COARSE_FW)
+            launch_fw_coarse(G->lev[l].geo, G->lev[l - 1].geo, G->lev[l - 1].K, G->lev[l].K, G->stream);
+        else
+            launch_inject(G->lev[l].geo, G->lev[l - 1].geo, G->lev[l - 1].K, G->lev[l].K, G->stream);
+    }
     if (G->precision == RS_MIXED)
         for (int l = 0; l < G->nlev; ++l)
             launch_to_f32(G->lev[l].geo.N, G->lev[l].K, G->lev[l].K32, G->stream);

@@ -1026,6 +1026,7 @@ int rs_engine_submit(rs_engine *E, const rs_grid_desc *d, const rs_constitutive 
         return fail(RS_EINVAL, "the engine serves kappa rules CONST and REL");
     if (c->Ks_field) return fail(RS_EINVAL, "the engine serves uniform Ks");
     if (c->lag_extrap) return fail(RS_EINVAL, "the engine lags K at psi^n");
+    if (c->coarse_kstar != RS_COARSE_INJECT) return fail(RS_EINVAL, "the engine injects K* to coarse levels");
     if (!(dt > 0.0)) return fail(RS_EINVAL, "dt must be positive");
     if (order != 1 && order != 2) return fail(RS_EINVAL, "order must be 1 or 2");
     if (nsteps < 1) return fail(RS_EINVAL, "nsteps must be >= 1");

@@ -70,6 +70,20 @@ __global__ __launch_bounds__(256) void k_inject(Geo gc, Geo gf, const double *Kf
     Kc[I] = Kf[F];
 }
 
+// Coarse K* as the full-weighting average of the finer level's K* (the
+// alternative to k_inject; section 3.2 defines the coarse operator by analogy).
+template <int DIM>
+__global__ __launch_bounds__(256) void k_fw_coarse(Geo gc, Geo gf, const double *Kf, double *Kc,
+                                                   NodeMap nm)
+{
+    const unsigned long long t =
+        (unsigned long long)xcd_block(gridDim.x / 8u) * blockDim.x + threadIdx.x;
+    if (t >= (unsigned long long)gc.N) return;
+    int i, j, k;
+    node_ijk(nm, t, i, j, k);
+    Kc[t] = fw_value<DIM, double>(gf, Kf, i, j, k);
+}
+
 // max over red unknowns of the row sum of U over unknown neighbours (the red-
 // black ordering puts every neighbour of a red node after it)
 __global__ __launch_bounds__(256) void k_lambda_u(Geo g, const double *K, unsigned long long *out)
@@ -681,6 +695,18 @@ void launch_inject_u8(const Geo &gc, const Geo &gf, const unsigned char *vf, uns
 void launch_inject(const Geo &gc, const Geo &gf, const double *Kf, double *Kc, hipStream_t s)
 {
     hipLaunchKernelGGL(k_inject, node_grid(gc), dim3(kBX, kBY), 0, s, gc, gf, Kf, Kc);
+}
+
+void launch_fw_coarse(const Geo &gc, const Geo &gf, const double *Kf, double *Kc, hipStream_t s)
+{
+    const dim3 grid(xcd_grid(((unsigned long long)gc.N + 255) / 256));
+    const NodeMap nm = node_map(gc);
+    if (gc.dim == 1)
+        hipLaunchKernelGGL((k_fw_coarse<1>), grid, dim3(256), 0, s, gc, gf, Kf, Kc, nm);
+    else if (gc.dim == 2)
+        hipLaunchKernelGGL((k_fw_coarse<2>), grid, dim3(256), 0, s, gc, gf, Kf, Kc, nm);
+    else
+        hipLaunchKernelGGL((k_fw_coarse<3>), grid, dim3(256), 0, s, gc, gf, Kf, Kc, nm);
 }
 
 void launch_lambda_u(const Geo &g, const double *K, unsigned long long *out, hipStream_t s)

@@ -106,6 +106,8 @@ void launch_setup_kstar(const Geo &g, const Law &law, const Step &st, const doub
 void launch_setup_g(const Geo &g, const Law &law, const Step &st, const double *psi_n,
                     const double *psi_nm1, const double *K, double *gvec, hipStream_t s);
 void launch_inject(const Geo &gc, const Geo &gf, const double *Kf, double *Kc, hipStream_t s);
+// Kc = full-weighting average of Kf around each coarse node (mirrored at the ends)
+void launch_fw_coarse(const Geo &gc, const Geo &gf, const double *Kf, double *Kc, hipStream_t s);
 void launch_inject_u8(const Geo &gc, const Geo &gf, const unsigned char *vf, unsigned char *vc,
                       hipStream_t s);
 void launch_lambda_u(const Geo &g, const double *K, unsigned long long *out, hipStream_t s);

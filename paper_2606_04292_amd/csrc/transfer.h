@@ -77,6 +77,41 @@ __device__ __forceinline__ void restrict_at(const Geo &gc, const Geo &gf, const 
     g_c[I] = sd;
 }
 
+// Full weighting of v at coarse node (I0, I1, I2): the tensor (1/4, 1/2, 1/4)
+// around fine node 2I with missing neighbours mirrored at the ends, summed in
+// the order of restrict_at.
+template <int DIM, typename T>
+__device__ __forceinline__ T fw_value(const Geo &gf, const T *v, int I0, int I1, int I2)
+{
+    const int F[3] = {2 * I0, 2 * I1, 2 * I2};
+    long long off[3][3];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        const int n = gf.n[l];
+        const long long st = gf.stride[l];
+        const int m = F[l] == 0 ? 1 : F[l] - 1;
+        const int p = F[l] == n - 1 ? n - 2 : F[l] + 1;
+        off[l][0] = (long long)m * st;
+        off[l][1] = (long long)F[l] * st;
+        off[l][2] = (long long)p * st;
+    }
+    const T wt[3] = {T(0.25), T(0.5), T(0.25)};
+    T s = T(0);
+#pragma unroll
+    for (int o2 = 0; o2 < (DIM > 2 ? 3 : 1); ++o2) {
+        const T w2 = DIM > 2 ? wt[o2] : T(1);
+        const long long b2 = DIM > 2 ? off[2][o2] : 0;
+#pragma unroll
+        for (int o1 = 0; o1 < (DIM > 1 ? 3 : 1); ++o1) {
+            const T w1 = DIM > 1 ? wt[o1] : T(1);
+            const long long b1 = b2 + (DIM > 1 ? off[1][o1] : 0);
+#pragma unroll
+            for (int o0 = 0; o0 < 3; ++o0) s += wt[o0] * w1 * w2 * v[b1 + off[0][o0]];
+        }
+    }
+    return s;
+}
+
 // psi_h += I_h^H (psi_H - psibar_H) at fine unknowns (tensor linear
 // interpolation: even index -> coarse node, odd -> mean of the two).  Two taps
 // per axis, the second with weight 0 at an even index, so the sum has no

@@ -63,6 +63,18 @@ def cases():
     # a column longer than the one-work-group tail (2049 nodes): its fine
     # levels run the multi-launch 1-D kernels
     out["c1_col4097"] = W.config1(4097)
+    # coarse K* by full weighting: a smooth 3-D block, and a column whose start
+    # state is drawn per node (K* jumps by decades between neighbours; the
+    # injected cycle diverges there, the averaged one converges)
+    w = W.shrink(W.config3(), 33)
+    out["c3_block33_fw"] = dataclasses.replace(w, name="block33_fw",
+                                               law=dataclasses.replace(w.law, coarse_k=W.COARSE_FW))
+    g1 = W.GridSpec(dim=1, n=[1025], L=[0.5], face_bc=[W.BC_NOFLUX, W.BC_DIRICHLET], face_value=[0.0, -0.5])
+    rough = -0.2 - 0.6 * np.random.default_rng(W.seed_sequence(9, 0)).random(g1.shape)
+    out["rough_col1025_fw"] = W.Workload("rough_column1025_fw", g1,
+                                         dataclasses.replace(W.config1(5).law, xi=1e-5,
+                                                             coarse_k=W.COARSE_FW),
+                                         rough, dt=120.0, steps=3, order=2)
     # layered media and the Gardner law (section 4)
     out["lay_celia129"] = W.celia_composite(129)
     out["lay_2layer33"] = W.two_layer_vg(33)

@@ -157,7 +157,8 @@ def test_unsupported_requests_are_rejected(torch_cuda):
     import dataclasses
     for law in (dataclasses.replace(w.law, kappa_rule=W.KAPPA_REMARK),
                 dataclasses.replace(w.law, sink=W.SINK_FEDDES_EXP, Tp=1e-8, root_len=0.2,
-                                    h1=-0.1, h2=-0.25, h3=-4.0, h4=-80.0)):
+                                    h1=-0.1, h2=-0.25, h3=-4.0, h4=-80.0),
+                dataclasses.replace(w.law, coarse_k=W.COARSE_FW)):
         with pytest.raises(rsl.RsError) as ei:
             E.submit(dataclasses.replace(w, law=law))
         assert ei.value.code == rsl.RS_EINVAL
