@@ -21,8 +21,9 @@
  * alone and in any mix.
  *
  * Scope: models RS_VGM, RS_HAVERKAMP, RS_LINEAR; kappa rules RS_KAPPA_CONST and
- * RS_KAPPA_REL; no sink term and no per-node Ks field (those requests are
- * rejected with RS_EINVAL; use the single-grid API for them).
+ * RS_KAPPA_REL; coarse K* by injection (RS_COARSE_INJECT); no sink term and
+ * no per-node Ks field (other requests are rejected with RS_EINVAL; use the
+ * single-grid API for them).
  *
  * Threading: all calls on one engine must come from one thread at a time.
  * Device work is queued on the engine's stream; rs_engine_tick synchronises it.
