@@ -25,6 +25,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_UPDATE = 32.0   # FP64 sweep: read psi, K*, g and write psi, 8 B each
+BYTES_PER_UPDATE_32 = 20.0   # FP32 correction sweep: read delta, K*, rhs, psi_b and write delta, 4 B each
 
 
 def log(*a):
@@ -129,6 +130,8 @@ def gpu_run(args):
         H = rsl.Grid(w, precision=rsl.RS_MIXED, device="cuda:0")
         for s in range(args.warmup):
             H.bdf_step(opts=opts)
+        H.profile_enable(True)
+        H.profile_read(reset=True)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         mup, outer = 0.0, []
@@ -140,13 +143,23 @@ def gpu_run(args):
             outer.append(st.cycles)
         torch.cuda.synchronize()
         el2 = time.perf_counter() - t1
+        ms32, l32, c32 = H.profile_read(reset=True)
+        H.profile_enable(False)
         psi_mp = H.get_state()[0]
         err = float((psi_mp - psi_fp64).abs().max() / psi_fp64.abs().max())
+        t32 = ms32 * 1e-3 / max(l32, 1)
+        b32 = BYTES_PER_UPDATE_32 * c32 / max(l32, 1)
         mixed = {"ms_per_step": round(el2 * 1e3 / args.steps, 3),
                  "speedup_vs_fp64": round(elapsed / el2, 3),
                  "fp32_cell_updates_per_s": mup / el2,
                  "outer_corrections_per_step": outer,
                  "rel_err_vs_fp64": err,
+                 "fp32_sweep_roofline": {"bound": "hbm", "achieved": round(b32 / t32 / 1e9, 1),
+                                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                         "frac": round(b32 / t32 / 1e9 / HBM_PEAK_GBS, 4),
+                                         "kernel": "k_sweep32 (finest level, one colour per launch)",
+                                         "bytes_per_update": BYTES_PER_UPDATE_32,
+                                         "avg_launch_us": round(t32 * 1e6, 2), "launches": l32},
                  "note": "same steps and tolerance; FP64 path is parity-tested against the oracle"}
         log("mixed: %.2f ms/step, rel diff vs FP64 %.2e" % (el2 * 1e3 / args.steps, err))
         H.close()
