@@ -171,7 +171,10 @@ typedef struct rs_solve_opts {
     int nu1, nu2, nu_coarse, max_cycles;
     double tol_abs;       /* stop when ||g - N(psi)||_inf <= tol_abs */
     int stagnation;       /* also stop, with RS_OK, at the rounding floor: two cycles
-                             in a row that set no new minimum of the norm */
+                             in a row that set no new minimum of the norm.  A cycle
+                             that diverges stops the same way: compare res with
+                             res0 and res_hist of rs_step_stats (coarse_kstar =
+                             RS_COARSE_FW where K* jumps between nodes) */
     int mp_inner_cycles;  /* RS_MIXED: FP32 V-cycles per FP64 defect correction */
     int fmg;              /* 1: the first cycle of every step is one FMG(nu1, nu2) cycle
                              (rs_fmg, in FP64), counted as a cycle */
