@@ -466,6 +466,26 @@ int fine_norm(rs_grid *G, double *out, double *d = nullptr, bool mp_start = fals
     return read_norm(G, out);
 }
 
+// Scale of the defect's rounding floor on the finest level: the largest sum
+// of the magnitudes of the terms one node's defect adds up.
+int defect_scale(rs_grid *G, double *out)
+{
+    LevelData &f = G->lev[0];
+    unsigned long long *w = G->scratch + (kScratchWords - 1);
+    launch_fill_u64(w, 1, 0ull, G->stream);
+    launch_defect_scale(f.geo, G->law, G->step, f.beta, f.K, f.g, f.psi, w, G->stream);
+    HIPCALL(hipGetLastError());
+    HIPCALL(hipMemcpyAsync(G->host_bits + (kScratchWords - 1), w, sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost, G->stream));
+    HIPCALL(hipStreamSynchronize(G->stream));
+    memcpy(out, &G->host_bits[kScratchWords - 1], sizeof(double));
+    return RS_OK;
+}
+
+// A stall of the cycle counts as the rounding floor when its best residual is
+// within this fraction of the defect's term scale (about 1e6 ulp).
+constexpr double kFloorRel = 1e6 * 2.220446049250313e-16;
+
 // FP32 red-black sweeps of the correction equation on level l.
 void sweep32_level(rs_grid *G, int l, int nsweeps)
 {
@@ -992,8 +1012,21 @@ int rs_bdf_step(rs_grid *G, double dt, int order, const rs_solve_opts *o, rs_ste
         }
     }
     int status = RS_OK;
+    bool stalled = false;
     if (!std::isfinite(r)) status = RS_ENONFINITE;
     else if (r > o->tol_abs && !stagnated) status = RS_ENOTCONV;
+    else if (stagnated && best > o->tol_abs) {
+        // two cycles without a new minimum: the rounding floor, unless the
+        // best residual is far above the size of the defect's terms (a cycle
+        // that diverges or stalls)
+        double sc;
+        e = defect_scale(G, &sc);
+        if (e) return e;
+        if (!(best <= kFloorRel * sc)) {
+            status = RS_ENOTCONV;
+            stalled = true;
+        }
+    }
     if (st) {
         st->cycles = cycles;
         st->status = status;
@@ -1005,7 +1038,8 @@ int rs_bdf_step(rs_grid *G, double dt, int order, const rs_solve_opts *o, rs_ste
     }
     if (status != RS_OK) {
         return fail(status, status == RS_ENONFINITE ? "residual is not finite"
-                                                    : "tolerance not reached in max_cycles");
+                            : stalled ? "the cycle stalled far above the rounding floor (it diverges)"
+                                      : "tolerance not reached in max_cycles");
     }
     return rs_end_step(G);
 }

@@ -589,6 +589,43 @@ __global__ __launch_bounds__(256) void k_residual_pair(Geo g, Law L, Step st, co
     }
 }
 
+// Size of the terms the defect of a node sums (|g|, a |theta|, the sink,
+// xi |psi| and each |m_ij (psi_i - psi_j)|), maximised over the unknowns: the
+// scale of the defect's rounding floor.
+template <int MODEL, bool SINK, int DIM>
+__global__ __launch_bounds__(256) void k_defect_scale(Geo g, Law L, Step st, const double *beta,
+                                                      const double *K, const double *gv,
+                                                      const double *psi, unsigned long long *out,
+                                                      NodeMap nm)
+{
+    double v = 0.0;
+    const unsigned long long t =
+        (unsigned long long)xcd_block(gridDim.x / 8u) * blockDim.x + threadIdx.x;
+    if (t < (unsigned long long)g.N) {
+        int i, j, k;
+        node_ijk(nm, t, i, j, k);
+        if (!dirichlet_at(g, i, j, k, nullptr)) {
+            const long long idx = (long long)t;
+            const Stencil<DIM> sn = stencil<DIM>(g, i, j, k, idx);
+            const double x = psi[idx], Ki = K[idx];
+            double th;
+            if constexpr (MODEL == kMulti) th = theta_only(L.soils[g.soil[idx]], x);
+            else th = theta_only_t<MODEL>(L, x);
+            v = fabs(gv[idx]) + fabs(st.a * th) + fabs(L.xi * x);
+            if (SINK) {
+                double fa, dfa;
+                feddes(L, x, fa, dfa);
+                v += fabs(beta[(DIM == 1) ? i : (DIM == 2 ? j : k)] * fa);
+            }
+#pragma unroll
+            for (int q = 0; q < 2 * DIM; ++q)
+                v += fabs(sn.cf[q] * (Ki + K[sn.jn[q]]) * (x - psi[sn.jn[q]]));
+        }
+    }
+    v = block_max(v);
+    if (threadIdx.x == 0) atomicMax(out, (unsigned long long)__double_as_longlong(v));
+}
+
 // ---------------------------------------------------------------------------
 // Transfers (section 3.2 steps 3, 4 and 6)
 // ---------------------------------------------------------------------------
@@ -791,6 +828,25 @@ struct CoarseRhsLaunch {
                            g, law, st, beta, K, psibar, gvec, psi, node_map(g));
     }
 };
+
+struct ScaleLaunch {
+    const Geo &g; const Law &law; const Step &st; const double *beta; const double *K;
+    const double *gvec; const double *psi; unsigned long long *out; hipStream_t s;
+    template <int M, bool S, int D>
+    void go()
+    {
+        hipLaunchKernelGGL((k_defect_scale<M, S, D>),
+                           dim3(xcd_grid(((unsigned long long)g.N + 255) / 256)), dim3(256), 0, s,
+                           g, law, st, beta, K, gvec, psi, out, node_map(g));
+    }
+};
+
+void launch_defect_scale(const Geo &g, const Law &law, const Step &st, const double *beta,
+                         const double *K, const double *gvec, const double *psi,
+                         unsigned long long *out, hipStream_t s)
+{
+    dispatch<true>(law, g.dim, ScaleLaunch{g, law, st, beta, K, gvec, psi, out, s});
+}
 
 struct ResidualLaunch {
     const Geo &g; const Law &law; const Step &st; const double *beta; const double *K;

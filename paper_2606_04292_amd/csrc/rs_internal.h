@@ -129,6 +129,11 @@ struct MpStart {
 void launch_residual(const Geo &g, const Law &law, const Step &st, const double *beta,
                      const double *K, const double *gvec, const double *psi, double *d,
                      unsigned long long *norm_bits, hipStream_t s, MpStart mp = {});
+// max over the unknowns of the summed magnitudes of the defect's terms, as
+// the bits of a non-negative double, atomically max-ed into *out
+void launch_defect_scale(const Geo &g, const Law &law, const Step &st, const double *beta,
+                         const double *K, const double *gvec, const double *psi,
+                         unsigned long long *out, hipStream_t s);
 void launch_restrict(const Geo &gc, const Geo &gf, const double *psi_f, const double *d_f,
                      double *psibar_c, double *g_c, hipStream_t s);
 void launch_coarse_rhs(const Geo &gc, const Law &law, const Step &st, const double *beta,

@@ -463,6 +463,26 @@ def test_fused_sweep_is_independent_of_the_tiling(torch_cuda):
     assert rel(outs[0], S.psi()) <= TOL_SWEEP
 
 
+def test_a_diverging_cycle_is_not_reported_as_converged(torch_cuda):
+    """With the stagnation stop on, a step whose cycle diverges (injected K* on
+    a column whose start is drawn per node) ends as RS_ENOTCONV, leaving the
+    history; with averaged coarse K* the same step reaches the rounding floor
+    and returns RS_OK."""
+    w = CASES["rough_col1025_fw"]
+    opts = rsl.solve_opts(w.nu1, w.nu2, w.nu_coarse, max_cycles=400, tol_abs=0.0, stagnation=1)
+    G = rsl.Grid(dataclasses.replace(w, law=dataclasses.replace(w.law, coarse_k=W.COARSE_INJECT)))
+    code, st = G.bdf_step(opts=opts)
+    say("injected K*: code", code, "cycles", st.cycles, "res0 %.2e res %.2e" % (st.res0, st.res))
+    assert code == rsl.RS_ENOTCONV
+    assert G.get_state()[2] == 0          # history not advanced
+    G.close()
+    G = rsl.Grid(w)
+    code, st = G.bdf_step(opts=opts)
+    say("averaged K*: code", code, "cycles", st.cycles, "res0 %.2e res %.2e" % (st.res0, st.res))
+    assert code == rsl.RS_OK and st.res < 1e-10 * st.res0
+    G.close()
+
+
 def test_layered_media_errors(torch_cuda):
     """Layered media and the Gardner law run on FP64 grids; a soil index beyond
     the table is refused; the serving engine refuses both."""
