@@ -92,7 +92,12 @@ struct EDyn {
     int state, end_prev, steps_done, corr, corr_total, corr_max, slow, order_eff, status, pad;
     double a, r0, best, res;
     unsigned long long norm_bits;
+    unsigned long long scale_bits;   // max over nodes of |g| + |N(psi)| (scale of the defect's floor)
 };
+
+// A stall counts as the rounding floor when the best defect norm is within
+// this fraction of the defect's scale (about 1e6 ulp).
+constexpr double kEngFloorRel = 1e6 * 2.220446049250313e-16;
 
 // Work list: count items (slot, level) and three tile prefix sums:
 // kind 0 = colour-packed cells of the level, 1 = nodes of the level,
@@ -255,7 +260,7 @@ __global__ __launch_bounds__(256) void e_defect(const EList *FL, const ESlot *sl
                                                 const ELevel *levels, int want)
 {
     const EList L = *FL;
-    double v = 0.0;
+    double v = 0.0, vs = 0.0;
     tile_loop(L, 1, [&](int it, unsigned tile) {
         const int s = L.slot[it];
         if (dyn[s].state != want) return;
@@ -273,6 +278,8 @@ __global__ __launch_bounds__(256) void e_defect(const EList *FL, const ESlot *sl
                 r = S.g[t] - apply_N_t<decltype(M)::value, false, decltype(Dm)::value, true>(
                                  L0.geo, S.law, a, nullptr, S.K, S.psi, i, j, k, (long long)t);
             });
+            const double sc = fabs(S.g[t]) + fabs(S.g[t] - r);
+            vs = sc > vs ? sc : vs;
         }
         const double ar = fabs(r);
         v = (ar > v || ar != ar) ? ar : v;
@@ -290,7 +297,11 @@ __global__ __launch_bounds__(256) void e_defect(const EList *FL, const ESlot *sl
         const double m = block_max(v);
         if (threadIdx.x == 0) atomicMax(&dyn[s].norm_bits, (unsigned long long)__double_as_longlong(m));
         __syncthreads();
+        const double ms = block_max(vs);
+        if (threadIdx.x == 0) atomicMax(&dyn[s].scale_bits, (unsigned long long)__double_as_longlong(ms));
+        __syncthreads();
         v = 0.0;
+        vs = 0.0;
     });
 }
 
@@ -305,9 +316,11 @@ __global__ __launch_bounds__(256) void e_control(const ESlot *slots, EDyn *dyn, 
         EDyn D = dyn[s];
         const ESlot &S = slots[s];
         double res = __longlong_as_double((long long)D.norm_bits);
+        const double scale = __longlong_as_double((long long)D.scale_bits);
         if (mode == 0) {
             if (D.state != kBegin) continue;
             D.norm_bits = 0ull;
+            D.scale_bits = 0ull;
             D.res = res;
             D.r0 = res;
             D.best = res;
@@ -324,6 +337,7 @@ __global__ __launch_bounds__(256) void e_control(const ESlot *slots, EDyn *dyn, 
         }
         if (D.state != kActive) continue;
         D.norm_bits = 0ull;
+        D.scale_bits = 0ull;
         D.res = res;
         D.corr += 1;
         D.corr_total += 1;
@@ -338,8 +352,18 @@ __global__ __launch_bounds__(256) void e_control(const ESlot *slots, EDyn *dyn, 
             if (res < D.best) {
                 D.best = res;
                 D.slow = 0;
-            } else if (++D.slow >= 2) {
-                done = true;
+            } else if (++D.slow >= 2 && !done) {
+                // two corrections without a new minimum: the rounding floor if
+                // the best norm is near the defect's scale, else the iteration
+                // diverges or stalls
+                if (D.best <= kEngFloorRel * scale) {
+                    done = true;
+                } else {
+                    D.state = kFailed;
+                    D.status = RS_ENOTCONV;
+                    dyn[s] = D;
+                    continue;
+                }
             }
         }
         if (done) {

@@ -150,6 +150,24 @@ def test_admission_follows_the_arena_footprint(torch_cuda):
         assert rel(res[q][0], oracle_solution(w)) <= TOL_CONV
 
 
+def test_a_diverging_request_fails_instead_of_finishing(torch_cuda):
+    """A request whose cycle diverges (a column whose start is drawn per node,
+    so K* jumps by decades; the engine injects coarse K*) stops under the
+    stagnation rule as RS_REQ_FAILED / RS_ENOTCONV rather than as a false
+    rounding floor; a smooth request served beside it finishes."""
+    g = W.GridSpec(dim=1, n=[1025], L=[0.5], face_bc=[W.BC_NOFLUX, W.BC_DIRICHLET], face_value=[0.0, -0.5])
+    rough = -0.2 - 0.6 * np.random.default_rng(W.seed_sequence(9, 0)).random(g.shape)
+    import dataclasses
+    bad = W.Workload("rough_column1025", g, dataclasses.replace(W.config1(5).law, xi=1e-5), rough,
+                     dt=120.0, steps=2, order=2)
+    good = small_requests(1)[0]
+    res = serve_all([bad, good], serve.engine_opts())
+    assert res[0][1].state == serve.RS_REQ_FAILED
+    assert res[0][1].status == rsl.RS_ENOTCONV
+    assert res[1][1].state == serve.RS_REQ_FINISHED
+    assert rel(res[1][0], oracle_solution(good)) <= TOL_CONV
+
+
 def test_unsupported_requests_are_rejected(torch_cuda):
     opts = serve.engine_opts(max_slots=4)
     E = serve.Engine(serve.control_bytes(opts) + (64 << 20), opts)
