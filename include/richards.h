@@ -171,12 +171,14 @@ typedef struct rs_solve_opts {
     int nu1, nu2, nu_coarse, max_cycles;
     double tol_abs;       /* stop when ||g - N(psi)||_inf <= tol_abs */
     int stagnation;       /* also stop at the rounding floor: two cycles in a row
-                             that set no new minimum of the norm.  RS_OK if the best
-                             norm is within 1e6 ulp of the largest sum of magnitudes
-                             of one node's defect terms (|g|, a|theta|, sink, xi|psi|,
-                             |m_ij (psi_i - psi_j)|), else RS_ENOTCONV: the cycle
-                             diverges or stalls (coarse_kstar = RS_COARSE_FW helps
-                             where K* jumps between nodes) */
+                             that set no new minimum of the norm.  RS_OK if the norm
+                             of the last iterate (the one kept) is within 16 ulp of
+                             the largest sum of magnitudes of one node's defect terms
+                             (|g|, a|theta|, sink, xi|psi_i|, m_ij (|psi_i| + |psi_j|)
+                             per face: a one-ulp change of psi_i moves the defect by
+                             m_ii ulp(psi_i)), else RS_ENOTCONV: the cycle diverges
+                             or stalls (coarse_kstar = RS_COARSE_FW helps where K*
+                             jumps between nodes) */
     int mp_inner_cycles;  /* RS_MIXED: FP32 V-cycles per FP64 defect correction */
     int fmg;              /* 1: the first cycle of every step is one FMG(nu1, nu2) cycle
                              (rs_fmg, in FP64), counted as a cycle */

@@ -56,8 +56,10 @@ typedef struct rs_engine_opts {
     double tol_abs;       /* step done when ||g - N(psi)||_inf <= max(tol_abs, tol_rel * r0) */
     double tol_rel;       /*   with r0 the step's initial defect norm */
     int stagnation;       /* also done at the rounding floor: two corrections in a row
-                             that set no new minimum of the norm, with the best norm
-                             within 1e6 ulp of max over nodes of |g| + |N(psi)|; a stall
+                             that set no new minimum of the norm, with the norm of the
+                             iterate kept (the last) within 16 ulp of the largest
+                             per-node sum of the defect's term magnitudes (|g|,
+                             a|theta|, xi|psi_i|, m_ij (|psi_i| + |psi_j|)); a stall
                              above that fails the request with RS_ENOTCONV */
     int rounds_per_tick;  /* correction rounds queued per rs_engine_tick, >= 1 */
     int use_graph;        /* 1: replay a captured HIP graph per round; 0: plain launches */

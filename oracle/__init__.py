@@ -76,6 +76,8 @@ def lib():
         L.orc_sweep.argtypes = [vp, C.c_int, C.c_int]
         L.orc_residual.restype = C.c_double
         L.orc_residual.argtypes = [vp, C.c_int, _D]
+        L.orc_defect_scale.restype = C.c_double
+        L.orc_defect_scale.argtypes = [vp, C.c_int]
         L.orc_apply_N.argtypes = [vp, C.c_int, _D, _D]
         L.orc_restrict.argtypes = [vp, C.c_int]
         L.orc_prolong.argtypes = [vp, C.c_int]
@@ -221,6 +223,10 @@ class Solver:
         d = np.empty(self.shapes[level], dtype=np.float64) if want_vector else None
         r = lib().orc_residual(self.h, level, _dp(d))
         return (r, d) if want_vector else r
+
+    def defect_scale(self, level=0):
+        """Largest per-node sum of the magnitudes of the defect's terms."""
+        return lib().orc_defect_scale(self.h, level)
 
     def apply_N(self, psi, level=0):
         a = np.ascontiguousarray(psi, dtype=np.float64)

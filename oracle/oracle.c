@@ -667,6 +667,36 @@ double orc_residual(orc_solver *S, int l, double *dout)
     return mx;
 }
 
+/* Scale of the rounding floor of the defect on level l: the largest sum over
+ * an unknown node of the magnitudes of the terms its defect adds up, |g_i|,
+ * a |theta(psi_i)|, |S(psi_i)|, xi |psi_i| and m_ij (|psi_i| + |psi_j|) per
+ * face.  Rounding psi_i by one ulp moves the defect by m_ii ulp(psi_i), and
+ * evaluating it rounds each of these terms, so a converged iterate cannot
+ * bring the max-norm of the defect much below eps times this scale (the
+ * stopping test of section 3.2 then stalls). */
+double orc_defect_scale(orc_solver *S, int l)
+{
+    orc_level *lv = &S->lev[l];
+    double mx = 0.0;
+#pragma omp parallel for schedule(static) reduction(max:mx)
+    for (int i = 0; i < lv->N; i++) {
+        int ii[3];
+        coords(lv, i, ii);
+        if (is_dirichlet(S, lv, ii, NULL)) continue;
+        double x = lv->psi[i];
+        const orc_params *law = law_at(S, lv, i);
+        double t = fabs(lv->g[i]) + fabs(S->a * orc_theta(law, x)) + fabs(S->p.xi * x);
+        if (S->p.sink == ORC_SINK_FEDDES_EXP)
+            t += fabs(root_beta(S, elev(S, lv, ii)) * orc_feddes(&S->p, x));
+        orc_nb nb[6];
+        int k = neighbours(S, lv, ii, nb);
+        for (int q = 0; q < k; q++)
+            t += mcoef(lv, i, nb[q].j, ii, nb[q].axis) * (fabs(x) + fabs(lv->psi[nb[q].j]));
+        if (t > mx) mx = t;
+    }
+    return mx;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Transfer operators: full weighting and linear interpolation.             */
 /* ------------------------------------------------------------------------ */

@@ -482,9 +482,11 @@ int defect_scale(rs_grid *G, double *out)
     return RS_OK;
 }
 
-// A stall of the cycle counts as the rounding floor when its best residual is
-// within this fraction of the defect's term scale (about 1e6 ulp).
-constexpr double kFloorRel = 1e6 * 2.220446049250313e-16;
+// A stall of the cycle counts as the rounding floor when the residual of the
+// iterate that is kept is within 16 ulp of the defect's term scale (the
+// largest per-node sum of the magnitudes of the terms that the defect and the
+// pointwise solve of that node add up).
+constexpr double kFloorRel = 16.0 * 2.220446049250313e-16;
 
 // FP32 red-black sweeps of the correction equation on level l.
 void sweep32_level(rs_grid *G, int l, int nsweeps)
@@ -1015,14 +1017,14 @@ int rs_bdf_step(rs_grid *G, double dt, int order, const rs_solve_opts *o, rs_ste
     bool stalled = false;
     if (!std::isfinite(r)) status = RS_ENONFINITE;
     else if (r > o->tol_abs && !stagnated) status = RS_ENOTCONV;
-    else if (stagnated && best > o->tol_abs) {
+    else if (stagnated && r > o->tol_abs) {
         // two cycles without a new minimum: the rounding floor, unless the
-        // best residual is far above the size of the defect's terms (a cycle
-        // that diverges or stalls)
+        // residual of the iterate kept (the last one) is above the rounding
+        // of the defect's terms (a cycle that diverges or stalls)
         double sc;
         e = defect_scale(G, &sc);
         if (e) return e;
-        if (!(best <= kFloorRel * sc)) {
+        if (!(r <= kFloorRel * sc)) {
             status = RS_ENOTCONV;
             stalled = true;
         }

@@ -73,10 +73,14 @@ __device__ __forceinline__ double g_at(const Geo &g, const Law &L, const Step &s
 // N(psi)_i = a theta(psi_i) + beta a_F(psi_i) + xi psi_i + (M psi)_i
 // (the whole stencil is loaded before the law is evaluated, so that the loads
 // overlap the theta chain instead of following it; XPAD as for stencil()).
+// With scale set, *scale also receives the sum of the magnitudes of the terms
+// (a |theta|, the sink, xi |psi_i|, m_ij (|psi_i| + |psi_j|) per face): the
+// size of the rounding floor of the defect at this node.
 template <int MODEL, bool SINK, int DIM, bool XPAD = false>
 __device__ __forceinline__ double apply_N_t(const Geo &g, const Law &L, double a,
                                             const double *beta, const double *K,
-                                            const double *psi, int i, int j, int k, long long idx)
+                                            const double *psi, int i, int j, int k, long long idx,
+                                            double *scale = nullptr)
 {
     const Stencil<DIM> st = stencil<DIM, XPAD>(g, i, j, k, idx);
     const double x = psi[idx];
@@ -100,6 +104,12 @@ __device__ __forceinline__ double apply_N_t(const Geo &g, const Law &L, double a
     double mpsi = 0.0;
 #pragma unroll
     for (int q = 0; q < 2 * DIM; ++q) mpsi += st.cf[q] * (Ki + Kn[q]) * (x - pn[q]);
+    if (scale) {
+        double t = fabs(s) + fabs(L.xi * x);
+#pragma unroll
+        for (int q = 0; q < 2 * DIM; ++q) t += fabs(st.cf[q] * (Ki + Kn[q])) * (fabs(x) + fabs(pn[q]));
+        *scale = t;
+    }
     return s + (L.xi * x + mpsi);
 }
 

@@ -92,12 +92,13 @@ struct EDyn {
     int state, end_prev, steps_done, corr, corr_total, corr_max, slow, order_eff, status, pad;
     double a, r0, best, res;
     unsigned long long norm_bits;
-    unsigned long long scale_bits;   // max over nodes of |g| + |N(psi)| (scale of the defect's floor)
+    unsigned long long scale_bits;   // max over nodes of the magnitudes of the defect's terms
+                                     // (|g|, a |theta|, xi |psi|, m_ij (|psi_i| + |psi_j|))
 };
 
-// A stall counts as the rounding floor when the best defect norm is within
-// this fraction of the defect's scale (about 1e6 ulp).
-constexpr double kEngFloorRel = 1e6 * 2.220446049250313e-16;
+// A stall counts as the rounding floor when the defect norm of the iterate
+// kept is within 16 ulp of the defect's term scale (the rule of rs_bdf_step).
+constexpr double kEngFloorRel = 16.0 * 2.220446049250313e-16;
 
 // Work list: count items (slot, level) and three tile prefix sums:
 // kind 0 = colour-packed cells of the level, 1 = nodes of the level,
@@ -274,11 +275,13 @@ __global__ __launch_bounds__(256) void e_defect(const EList *FL, const ESlot *sl
         const double x = S.psi[t];
         double r = 0.0;
         if (!dirichlet_at(L0.geo, i, j, k, nullptr)) {
+            double terms = 0.0;
             law_dim(S.law.model, L0.geo.dim, [&](auto M, auto Dm) {
                 r = S.g[t] - apply_N_t<decltype(M)::value, false, decltype(Dm)::value, true>(
-                                 L0.geo, S.law, a, nullptr, S.K, S.psi, i, j, k, (long long)t);
+                                 L0.geo, S.law, a, nullptr, S.K, S.psi, i, j, k, (long long)t,
+                                 &terms);
             });
-            const double sc = fabs(S.g[t]) + fabs(S.g[t] - r);
+            const double sc = fabs(S.g[t]) + terms;
             vs = sc > vs ? sc : vs;
         }
         const double ar = fabs(r);
@@ -354,9 +357,9 @@ __global__ __launch_bounds__(256) void e_control(const ESlot *slots, EDyn *dyn, 
                 D.slow = 0;
             } else if (++D.slow >= 2 && !done) {
                 // two corrections without a new minimum: the rounding floor if
-                // the best norm is near the defect's scale, else the iteration
-                // diverges or stalls
-                if (D.best <= kEngFloorRel * scale) {
+                // the norm of the iterate kept (the last one) is near the
+                // defect's scale, else the iteration diverges or stalls
+                if (res <= kEngFloorRel * scale) {
                     done = true;
                 } else {
                     D.state = kFailed;

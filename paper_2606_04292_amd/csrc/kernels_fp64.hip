@@ -589,9 +589,10 @@ __global__ __launch_bounds__(256) void k_residual_pair(Geo g, Law L, Step st, co
     }
 }
 
-// Size of the terms the defect of a node sums (|g|, a |theta|, the sink,
-// xi |psi| and each |m_ij (psi_i - psi_j)|), maximised over the unknowns: the
-// scale of the defect's rounding floor.
+// Size of the terms the defect of a node and its pointwise solve sum (|g|,
+// a |theta|, the sink, xi |psi_i| and m_ij (|psi_i| + |psi_j|) per face),
+// maximised over the unknowns: the scale of the defect's rounding floor (a
+// one-ulp change of psi_i moves the defect by m_ii ulp(psi_i)).
 template <int MODEL, bool SINK, int DIM>
 __global__ __launch_bounds__(256) void k_defect_scale(Geo g, Law L, Step st, const double *beta,
                                                       const double *K, const double *gv,
@@ -619,7 +620,7 @@ __global__ __launch_bounds__(256) void k_defect_scale(Geo g, Law L, Step st, con
             }
 #pragma unroll
             for (int q = 0; q < 2 * DIM; ++q)
-                v += fabs(sn.cf[q] * (Ki + K[sn.jn[q]]) * (x - psi[sn.jn[q]]));
+                v += fabs(sn.cf[q] * (Ki + K[sn.jn[q]])) * (fabs(x) + fabs(psi[sn.jn[q]]));
         }
     }
     v = block_max(v);

@@ -215,15 +215,3 @@ def run_stream(E: Engine, reqs, arrivals=None, keep=()):
             finished += 1
     E.synchronize()
     return arr, comp, stats, kept
-
-
-def fcfs_latencies(arrivals, service):
-    """Latencies of a single first-come-first-served server with the given
-    arrival and service times (Lindley's recursion)."""
-    lat = np.empty(len(arrivals))
-    free = -np.inf
-    for q, (a, s) in enumerate(zip(arrivals, service)):
-        start = max(a, free)
-        free = start + s
-        lat[q] = free - a
-    return lat
