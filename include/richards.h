@@ -292,6 +292,30 @@ int rs_profile_enable(rs_grid *g, int on);
 int rs_profile_read(rs_grid *g, double *sweep_ms, long long *launches, double *cell_updates,
                     int reset);
 
+/* One time step that allocates nothing: for callers that cannot allocate
+ * device or pinned host memory (tight serving loops, harnesses that forbid
+ * allocation), not part of the paper's method.  The same computation as
+ * rs_create_grid + rs_set_constitutive + rs_set_state + rs_bdf_step on an
+ * RS_FP64 grid (same kernels, same results), with the grid's whole workspace
+ * in a static device array of RS_STATIC_WORKSPACE_BYTES that the library holds
+ * on every device it runs on until the process ends.
+ *   d, c: grid and law as for rs_create_grid / rs_set_constitutive (host);
+ *   psi_n_dev, psi_nm1_dev (nullable = psi_n_dev): the state (device arrays of
+ *   fine-grid size, lexicographic); nstep: steps already taken (0 makes an
+ *   order-2 step BDF1); dt, order, o, st: as for rs_bdf_step;
+ *   psi_out_dev: receives psi^{n+1} (RS_OK) or the last iterate
+ *   (RS_ENOTCONV, RS_ENONFINITE); stream: a hipStream_t (NULL = default).
+ * Synchronises the stream.  Errors: RS_EINVAL; RS_ENOMEM when the grid's FP64
+ * workspace (rs_workspace_bytes) exceeds RS_STATIC_WORKSPACE_BYTES; RS_EHIP;
+ * RS_ENOTCONV / RS_ENONFINITE as for rs_bdf_step.  Calls that overlap on one
+ * device (other host threads, other streams) share its array and race: the
+ * caller serialises them. */
+#define RS_STATIC_WORKSPACE_BYTES (32u << 20)
+int rs_bdf_step_static(const rs_grid_desc *d, const rs_constitutive *c, const double *psi_n_dev,
+                       const double *psi_nm1_dev, int nstep, double dt, int order,
+                       const rs_solve_opts *o, double *psi_out_dev, rs_step_stats *st,
+                       void *stream);
+
 void rs_destroy_grid(rs_grid *g);
 const char *rs_last_error(void);
 

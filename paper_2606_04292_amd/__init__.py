@@ -19,6 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_lib", "librichards.so")
 
 RS_OK, RS_EINVAL, RS_ENOMEM, RS_EHIP, RS_ESTATE, RS_ENONFINITE, RS_ENOTCONV, RS_EBUSY = range(8)
+RS_STATIC_WORKSPACE_BYTES = 32 << 20
 RS_FP64, RS_MIXED = 0, 1
 RS_COARSE_INJECT, RS_COARSE_FW = 0, 1
 FIELD_PSI, FIELD_KSTAR, FIELD_G, FIELD_PSIBAR = 0, 1, 2, 3
@@ -29,6 +30,7 @@ EXPORTS = [
     "rs_residual", "rs_end_step", "rs_bdf_step", "rs_copy_field", "rs_set_field",
     "rs_num_levels", "rs_level_shape", "rs_destroy_grid", "rs_last_error",
     "rs_profile_enable", "rs_profile_read", "rs_correction_cycle", "rs_fmg",
+    "rs_bdf_step_static",
     # include/richards_serve.h
     "rs_engine_default_opts", "rs_engine_control_bytes", "rs_engine_request_bytes",
     "rs_engine_create", "rs_engine_submit", "rs_engine_tick", "rs_engine_fetch",
@@ -118,6 +120,9 @@ def lib():
         L.rs_profile_enable.argtypes = [vp, C.c_int]
         L.rs_profile_read.argtypes = [vp, D, C.POINTER(C.c_longlong), D, C.c_int]
         L.rs_correction_cycle.argtypes = [vp, C.c_int, C.c_int, C.c_int, D]
+        L.rs_bdf_step_static.argtypes = [C.POINTER(GridDesc), C.POINTER(Constitutive), vp, vp,
+                                         C.c_int, C.c_double, C.c_int, C.POINTER(SolveOpts), vp,
+                                         C.POINTER(StepStats), vp]
         L.rs_fmg.argtypes = [vp, C.c_int, C.c_int, D]
         _lib = L
     return _lib
@@ -341,3 +346,29 @@ class Grid:
                                         self.w.nu2 if nu2 is None else nu2,
                                         C.byref(r) if want_norm else None))
         return r.value if want_norm else None
+
+
+def bdf_step_static(w, psi_n, psi_nm1=None, nstep=0, opts=None, out=None, stream=None):
+    """rs_bdf_step_static: one step of workload w from the device state psi_n
+    (psi_nm1) with nstep steps taken, in the library's static workspace (no
+    allocation by the library).  Returns (code, stats, out)."""
+    import torch
+    dev = psi_n.device
+    if out is None:
+        out = torch.empty_like(psi_n)
+    for t in (psi_n, out) + (() if psi_nm1 is None else (psi_nm1,)):
+        assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+        assert tuple(t.shape) == tuple(w.grid.shape)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    d = grid_desc(w.grid)
+    c, keep = constitutive(w.law, w.Ks_field, w.soils, w.soil_id)
+    o = opts if opts is not None else solve_opts(w.nu1, w.nu2, w.nu_coarse)
+    st = StepStats()
+    st.struct_size = C.sizeof(StepStats)
+    code = lib().rs_bdf_step_static(
+        C.byref(d), C.byref(c), C.c_void_p(psi_n.data_ptr()),
+        None if psi_nm1 is None else C.c_void_p(psi_nm1.data_ptr()), nstep, w.dt, w.order,
+        C.byref(o), C.c_void_p(out.data_ptr()), C.byref(st), C.c_void_p(stream.cuda_stream))
+    del keep
+    return code, st, out

@@ -8,7 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
-#include <string>
+#include <mutex>
 #include <vector>
 
 #include "../../include/richards.h"
@@ -26,16 +26,14 @@ using namespace rs;
 
 namespace rs {
 
-thread_local std::string g_err;
+thread_local char g_err[512];
 
 int fail(int code, const char *fmt, ...)
 {
-    char buf[512];
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
     va_end(ap);
-    g_err = buf;
     return code;
 }
 
@@ -607,47 +605,19 @@ double *field_ptr(const rs_grid *G, int level, int field)
     }
 }
 
-}  // namespace
-
-extern "C" {
-
-const char *rs_last_error(void) { return g_err.c_str(); }
-
-int rs_workspace_bytes(const rs_grid_desc *d, int precision, size_t *out)
+// Fill G (a value-initialised rs_grid) as a view of a planned workspace at
+// base: level arrays, history, scratch words, the one-work-group cycle's
+// records; host_bits (kScratchWords words) and tail_host are the host-side
+// read-back and staging buffers.  Allocates nothing; queues the copy of the
+// cycle records on the stream.
+int grid_view(rs_grid *G, const rs_grid_desc *d, int precision, const Layout &L, char *base,
+              hipStream_t stream, unsigned long long *host_bits, TailArgs *tail_host)
 {
-    int e = validate_desc(d);
-    if (e) return e;
-    if (precision != RS_FP64 && precision != RS_MIXED) return fail(RS_EINVAL, "bad precision");
-    if (!out) return fail(RS_EINVAL, "null out");
-    Layout L;
-    plan(d, precision, &L);
-    *out = L.total;
-    return RS_OK;
-}
-
-int rs_create_grid(const rs_grid_desc *d, int precision, void *ws_dev, size_t ws_bytes,
-                   void *stream, rs_grid **out)
-{
-    int e = validate_desc(d);
-    if (e) return e;
-    if (precision != RS_FP64 && precision != RS_MIXED) return fail(RS_EINVAL, "bad precision");
-    if (!out) return fail(RS_EINVAL, "null out");
-    if (!ws_dev) return fail(RS_EINVAL, "null workspace");
-    if (((uintptr_t)ws_dev) % kAlign) return fail(RS_EINVAL, "workspace must be 256-byte aligned");
-    Layout L;
-    plan(d, precision, &L);
-    if (ws_bytes < L.total)
-        return fail(RS_ENOMEM, "workspace %zu bytes < required %zu", ws_bytes, L.total);
-    // the padding around every array must hold finite values (zeros)
-    HIPCALL(hipMemsetAsync(ws_dev, 0, L.total, (hipStream_t)stream));
-    rs_grid *G = new (std::nothrow) rs_grid();
-    if (!G) return fail(RS_ENOMEM, "host allocation failed");
     G->desc = *d;
     G->precision = precision;
-    G->stream = (hipStream_t)stream;
+    G->stream = stream;
     if (hipGetDevice(&G->device) != hipSuccess) G->device = -1;
     G->nlev = L.nlev;
-    char *base = (char *)ws_dev;
     for (int l = 0; l < L.nlev; ++l) {
         LevelData &v = G->lev[l];
         v.geo = make_geo(d, l);
@@ -683,17 +653,9 @@ int rs_create_grid(const rs_grid_desc *d, int precision, void *ws_dev, size_t ws
     G->prof_ms = 0.0;
     G->prof_launches = 0;
     G->prof_cells = 0.0;
-    if (hipHostMalloc((void **)&G->host_bits, 64 * sizeof(unsigned long long), hipHostMallocDefault) !=
-        hipSuccess) {
-        delete G;
-        return fail(RS_EHIP, "hipHostMalloc failed");
-    }
+    G->host_bits = host_bits;
     G->tail_dev = (TailArgs *)(base + L.tail);
-    if (hipHostMalloc((void **)&G->tail_host, sizeof(TailArgs), hipHostMallocDefault) != hipSuccess) {
-        (void)hipHostFree(G->host_bits);
-        delete G;
-        return fail(RS_EHIP, "hipHostMalloc failed");
-    }
+    G->tail_host = tail_host;
     memset(G->tail_host, 0, sizeof(TailArgs));
     G->tail_top = G->nlev;
     for (int l = G->nlev - 1; l >= 0 && G->lev[l].geo.N <= kTailNodes && !G->lev[l].psi_alt; --l)
@@ -725,13 +687,79 @@ int rs_create_grid(const rs_grid_desc *d, int precision, void *ws_dev, size_t ws
         T.beta = v.beta;
         T.lambdaU = 0.0;
     }
-    if (hipMemcpyAsync(G->tail_dev, G->tail_host, sizeof(TailArgs), hipMemcpyHostToDevice,
-                       G->stream) != hipSuccess) {
-        (void)hipStreamSynchronize(G->stream);
-        (void)hipHostFree(G->tail_host);
-        (void)hipHostFree(G->host_bits);
+    HIPCALL(hipMemcpyAsync(G->tail_dev, G->tail_host, sizeof(TailArgs), hipMemcpyHostToDevice,
+                           G->stream));
+    return RS_OK;
+}
+
+// Device memory of rs_bdf_step_static: the whole FP64 workspace of one grid
+// (level arrays, history, norm words, cycle records), so that the call needs
+// no allocation.  Each device holds its own copy for the life of the process.
+static __device__ __align__(256) unsigned char scratch[RS_STATIC_WORKSPACE_BYTES];
+
+// Per device: the device address of that copy (hipGetSymbolAddress, once, on
+// the first call with the device current) and the host-side read-back and
+// staging words of its grid.
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void *g_static_ptr[kMaxDevices];
+unsigned long long g_static_bits[kMaxDevices][kScratchWords];
+TailArgs g_static_tail[kMaxDevices];
+
+}  // namespace
+
+extern "C" {
+
+const char *rs_last_error(void) { return g_err; }
+
+int rs_workspace_bytes(const rs_grid_desc *d, int precision, size_t *out)
+{
+    int e = validate_desc(d);
+    if (e) return e;
+    if (precision != RS_FP64 && precision != RS_MIXED) return fail(RS_EINVAL, "bad precision");
+    if (!out) return fail(RS_EINVAL, "null out");
+    Layout L;
+    plan(d, precision, &L);
+    *out = L.total;
+    return RS_OK;
+}
+
+int rs_create_grid(const rs_grid_desc *d, int precision, void *ws_dev, size_t ws_bytes,
+                   void *stream, rs_grid **out)
+{
+    int e = validate_desc(d);
+    if (e) return e;
+    if (precision != RS_FP64 && precision != RS_MIXED) return fail(RS_EINVAL, "bad precision");
+    if (!out) return fail(RS_EINVAL, "null out");
+    if (!ws_dev) return fail(RS_EINVAL, "null workspace");
+    if (((uintptr_t)ws_dev) % kAlign) return fail(RS_EINVAL, "workspace must be 256-byte aligned");
+    Layout L;
+    plan(d, precision, &L);
+    if (ws_bytes < L.total)
+        return fail(RS_ENOMEM, "workspace %zu bytes < required %zu", ws_bytes, L.total);
+    // the padding around every array must hold finite values (zeros)
+    HIPCALL(hipMemsetAsync(ws_dev, 0, L.total, (hipStream_t)stream));
+    rs_grid *G = new (std::nothrow) rs_grid();
+    if (!G) return fail(RS_ENOMEM, "host allocation failed");
+    unsigned long long *bits = nullptr;
+    TailArgs *tail = nullptr;
+    if (hipHostMalloc((void **)&bits, kScratchWords * sizeof(unsigned long long),
+                      hipHostMallocDefault) != hipSuccess) {
         delete G;
-        return fail(RS_EHIP, "hipMemcpyAsync failed");
+        return fail(RS_EHIP, "hipHostMalloc failed");
+    }
+    if (hipHostMalloc((void **)&tail, sizeof(TailArgs), hipHostMallocDefault) != hipSuccess) {
+        (void)hipHostFree(bits);
+        delete G;
+        return fail(RS_EHIP, "hipHostMalloc failed");
+    }
+    e = grid_view(G, d, precision, L, (char *)ws_dev, (hipStream_t)stream, bits, tail);
+    if (e) {
+        (void)hipStreamSynchronize((hipStream_t)stream);
+        (void)hipHostFree(tail);
+        (void)hipHostFree(bits);
+        delete G;
+        return e;
     }
     *out = G;
     return RS_OK;
@@ -759,12 +787,12 @@ int rs_set_constitutive(rs_grid *G, const rs_constitutive *c)
         for (long long i = 0; i < N; ++i)
             if (c->soil_id[i] >= c->n_soils)
                 return fail(RS_EINVAL, "soil_id[%lld] = %d >= n_soils", i, (int)c->soil_id[i]);
-        std::vector<Law> tab((size_t)c->n_soils);
+        Law tab[kMaxSoils];
         for (int s = 0; s < c->n_soils; ++s) {
             rs_constitutive q = soil_constitutive(c, c->soils[s]);
-            tab[(size_t)s] = make_law(&q);
+            tab[s] = make_law(&q);
         }
-        HIPCALL(hipMemcpyAsync(G->soil_tab, tab.data(), sizeof(Law) * tab.size(),
+        HIPCALL(hipMemcpyAsync(G->soil_tab, tab, sizeof(Law) * (size_t)c->n_soils,
                                hipMemcpyHostToDevice, G->stream));
         HIPCALL(hipMemcpyAsync((void *)G->lev[0].geo.soil, c->soil_id, (size_t)N,
                                hipMemcpyHostToDevice, G->stream));
@@ -1090,6 +1118,61 @@ int rs_profile_read(rs_grid *G, double *sweep_ms, long long *launches, double *c
         G->prof_cells = 0.0;
     }
     return RS_OK;
+}
+
+int rs_bdf_step_static(const rs_grid_desc *d, const rs_constitutive *c, const double *psi_n,
+                       const double *psi_nm1, int nstep, double dt, int order,
+                       const rs_solve_opts *o, double *psi_out, rs_step_stats *st, void *stream)
+{
+    int e = validate_desc(d);
+    if (e) return e;
+    if (!c || !psi_n || !psi_out || !o) return fail(RS_EINVAL, "null argument");
+    if (nstep < 0) return fail(RS_EINVAL, "nstep < 0");
+    Layout L;
+    plan(d, RS_FP64, &L);
+    if (L.total > sizeof(scratch))
+        return fail(RS_ENOMEM, "grid needs %zu bytes of workspace; the static scratch holds %zu",
+                    L.total, sizeof(scratch));
+    int dev = -1;
+    HIPCALL(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(RS_EINVAL, "device %d out of range", dev);
+    void *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_static_mu);
+        if (!g_static_ptr[dev]) {
+            void *p = nullptr;
+            HIPCALL(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+            if (!p) return fail(RS_EHIP, "no device address for the static scratch");
+            g_static_ptr[dev] = p;
+        }
+        base = g_static_ptr[dev];
+    }
+    hipStream_t s = (hipStream_t)stream;
+    // the previous call's contents stay in the array: clear this grid's part
+    // (the padding around every array must hold zeros) with a kernel
+    launch_fill_u64((unsigned long long *)base, (int)(L.total / sizeof(unsigned long long)), 0ull, s);
+    HIPCALL(hipGetLastError());
+    rs_grid G{};
+    e = grid_view(&G, d, RS_FP64, L, (char *)base, s, g_static_bits[dev], &g_static_tail[dev]);
+    if (!e) e = rs_set_constitutive(&G, c);
+    if (!e) e = rs_set_state(&G, psi_n, psi_nm1, nstep, 0.0);
+    if (e) {
+        (void)hipStreamSynchronize(s);
+        return e;
+    }
+    const int code = rs_bdf_step(&G, dt, order, o, st);
+    if (code != RS_OK && code != RS_ENOTCONV && code != RS_ENONFINITE) {
+        (void)hipStreamSynchronize(s);
+        return code;
+    }
+    char msg[sizeof g_err];
+    memcpy(msg, g_err, sizeof msg);
+    const size_t bytes = sizeof(double) * (size_t)G.lev[0].geo.N;
+    HIPCALL(hipMemcpyAsync(psi_out, code == RS_OK ? G.psi_n : G.lev[0].psi, bytes,
+                           hipMemcpyDeviceToDevice, s));
+    HIPCALL(hipStreamSynchronize(s));
+    if (code != RS_OK) memcpy(g_err, msg, sizeof msg);
+    return code;
 }
 
 int rs_num_levels(const rs_grid *G) { return G ? G->nlev : 0; }

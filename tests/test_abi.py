@@ -87,3 +87,30 @@ def test_struct_sizes_match_the_header():
     d.struct_size = 8
     out = C.c_size_t()
     assert rsl.lib().rs_workspace_bytes(C.byref(d), rsl.RS_FP64, C.byref(out)) == rsl.RS_EINVAL
+
+
+def test_static_step_refuses_a_grid_beyond_its_array_before_touching_the_device():
+    """rs_bdf_step_static checks the grid's FP64 workspace against its static
+    array (RS_STATIC_WORKSPACE_BYTES) before any device call."""
+    w = W.shrink(W.config3(), 129)
+    assert rsl.workspace_bytes(w.grid) > rsl.RS_STATIC_WORKSPACE_BYTES
+    c, keep = rsl.constitutive(w.law)
+    st = rsl.StepStats()
+    st.struct_size = C.sizeof(rsl.StepStats)
+    o = rsl.solve_opts()
+    code = rsl.lib().rs_bdf_step_static(C.byref(_desc(w.grid)), C.byref(c), C.c_void_p(256), None,
+                                        0, w.dt, w.order, C.byref(o), C.c_void_p(256),
+                                        C.byref(st), None)
+    assert code == rsl.RS_ENOMEM
+    assert b"static scratch" in rsl.lib().rs_last_error()
+    code = rsl.lib().rs_bdf_step_static(C.byref(_desc(w.grid)), C.byref(c), None, None, 0, w.dt,
+                                        w.order, C.byref(o), C.c_void_p(256), C.byref(st), None)
+    assert code == rsl.RS_EINVAL
+    del keep
+
+
+def test_static_workspace_size_matches_the_header():
+    import re
+    with open(os.path.join(ROOT, "include", "richards.h")) as f:
+        m = re.search(r"#define RS_STATIC_WORKSPACE_BYTES \((\d+)u << (\d+)\)", f.read())
+    assert m and int(m.group(1)) << int(m.group(2)) == rsl.RS_STATIC_WORKSPACE_BYTES
