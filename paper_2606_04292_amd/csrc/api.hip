@@ -621,6 +621,10 @@ int grid_view(rs_grid *G, const rs_grid_desc *d, int precision, const Layout &L,
     for (int l = 0; l < L.nlev; ++l) {
         LevelData &v = G->lev[l];
         v.geo = make_geo(d, l);
+        // rows split by parity: a colour pass reads and writes whole cache
+        // lines of its own colour (the C ABI exchanges lexicographic arrays)
+        v.geo.xs = 1;
+        v.geo.xh = (v.geo.n[0] + 1) / 2;
         v.geo.soil = (const unsigned char *)(base + L.soil_off[l]);
         v.psi = (double *)(base + L.lev_off[l][0]);
         v.K = (double *)(base + L.lev_off[l][1]);
@@ -794,8 +798,11 @@ int rs_set_constitutive(rs_grid *G, const rs_constitutive *c)
         }
         HIPCALL(hipMemcpyAsync(G->soil_tab, tab, sizeof(Law) * (size_t)c->n_soils,
                                hipMemcpyHostToDevice, G->stream));
-        HIPCALL(hipMemcpyAsync((void *)G->lev[0].geo.soil, c->soil_id, (size_t)N,
-                               hipMemcpyHostToDevice, G->stream));
+        // staged in the level's defect array, then reordered to the row layout
+        unsigned char *stage = (unsigned char *)G->lev[0].d;
+        HIPCALL(hipMemcpyAsync(stage, c->soil_id, (size_t)N, hipMemcpyHostToDevice, G->stream));
+        launch_relayout_u8(G->lev[0].geo, stage, (unsigned char *)G->lev[0].geo.soil, true,
+                           G->stream);
         for (int l = 1; l < G->nlev; ++l)
             launch_inject_u8(G->lev[l].geo, G->lev[l - 1].geo, G->lev[l - 1].geo.soil,
                              (unsigned char *)G->lev[l].geo.soil, G->stream);
@@ -809,7 +816,9 @@ int rs_set_constitutive(rs_grid *G, const rs_constitutive *c)
     G->coarse_k = c->coarse_kstar;
     if (c->Ks_field) {
         size_t bytes = sizeof(double) * (size_t)G->lev[0].geo.N;
-        HIPCALL(hipMemcpyAsync(G->ks, c->Ks_field, bytes, hipMemcpyHostToDevice, G->stream));
+        HIPCALL(hipMemcpyAsync(G->lev[0].d, c->Ks_field, bytes, hipMemcpyHostToDevice, G->stream));
+        launch_relayout(G->lev[0].geo, G->lev[0].d, G->ks, true, G->stream);
+        HIPCALL(hipGetLastError());
         HIPCALL(hipStreamSynchronize(G->stream));
         G->has_ks = true;
     } else {
@@ -836,10 +845,10 @@ int rs_set_constitutive(rs_grid *G, const rs_constitutive *c)
 int rs_set_state(rs_grid *G, const double *psi_n, const double *psi_nm1, int nstep, double t)
 {
     if (!G || !psi_n) return fail(RS_EINVAL, "null argument");
-    size_t bytes = sizeof(double) * (size_t)G->lev[0].geo.N;
-    HIPCALL(hipMemcpyAsync(G->psi_n, psi_n, bytes, hipMemcpyDeviceToDevice, G->stream));
-    HIPCALL(hipMemcpyAsync(G->psi_nm1, psi_nm1 ? psi_nm1 : psi_n, bytes, hipMemcpyDeviceToDevice,
-                           G->stream));
+    const Geo &g0 = G->lev[0].geo;
+    launch_relayout(g0, psi_n, G->psi_n, true, G->stream);
+    launch_relayout(g0, psi_nm1 ? psi_nm1 : psi_n, G->psi_nm1, true, G->stream);
+    HIPCALL(hipGetLastError());
     G->nstep = nstep;
     G->t = t;
     G->in_step = false;
@@ -849,10 +858,10 @@ int rs_set_state(rs_grid *G, const double *psi_n, const double *psi_nm1, int nst
 int rs_get_state(const rs_grid *G, double *psi_n, double *psi_nm1, int *nstep, double *t)
 {
     if (!G) return fail(RS_EINVAL, "null grid");
-    size_t bytes = sizeof(double) * (size_t)G->lev[0].geo.N;
-    if (psi_n) HIPCALL(hipMemcpyAsync(psi_n, G->psi_n, bytes, hipMemcpyDeviceToDevice, G->stream));
-    if (psi_nm1)
-        HIPCALL(hipMemcpyAsync(psi_nm1, G->psi_nm1, bytes, hipMemcpyDeviceToDevice, G->stream));
+    const Geo &g0 = G->lev[0].geo;
+    if (psi_n) launch_relayout(g0, G->psi_n, psi_n, false, G->stream);
+    if (psi_nm1) launch_relayout(g0, G->psi_nm1, psi_nm1, false, G->stream);
+    HIPCALL(hipGetLastError());
     if (nstep) *nstep = G->nstep;
     if (t) *t = G->t;
     return RS_OK;
@@ -969,7 +978,8 @@ int rs_residual(rs_grid *G, double *d_dev)
     if (!G || !d_dev) return fail(RS_EINVAL, "null argument");
     if (!G->in_step) return fail(RS_ESTATE, "no active step (call rs_begin_step)");
     LevelData &f = G->lev[0];
-    launch_residual(f.geo, G->law, G->step, f.beta, f.K, f.g, f.psi, d_dev, nullptr, G->stream);
+    launch_residual(f.geo, G->law, G->step, f.beta, f.K, f.g, f.psi, f.d, nullptr, G->stream);
+    launch_relayout(f.geo, f.d, d_dev, false, G->stream);
     HIPCALL(hipGetLastError());
     return RS_OK;
 }
@@ -1080,8 +1090,8 @@ int rs_copy_field(const rs_grid *G, int level, int field, double *dst)
     if (level < 0 || level >= G->nlev) return fail(RS_EINVAL, "level out of range");
     double *p = field_ptr(G, level, field);
     if (!p) return fail(RS_EINVAL, "unknown field %d", field);
-    HIPCALL(hipMemcpyAsync(dst, p, sizeof(double) * (size_t)G->lev[level].geo.N,
-                           hipMemcpyDeviceToDevice, G->stream));
+    launch_relayout(G->lev[level].geo, p, dst, false, G->stream);
+    HIPCALL(hipGetLastError());
     return RS_OK;
 }
 
@@ -1091,8 +1101,8 @@ int rs_set_field(rs_grid *G, int level, int field, const double *src)
     if (level < 0 || level >= G->nlev) return fail(RS_EINVAL, "level out of range");
     double *p = field_ptr(G, level, field);
     if (!p) return fail(RS_EINVAL, "unknown field %d", field);
-    HIPCALL(hipMemcpyAsync(p, src, sizeof(double) * (size_t)G->lev[level].geo.N,
-                           hipMemcpyDeviceToDevice, G->stream));
+    launch_relayout(G->lev[level].geo, src, p, true, G->stream);
+    HIPCALL(hipGetLastError());
     return RS_OK;
 }
 
@@ -1167,9 +1177,8 @@ int rs_bdf_step_static(const rs_grid_desc *d, const rs_constitutive *c, const do
     }
     char msg[sizeof g_err];
     memcpy(msg, g_err, sizeof msg);
-    const size_t bytes = sizeof(double) * (size_t)G.lev[0].geo.N;
-    HIPCALL(hipMemcpyAsync(psi_out, code == RS_OK ? G.psi_n : G.lev[0].psi, bytes,
-                           hipMemcpyDeviceToDevice, s));
+    launch_relayout(G.lev[0].geo, code == RS_OK ? G.psi_n : G.lev[0].psi, psi_out, false, s);
+    HIPCALL(hipGetLastError());
     HIPCALL(hipStreamSynchronize(s));
     if (code != RS_OK) memcpy(g_err, msg, sizeof msg);
     return code;

@@ -25,7 +25,7 @@ __device__ __forceinline__ void ngs_cell32(const Geo &g, const Law32 &L, float a
                                            const float *rhs, const float *pb, float *dl, int i,
                                            int j, int k, int colour)
 {
-    const long long idx = i + (long long)j * g.stride[1] + (long long)k * g.stride[2];
+    const long long idx = lin(g, i, j, k);
     const Stencil<DIM> st = stencil<DIM, XPAD>(g, i, j, k, idx);
     const float Ki = K[idx];
     const float d0 = dl[idx];

@@ -190,11 +190,6 @@ __device__ __forceinline__ Step slot_step(const ESlot &S, const EDyn &D)
     return st;
 }
 
-__device__ __forceinline__ long long lin(const Geo &g, int i, int j, int k)
-{
-    return i + (long long)j * g.stride[1] + (long long)k * g.stride[2];
-}
-
 // ---------------------------------------------------------------------------
 // Step set-up (slots in BEGIN)
 // ---------------------------------------------------------------------------

@@ -74,6 +74,26 @@ inline ColourMap colour_map(const Geo &g)
     return m;
 }
 
+// Memory position of node i within its row (see Geo::xs): i itself, or with
+// the row split by parity (i >> 1) + (i & 1) xh.  Defined for i = -1 and
+// i = n0 too (a row's neighbouring value, or the padding around an array).
+__host__ __device__ __forceinline__ long long xpos(const Geo &g, int i)
+{
+    return (long long)((i >> g.xs) + (i & 1) * g.xh);
+}
+
+// Memory index of node (i, j, k) of a level.
+__host__ __device__ __forceinline__ long long lin(const Geo &g, int i, int j, int k)
+{
+    return xpos(g, i) + (long long)j * g.stride[1] + (long long)k * g.stride[2];
+}
+
+// Index of the axis-0 neighbour i + side of node i stored at idx.
+__device__ __forceinline__ long long xnb(const Geo &g, int i, long long idx, int side)
+{
+    return idx - xpos(g, i) + xpos(g, i + side);
+}
+
 // Visit the neighbours of node (i, j, k) along the first DIM axes in the
 // order axis 0 low/high, axis 1 low/high, axis 2 low/high; fn(jdx, coef, axis,
 // side) with coef = 1/(2 w h^2).
@@ -85,8 +105,8 @@ __device__ __forceinline__ void for_nb(const Geo &g, int i, int j, int k, long l
         const int cl = (l == 0) ? i : (l == 1 ? j : k);
         const double cf = ((cl == 0 || cl == g.n[l] - 1) ? 1.0 : 0.5) * g.ih2[l];
         const long long s = g.stride[l];
-        if (cl > 0) fn(idx - s, cf, l, -1);
-        if (cl < g.n[l] - 1) fn(idx + s, cf, l, +1);
+        if (cl > 0) fn(l == 0 ? xnb(g, i, idx, -1) : idx - s, cf, l, -1);
+        if (cl < g.n[l] - 1) fn(l == 0 ? xnb(g, i, idx, 1) : idx + s, cf, l, +1);
     }
 }
 
@@ -100,8 +120,8 @@ __device__ __forceinline__ void for_each_nb(const Geo &g, const int c[3], long l
         if (l >= g.dim) break;
         double iw = (c[l] == 0 || c[l] == g.n[l] - 1) ? 2.0 : 1.0;
         double cf = 0.5 * iw * g.ih2[l];
-        if (c[l] > 0) fn(idx - g.stride[l], cf, l, -1);
-        if (c[l] < g.n[l] - 1) fn(idx + g.stride[l], cf, l, +1);
+        if (c[l] > 0) fn(l == 0 ? xnb(g, c[0], idx, -1) : idx - g.stride[l], cf, l, -1);
+        if (c[l] < g.n[l] - 1) fn(l == 0 ? xnb(g, c[0], idx, 1) : idx + g.stride[l], cf, l, +1);
     }
 }
 
@@ -110,9 +130,10 @@ __device__ __forceinline__ void for_each_nb(const Geo &g, const int c[3], long l
 // itself as index and a zero coefficient, so every load of a stencil can be
 // issued before any arithmetic (no branch per neighbour) and the zero terms
 // leave the sums unchanged.  XPAD (arrays with finite padding around them, as
-// in a grid workspace): the axis-0 neighbours are always idx -/+ 1 (the
-// neighbouring row's end node, or the padding, when outside the domain, still
-// with a zero coefficient), so the three loads of a row merge into wide loads.
+// in a grid workspace): the axis-0 neighbours are always the positions of
+// i -/+ 1 (another value of the row, the neighbouring row's first value, or
+// the padding, when outside the domain, still with a zero coefficient), so the
+// loads of a row need no branch.
 template <int DIM>
 struct Stencil {
     long long jn[2 * DIM];
@@ -127,12 +148,13 @@ __device__ __forceinline__ Stencil<DIM> stencil(const Geo &g, int i, int j, int 
     for (int l = 0; l < DIM; ++l) {
         const int cl = (l == 0) ? i : (l == 1 ? j : k);
         const double cf = ((cl == 0 || cl == g.n[l] - 1) ? 1.0 : 0.5) * g.ih2[l];
-        const long long st = l == 0 ? 1 : g.stride[l];   // axis 0 is contiguous
         const bool lo = cl > 0, hi = cl < g.n[l] - 1;
         const bool xp = XPAD && l == 0;
-        s.jn[2 * l] = (lo || xp) ? idx - st : idx;
+        const long long dn = l == 0 ? xnb(g, i, idx, -1) : idx - g.stride[l];
+        const long long up = l == 0 ? xnb(g, i, idx, 1) : idx + g.stride[l];
+        s.jn[2 * l] = (lo || xp) ? dn : idx;
         s.cf[2 * l] = lo ? cf : 0.0;
-        s.jn[2 * l + 1] = (hi || xp) ? idx + st : idx;
+        s.jn[2 * l + 1] = (hi || xp) ? up : idx;
         s.cf[2 * l + 1] = hi ? cf : 0.0;
     }
     return s;
@@ -141,6 +163,7 @@ __device__ __forceinline__ Stencil<DIM> stencil(const Geo &g, int i, int j, int 
 struct NodeMap {
     unsigned n0, n1;
     FastDiv d0, d1;
+    int xh;          // Geo::xh (0: lexicographic rows)
 };
 
 inline NodeMap node_map(const Geo &g)
@@ -150,15 +173,18 @@ inline NodeMap node_map(const Geo &g)
     m.n1 = (unsigned)g.n[1];
     m.d0 = make_fastdiv(m.n0);
     m.d1 = make_fastdiv(m.n1);
+    m.xh = g.xh;
     return m;
 }
 
-// (i, j, k) of node t of a level (t < 2^31).
+// (i, j, k) of the node stored at index t of a level (t < 2^31): threads that
+// walk t walk memory in order, whatever the row layout.
 __device__ __forceinline__ void node_ijk(const NodeMap &nm, unsigned long long t, int &i, int &j,
                                          int &k)
 {
     const unsigned row = udiv((unsigned)t, nm.d0);
-    i = (int)(t - (unsigned long long)row * nm.n0);
+    const int p = (int)(t - (unsigned long long)row * nm.n0);
+    i = nm.xh == 0 ? p : (p < nm.xh ? 2 * p : 2 * (p - nm.xh) + 1);
     k = (int)udiv(row, nm.d1);
     j = (int)row - k * (int)nm.n1;
 }

@@ -29,6 +29,22 @@ __global__ void k_fill_u64(unsigned long long *p, int n, unsigned long long v)
     if (t < n) p[t] = v;
 }
 
+// Reorder an array of one level between the lexicographic order of the C ABI
+// and the level's row layout (Geo::xs): to_level: dst[layout index of node t]
+// = src[t], t the lexicographic index; else dst[t] = src[layout index].
+template <typename T>
+__global__ __launch_bounds__(256) void k_relayout(Geo g, const T *src, T *dst, int to_level,
+                                                  FastDiv d0)
+{
+    const unsigned long long t = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (unsigned long long)g.N) return;
+    const unsigned row = udiv((unsigned)t, d0);
+    const int i = (int)(t - (unsigned long long)row * (unsigned)g.n[0]);
+    const long long m = (long long)row * g.n[0] + xpos(g, i);
+    if (to_level) dst[m] = src[t];
+    else dst[t] = src[m];
+}
+
 // ---------------------------------------------------------------------------
 // Step setup (eq. fully-bdf1; BDF2 reading; eq. Nh-def for g)
 // ---------------------------------------------------------------------------
@@ -41,7 +57,7 @@ __global__ __launch_bounds__(256) void k_setup_kstar(Geo g, Law L, Step st, cons
     int j = blockIdx.y * kBY + threadIdx.y;
     int k = blockIdx.z;
     if (i >= g.n[0] || j >= g.n[1]) return;
-    long long idx = i + (long long)j * g.stride[1] + (long long)k * g.stride[2];
+    long long idx = lin(g, i, j, k);
     double p0;
     K[idx] = kstar_at(g, L, st, psi_n, psi_nm1, Ks ? Ks[idx] : L.Ks, i, j, k, idx, &p0);
     psi[idx] = p0;
@@ -55,7 +71,7 @@ __global__ __launch_bounds__(256) void k_setup_g(Geo g, Law L, Step st, const do
     int j = blockIdx.y * kBY + threadIdx.y;
     int k = blockIdx.z;
     if (i >= g.n[0] || j >= g.n[1]) return;
-    long long idx = i + (long long)j * g.stride[1] + (long long)k * g.stride[2];
+    long long idx = lin(g, i, j, k);
     gv[idx] = g_at(g, L, st, psi_n, psi_nm1, K, i, j, k, idx);
 }
 
@@ -65,9 +81,7 @@ __global__ __launch_bounds__(256) void k_inject(Geo gc, Geo gf, const double *Kf
     int j = blockIdx.y * kBY + threadIdx.y;
     int k = blockIdx.z;
     if (i >= gc.n[0] || j >= gc.n[1]) return;
-    long long I = i + (long long)j * gc.stride[1] + (long long)k * gc.stride[2];
-    long long F = 2LL * i + 2LL * j * gf.stride[1] + 2LL * k * gf.stride[2];
-    Kc[I] = Kf[F];
+    Kc[lin(gc, i, j, k)] = Kf[lin(gf, 2 * i, 2 * j, 2 * k)];
 }
 
 // Coarse K* as the full-weighting average of the finer level's K* (the
@@ -93,7 +107,7 @@ __global__ __launch_bounds__(256) void k_lambda_u(Geo g, const double *K, unsign
     int k = blockIdx.z;
     double v = 0.0;
     if (i < g.n[0] && j < g.n[1] && ((i + j + k) & 1) == 0 && !dirichlet_at(g, i, j, k, nullptr)) {
-        long long idx = i + (long long)j * g.stride[1] + (long long)k * g.stride[2];
+        long long idx = lin(g, i, j, k);
         int c[3] = {i, j, k};
         double Ki = K[idx];
         for_each_nb(g, c, idx, [&](long long jn, double cf, int l, int side) {
@@ -163,7 +177,7 @@ __device__ __forceinline__ void ngs_cell(const Geo &g, const Law &L, double a, c
                                          double lambdaU, const double *K, const double *gv,
                                          double *psi, int i, int j, int k, int colour)
 {
-    const long long idx = i + (long long)j * g.stride[1] + (long long)k * g.stride[2];
+    const long long idx = lin(g, i, j, k);
     const Stencil<DIM> st = stencil<DIM, true>(g, i, j, k, idx);   // workspace arrays are padded
     const double Ki = K[idx];
     const double x0 = psi[idx];
@@ -236,7 +250,6 @@ __global__ __launch_bounds__(512) void k_sweep_fused(Geo g, Law L, Step st, cons
     if (in_y && lx == 0 && X0 > 0) { ring = true; ring_col = X0 - 1; }
     if (in_y && lx == IX + 1 && X1 < n0) { ring = true; ring_col = X1; }
     if (in_x && ((ly == 0 && Y0 > 0) || (ly == IY + 1 && Y1 < n1))) ring = true;
-    const long long s1 = g.stride[1], s2 = g.stride[2];
     const int xo = ly * W - (X0 - 2);   // LDS offset of (x, y) is xo + x
     __syncthreads();
 
@@ -247,7 +260,7 @@ __global__ __launch_bounds__(512) void k_sweep_fused(Geo g, Law L, Step st, cons
         const bool do_red = z < n2 && c < n0 &&
                             (interior || (ring && z >= Z0 && z < Z1 && (ring_col < 0 || ring_col == c)));
         if (do_red) {
-            const long long idx = c + y * s1 + z * s2;
+            const long long idx = lin(g, c, y, z);
             const double x0 = pin[idx];
             rz = x0;
             if (!dirichlet_at(g, c, y, z, nullptr)) {
@@ -268,7 +281,7 @@ __global__ __launch_bounds__(512) void k_sweep_fused(Geo g, Law L, Step st, cons
         }
         const int zb = z - 1;
         if (interior && zb >= Z0 && zb < Z1 && c < n0) {
-            const long long idx = c + y * s1 + zb * s2;
+            const long long idx = lin(g, c, y, zb);
             const double x0 = pin[idx];
             double v = x0;
             if (!dirichlet_at(g, c, y, zb, nullptr)) {
@@ -367,6 +380,7 @@ __device__ __forceinline__ NodeMap tail_nm(const TailLevel &T)
     m.n1 = T.nn1;
     m.d0 = FastDiv{T.d0_m, T.d0_s};
     m.d1 = FastDiv{T.d1_m, T.d1_s};
+    m.xh = T.g.xh;
     return m;
 }
 
@@ -483,10 +497,11 @@ __global__ __launch_bounds__(512) void k_vcycle_tail(const TailArgs *A, int top,
 // ---------------------------------------------------------------------------
 
 // Two neighbouring nodes of a row per thread (i = 2 ih, 2 ih + 1): both
-// stencils are loaded as pairs of adjacent values, so a row window of four
-// values and every off-row pair become wide loads, and the two theta chains
-// overlap.  Each node's arithmetic is that of apply_N_t with
-// XPAD.  Slots are those of the colour packing (H = (n0 + 1) / 2 per row).
+// stencils are loaded together (the row's nodes i - 1 .. i + 2 and the two
+// nodes' neighbours in the off-row directions), so the two theta chains
+// overlap.  Each node's arithmetic is that of apply_N_t with XPAD.  Slots are
+// those of the colour packing (H = (n0 + 1) / 2 per row): consecutive threads
+// take consecutive even and odd positions of a parity-split row.
 template <int MODEL, bool SINK, int DIM>
 __global__ __launch_bounds__(256) void k_residual_pair(Geo g, Law L, Step st, const double *beta,
                                                        const double *K, const double *gv,
@@ -507,14 +522,19 @@ __global__ __launch_bounds__(256) void k_residual_pair(Geo g, Law L, Step st, co
         } else if (DIM == 2) {
             j = (int)row;
         }
-        const long long idx0 = i0 + (long long)j * g.stride[1] + (long long)k * g.stride[2];
-        // row window psi/K[idx0 - 1 .. idx0 + 2] (padding keeps it in bounds)
+        const long long base = (long long)j * g.stride[1] + (long long)k * g.stride[2];
+        // the row's nodes i0 - 1 .. i0 + 2 (padding keeps them in bounds); with
+        // parity-split rows i0 and i0 + 2 are adjacent in the even half and
+        // i0 - 1, i0 + 1 in the odd half
+        long long xi[4];
         double P[4], KK[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            P[q] = psi[idx0 - 1 + q];
-            KK[q] = K[idx0 - 1 + q];
+            xi[q] = base + xpos(g, i0 - 1 + q);
+            P[q] = psi[xi[q]];
+            KK[q] = K[xi[q]];
         }
+        const long long idx0 = xi[1], idx1 = xi[2];
         // off-row neighbours as pairs: base (or the node itself when outside)
         constexpr int NO = 2 * (DIM - 1);
         double Po[NO > 0 ? NO : 1][2], Ko[NO > 0 ? NO : 1][2], cfo[NO > 0 ? NO : 1];
@@ -524,14 +544,14 @@ __global__ __launch_bounds__(256) void k_residual_pair(Geo g, Law L, Step st, co
             const int cl = l == 1 ? j : k;
             const bool up = q & 1;
             const bool ok = up ? cl < g.n[l] - 1 : cl > 0;
-            const long long b = ok ? idx0 + (up ? g.stride[l] : -(long long)g.stride[l]) : idx0;
-            Po[q][0] = psi[b];
-            Po[q][1] = psi[b + 1];
-            Ko[q][0] = K[b];
-            Ko[q][1] = K[b + 1];
+            const long long b = ok ? (up ? g.stride[l] : -(long long)g.stride[l]) : 0;
+            Po[q][0] = psi[idx0 + b];
+            Po[q][1] = psi[idx1 + b];
+            Ko[q][0] = K[idx0 + b];
+            Ko[q][1] = K[idx1 + b];
             cfo[q] = ok ? ((cl == 0 || cl == g.n[l] - 1) ? 1.0 : 0.5) * g.ih2[l] : 0.0;
         }
-        const double g0 = gv[idx0], g1 = gv[idx0 + 1];
+        const double g0 = gv[idx0], g1 = gv[idx1];
         double bz = 0.0;   // root density of the row (2-D, 3-D)
         if (SINK && DIM > 1) bz = beta[DIM == 2 ? j : k];
         double r[2] = {0.0, 0.0};
@@ -541,7 +561,7 @@ __global__ __launch_bounds__(256) void k_residual_pair(Geo g, Law L, Step st, co
             if (i >= g.n[0] || dirichlet_at(g, i, j, k, nullptr)) continue;
             const double x = P[1 + a], Ki = KK[1 + a];
             double s;
-            if constexpr (MODEL == kMulti) s = st.a * theta_only(L.soils[g.soil[idx0 + a]], x);
+            if constexpr (MODEL == kMulti) s = st.a * theta_only(L.soils[g.soil[a ? idx1 : idx0]], x);
             else s = st.a * theta_only_t<MODEL>(L, x);
             if (SINK) {
                 // in 1-D the row is the vertical axis: each node has its own root density
@@ -566,14 +586,15 @@ __global__ __launch_bounds__(256) void k_residual_pair(Geo g, Law L, Step st, co
         }
         if (d) {
             d[idx0] = r[0];
-            if (i0 + 1 < g.n[0]) d[idx0 + 1] = r[1];
+            if (i0 + 1 < g.n[0]) d[idx1] = r[1];
         }
         if (mp.rhs) {
             for (int a = 0; a < 2; ++a) {
                 if (i0 + a >= g.n[0]) break;
-                mp.rhs[idx0 + a] = (float)r[a];
-                mp.pb[idx0 + a] = (float)P[1 + a];
-                mp.dl[idx0 + a] = 0.0f;
+                const long long ia = a ? idx1 : idx0;
+                mp.rhs[ia] = (float)r[a];
+                mp.pb[ia] = (float)P[1 + a];
+                mp.dl[ia] = 0.0f;
             }
         }
         const double a0 = fabs(r[0]), a1 = fabs(r[1]);
@@ -701,6 +722,24 @@ void launch_root_beta(int nlev, const int *nvert, const double *hvert, double *c
     a.Tp = Tp;
     a.rl = root_len;
     hipLaunchKernelGGL(k_root_beta, dim3(1), dim3(256), 0, s, a);
+}
+
+template <typename T>
+static void relayout_t(const Geo &g, const T *src, T *dst, bool to_level, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_relayout<T>, dim3((unsigned)((g.N + 255) / 256)), dim3(256), 0, s, g, src,
+                       dst, to_level ? 1 : 0, make_fastdiv((unsigned)g.n[0]));
+}
+
+void launch_relayout(const Geo &g, const double *src, double *dst, bool to_level, hipStream_t s)
+{
+    relayout_t<double>(g, src, dst, to_level, s);
+}
+
+void launch_relayout_u8(const Geo &g, const unsigned char *src, unsigned char *dst, bool to_level,
+                        hipStream_t s)
+{
+    relayout_t<unsigned char>(g, src, dst, to_level, s);
 }
 
 void launch_fill_u64(unsigned long long *p, int n, unsigned long long v, hipStream_t s)

@@ -27,7 +27,13 @@ struct Geo {
     int n[3];        // nodes per axis (1 beyond dim)
     int dim;
     int vert;        // vertical axis = dim - 1
-    int stride[3];   // 1, n0, n0*n1
+    int stride[3];   // 1, n0, n0*n1 (rows of n0 values)
+    // Order of the n0 values of a row in memory: node i at position
+    // (i >> xs) + (i & 1) xh.  xs = xh = 0: lexicographic (axis 0 fastest);
+    // xs = 1, xh = (n0 + 1) / 2: the row split by parity, even nodes first,
+    // then odd ones, so that one colour of the red-black ordering fills whole
+    // cache lines.
+    int xs, xh;
     long long N;     // total nodes
     double h[3];
     double ih2[3];   // 1 / h^2
@@ -100,6 +106,10 @@ void launch_vcycle_tail(const TailArgs *args_dev, int top, int last, const Law &
                         hipStream_t s);
 constexpr size_t kTailLds = 56 * 1024;   // LDS for the deepest levels of that cycle
 void launch_fill_u64(unsigned long long *p, int n, unsigned long long v, hipStream_t s);
+// Lexicographic (C ABI) order <-> the level's row layout; src and dst must not overlap.
+void launch_relayout(const Geo &g, const double *src, double *dst, bool to_level, hipStream_t s);
+void launch_relayout_u8(const Geo &g, const unsigned char *src, unsigned char *dst, bool to_level,
+                        hipStream_t s);
 void launch_setup_kstar(const Geo &g, const Law &law, const Step &st, const double *psi_n,
                         const double *psi_nm1, const double *Ks_field, double *K, double *psi,
                         hipStream_t s);

@@ -8,37 +8,50 @@
 
 namespace rs {
 
+// Fine offsets of the three full-weighting taps of fine node F along every
+// axis (mirrored at both ends; axis 0 by row position).
+__device__ __forceinline__ void fw_offsets(const Geo &gf, const int F[3], long long off[3][3])
+{
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        const int n = gf.n[l];
+        const int m = F[l] == 0 ? 1 : F[l] - 1;
+        const int p = F[l] == n - 1 ? n - 2 : F[l] + 1;
+        if (l == 0) {
+            off[0][0] = xpos(gf, m);
+            off[0][1] = xpos(gf, F[0]);
+            off[0][2] = xpos(gf, p);
+        } else {
+            const long long st = gf.stride[l];
+            off[l][0] = (long long)m * st;
+            off[l][1] = (long long)F[l] * st;
+            off[l][2] = (long long)p * st;
+        }
+    }
+}
+
 // psibar_H = FW(psi_h), d_H = FW(d_h) stored in g_H (Dirichlet coarse nodes:
 // injection of psi, zero defect).  FW: tensor (1/4, 1/2, 1/4) around fine node
 // 2I, missing neighbours mirrored at the domain boundary.  The taps are summed
 // axis 2 outermost, axis 0 innermost, with weight (w0 w1) w2.  XPAD (arrays
 // with finite padding around them, as in a grid workspace): the three axis-0
-// taps are loaded as the window 2I0-1 .. 2I0+1 and mirrored in registers, so
-// their loads merge into wide ones; the sums are the same.
+// taps are loaded as the row's nodes 2I0-1 .. 2I0+1 without a bound check and
+// mirrored in registers; the sums are the same.
 template <int DIM, typename T, bool XPAD = false>
 __device__ __forceinline__ void restrict_at(const Geo &gc, const Geo &gf, const T *psi_f,
                                             const T *d_f, T *psibar_c, T *g_c, int I0, int I1,
                                             int I2)
 {
-    const long long I = I0 + (long long)I1 * gc.stride[1] + (long long)I2 * gc.stride[2];
+    const long long I = lin(gc, I0, I1, I2);
     const int F[3] = {2 * I0, 2 * I1, 2 * I2};
     if (dirichlet_at(gc, I0, I1, I2, nullptr)) {
-        psibar_c[I] = psi_f[F[0] + (long long)F[1] * gf.stride[1] + (long long)F[2] * gf.stride[2]];
+        psibar_c[I] = psi_f[lin(gf, F[0], F[1], F[2])];
         g_c[I] = T(0);
         return;
     }
-    // fine offsets of the three taps per axis (mirrored at both ends)
     long long off[3][3];
-#pragma unroll
-    for (int l = 0; l < 3; ++l) {
-        const int n = gf.n[l];
-        const long long st = gf.stride[l];
-        const int m = F[l] == 0 ? 1 : F[l] - 1;
-        const int p = F[l] == n - 1 ? n - 2 : F[l] + 1;
-        off[l][0] = (long long)m * st;
-        off[l][1] = (long long)F[l] * st;
-        off[l][2] = (long long)p * st;
-    }
+    fw_offsets(gf, F, off);
+    const long long x3[3] = {xpos(gf, F[0] - 1), xpos(gf, F[0]), xpos(gf, F[0] + 1)};
     const T wt[3] = {T(0.25), T(0.5), T(0.25)};
     T sp = T(0), sd = T(0);
 #pragma unroll
@@ -50,9 +63,8 @@ __device__ __forceinline__ void restrict_at(const Geo &gc, const Geo &gf, const 
             const T w1 = DIM > 1 ? wt[o1] : T(1);
             const long long b1 = b2 + (DIM > 1 ? off[1][o1] : 0);
             if constexpr (XPAD) {
-                const long long fc = b1 + F[0];
-                const T pl = psi_f[fc - 1], pc = psi_f[fc], pr = psi_f[fc + 1];
-                const T dl = d_f[fc - 1], dc = d_f[fc], dr = d_f[fc + 1];
+                const T pl = psi_f[b1 + x3[0]], pc = psi_f[b1 + x3[1]], pr = psi_f[b1 + x3[2]];
+                const T dl = d_f[b1 + x3[0]], dc = d_f[b1 + x3[1]], dr = d_f[b1 + x3[2]];
                 const bool first = F[0] == 0, last = F[0] == gf.n[0] - 1;
                 const T P3[3] = {first ? pr : pl, pc, last ? pl : pr};
                 const T D3[3] = {first ? dr : dl, dc, last ? dl : dr};
@@ -85,16 +97,7 @@ __device__ __forceinline__ T fw_value(const Geo &gf, const T *v, int I0, int I1,
 {
     const int F[3] = {2 * I0, 2 * I1, 2 * I2};
     long long off[3][3];
-#pragma unroll
-    for (int l = 0; l < 3; ++l) {
-        const int n = gf.n[l];
-        const long long st = gf.stride[l];
-        const int m = F[l] == 0 ? 1 : F[l] - 1;
-        const int p = F[l] == n - 1 ? n - 2 : F[l] + 1;
-        off[l][0] = (long long)m * st;
-        off[l][1] = (long long)F[l] * st;
-        off[l][2] = (long long)p * st;
-    }
+    fw_offsets(gf, F, off);
     const T wt[3] = {T(0.25), T(0.5), T(0.25)};
     T s = T(0);
 #pragma unroll
@@ -127,8 +130,8 @@ __device__ __forceinline__ void prolong_at(const Geo &gf, const Geo &gc, const T
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
         const bool odd = c[l] & 1;
-        off[l][0] = (long long)(c[l] >> 1) * gc.stride[l];
-        off[l][1] = (long long)((c[l] + 1) >> 1) * gc.stride[l];
+        off[l][0] = l == 0 ? xpos(gc, c[0] >> 1) : (long long)(c[l] >> 1) * gc.stride[l];
+        off[l][1] = l == 0 ? xpos(gc, (c[0] + 1) >> 1) : (long long)((c[l] + 1) >> 1) * gc.stride[l];
         wt[l][0] = odd ? T(0.5) : T(1);
         wt[l][1] = odd ? T(0.5) : T(0);
     }
@@ -148,8 +151,7 @@ __device__ __forceinline__ void prolong_at(const Geo &gf, const Geo &gc, const T
             }
         }
     }
-    const long long idx = i + (long long)j * gf.stride[1] + (long long)k * gf.stride[2];
-    psi_f[idx] += e;
+    psi_f[lin(gf, i, j, k)] += e;
 }
 
 // One coarse node per thread (restriction) / one fine node per thread
@@ -161,10 +163,8 @@ __global__ __launch_bounds__(256) void k_restrict(Geo gc, Geo gf, const T *psi_f
     const unsigned long long t =
         (unsigned long long)xcd_block(gridDim.x / 8u) * blockDim.x + threadIdx.x;
     if (t >= (unsigned long long)gc.N) return;
-    const unsigned row = udiv((unsigned)t, nm.d0);
-    const int i = (int)(t - (unsigned long long)row * nm.n0);
-    const int k = (int)udiv(row, nm.d1);
-    const int j = (int)row - k * (int)nm.n1;
+    int i, j, k;
+    node_ijk(nm, t, i, j, k);
     restrict_at<DIM, T, true>(gc, gf, psi_f, d_f, psibar_c, g_c, i, j, k);   // workspace arrays are padded
 }
 
@@ -173,8 +173,8 @@ __global__ __launch_bounds__(256) void k_restrict(Geo gc, Geo gf, const T *psi_f
 // (those inside the grid), each with the sum of prolong_at in the same order.
 // FULL: interpolate psi_H itself and assign it (the FMG interpolation;
 // psibar_c unused).  The arrays are padded workspace arrays: the two axis-0
-// corners and the two axis-0 fine nodes are loaded as pairs without a bound
-// check (a value past the end of a row has weight 0 or is not stored).
+// corners and the two axis-0 fine nodes are loaded without a bound check (a
+// value past the end of a row has weight 0 or is not stored).
 template <int DIM, typename T, bool FULL = false>
 __global__ __launch_bounds__(256) void k_prolong(Geo gf, Geo gc, const T *psi_c, const T *psibar_c,
                                                  T *psi_f, NodeMap nmc)
@@ -182,10 +182,10 @@ __global__ __launch_bounds__(256) void k_prolong(Geo gf, Geo gc, const T *psi_c,
     const unsigned long long t =
         (unsigned long long)xcd_block(gridDim.x / 8u) * blockDim.x + threadIdx.x;
     if (t >= (unsigned long long)gc.N) return;
-    const unsigned row = udiv((unsigned)t, nmc.d0);
-    int Ic[3] = {(int)(t - (unsigned long long)row * nmc.n0), 0, 0};
-    Ic[2] = (int)udiv(row, nmc.d1);
-    Ic[1] = (int)row - Ic[2] * (int)nmc.n1;
+    int Ic[3];
+    node_ijk(nmc, t, Ic[0], Ic[1], Ic[2]);
+    const long long cx[2] = {xpos(gc, Ic[0]), xpos(gc, Ic[0] + 1)};
+    const long long fx[2] = {xpos(gf, 2 * Ic[0]), xpos(gf, 2 * Ic[0] + 1)};
     // corner offsets along axes 1 and 2 (the upper corner clamped at the last
     // coarse node: its weight is 0 there or the fine node lies outside the
     // grid); along axis 0 the pair I0, I0 + 1 is loaded as it is
@@ -204,10 +204,10 @@ __global__ __launch_bounds__(256) void k_prolong(Geo gf, Geo gc, const T *psi_c,
 #pragma unroll
         for (int q1 = 0; q1 < N1; ++q1)
         {
-            const long long J = (DIM > 2 ? co[2][q2] : 0) + (DIM > 1 ? co[1][q1] : 0) + Ic[0];
-            const T c0 = psi_c[J], c1 = psi_c[J + 1];
-            E[q2][q1][0] = FULL ? c0 : c0 - psibar_c[J];
-            E[q2][q1][1] = FULL ? c1 : c1 - psibar_c[J + 1];
+            const long long J = (DIM > 2 ? co[2][q2] : 0) + (DIM > 1 ? co[1][q1] : 0);
+            const T c0 = psi_c[J + cx[0]], c1 = psi_c[J + cx[1]];
+            E[q2][q1][0] = FULL ? c0 : c0 - psibar_c[J + cx[0]];
+            E[q2][q1][1] = FULL ? c1 : c1 - psibar_c[J + cx[1]];
         }
 #pragma unroll
     for (int a2 = 0; a2 < N2; ++a2) {
@@ -217,11 +217,11 @@ __global__ __launch_bounds__(256) void k_prolong(Geo gf, Geo gc, const T *psi_c,
         for (int a1 = 0; a1 < N1; ++a1) {
             const int f1 = 2 * Ic[1] + a1;
             if (f1 >= gf.n[1]) continue;
-            const long long fr = 2LL * Ic[0] + (long long)f1 * gf.stride[1] + (long long)f2 * gf.stride[2];
+            const long long fr = (long long)f1 * gf.stride[1] + (long long)f2 * gf.stride[2];
             T old[2] = {T(0), T(0)};
             if (!FULL) {
-                old[0] = psi_f[fr];
-                old[1] = psi_f[fr + 1];
+                old[0] = psi_f[fr + fx[0]];
+                old[1] = psi_f[fr + fx[1]];
             }
 #pragma unroll
             for (int a0 = 0; a0 < 2; ++a0) {
@@ -242,7 +242,7 @@ __global__ __launch_bounds__(256) void k_prolong(Geo gf, Geo gc, const T *psi_c,
                         for (int q0 = 0; q0 < 2; ++q0)
                             e += w0[q0] * (DIM > 1 ? w1[q1] : T(1)) * (DIM > 2 ? w2[q2] : T(1)) *
                                  E[q2][q1][q0];
-                psi_f[fr + a0] = FULL ? e : old[a0] + e;
+                psi_f[fr + fx[a0]] = FULL ? e : old[a0] + e;
             }
         }
     }
@@ -287,9 +287,7 @@ __global__ __launch_bounds__(256) void k_inject_t(Geo gc, Geo gf, const T *vf, T
     int j = blockIdx.y * kBY + threadIdx.y;
     int k = blockIdx.z;
     if (i >= gc.n[0] || j >= gc.n[1]) return;
-    long long I = i + (long long)j * gc.stride[1] + (long long)k * gc.stride[2];
-    long long F = 2LL * i + 2LL * j * gf.stride[1] + 2LL * k * gf.stride[2];
-    vc[I] = vf[F];
+    vc[lin(gc, i, j, k)] = vf[lin(gf, 2 * i, 2 * j, 2 * k)];
 }
 
 }  // namespace rs
