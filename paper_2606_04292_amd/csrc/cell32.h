@@ -18,24 +18,43 @@ __device__ __forceinline__ int vert_index(int i, int j, int k)
 
 // New delta at unknown (i, j, k): f = rhs + sum_j m_ij delta_j + kappa delta_i,
 // c = xi + kappa + m_ii, then the scalar correction solve.  XPAD: the arrays
-// have finite padding around them (see stencil()).
-template <int MODEL, bool SINK, int DIM, bool XPAD = false>
+// have finite padding around them (see stencil()).  SPLIT: the level has
+// parity-split rows and padded arrays; the axis-0 neighbours are loaded as
+// one pair from xl (idx and xl < 0: computed here).
+template <int MODEL, bool SINK, int DIM, bool XPAD = false, bool SPLIT = false>
 __device__ __forceinline__ void ngs_cell32(const Geo &g, const Law32 &L, float a,
                                            const double *beta, float lambdaU, const float *K,
                                            const float *rhs, const float *pb, float *dl, int i,
-                                           int j, int k, int colour)
+                                           int j, int k, int colour, long long idx = -1,
+                                           long long xl = -1)
 {
-    const long long idx = lin(g, i, j, k);
-    const Stencil<DIM> st = stencil<DIM, XPAD>(g, i, j, k, idx);
+    if (idx < 0) idx = lin(g, i, j, k);
+    Stencil<DIM> st;
+    float Kn[2 * DIM], dn[2 * DIM];
+    if constexpr (SPLIT) {
+        if (xl < 0) xl = xnb(g, i, idx, -1);
+        st = stencil_split<DIM>(g, i, j, k, idx, xl);
+        const float2_u kx = load_pair(K + xl), dx = load_pair(dl + xl);
+        Kn[0] = kx.x;
+        Kn[1] = kx.y;
+        dn[0] = dx.x;
+        dn[1] = dx.y;
+#pragma unroll
+        for (int q = 2; q < 2 * DIM; ++q) {
+            Kn[q] = K[st.jn[q]];
+            dn[q] = dl[st.jn[q]];
+        }
+    } else {
+        st = stencil<DIM, XPAD>(g, i, j, k, idx);
+#pragma unroll
+        for (int q = 0; q < 2 * DIM; ++q) {
+            Kn[q] = K[st.jn[q]];
+            dn[q] = dl[st.jn[q]];
+        }
+    }
     const float Ki = K[idx];
     const float d0 = dl[idx];
     float f = rhs[idx];
-    float Kn[2 * DIM], dn[2 * DIM];
-#pragma unroll
-    for (int q = 0; q < 2 * DIM; ++q) {
-        Kn[q] = K[st.jn[q]];
-        dn[q] = dl[st.jn[q]];
-    }
     float mii = 0.0f;
 #pragma unroll
     for (int q = 0; q < 2 * DIM; ++q) {

@@ -160,6 +160,61 @@ __device__ __forceinline__ Stencil<DIM> stencil(const Geo &g, int i, int j, int 
     return s;
 }
 
+// Two adjacent values of an array as one access: 16-byte (8-byte for floats)
+// global loads need only dword alignment, so any pair of neighbouring
+// positions can be loaded together.
+typedef double double2_u __attribute__((ext_vector_type(2), aligned(8)));
+typedef float float2_u __attribute__((ext_vector_type(2), aligned(4)));
+template <typename T> struct PairOf;
+template <> struct PairOf<double> { typedef double2_u type; };
+template <> struct PairOf<float> { typedef float2_u type; };
+
+template <typename T>
+__device__ __forceinline__ typename PairOf<T>::type load_pair(const T *p)
+{
+    return *(const typename PairOf<T>::type *)p;
+}
+
+template <typename T>
+__device__ __forceinline__ void store_pair(T *p, T a, T b)
+{
+    typename PairOf<T>::type v;
+    v.x = a;
+    v.y = b;
+    *(typename PairOf<T>::type *)p = v;
+}
+
+// Stencil of node (i, j, k) stored at idx on a level with parity-split rows
+// (Geo::xs = 1, as in every level of a grid): the axis-0 neighbours i - 1 and
+// i + 1 sit side by side in the other half of the row, at xl and xl + 1
+// (xl = idx - xpos(i) + xpos(i - 1); at the ends of the row one of them is
+// another value of the row, or the next row's first value, with coefficient
+// 0).  Off-row neighbours as in stencil().
+template <int DIM>
+__device__ __forceinline__ Stencil<DIM> stencil_split(const Geo &g, int i, int j, int k,
+                                                      long long idx, long long xl)
+{
+    Stencil<DIM> s;
+    {
+        const double cf = ((i == 0 || i == g.n[0] - 1) ? 1.0 : 0.5) * g.ih2[0];
+        s.jn[0] = xl;
+        s.cf[0] = i > 0 ? cf : 0.0;
+        s.jn[1] = xl + 1;
+        s.cf[1] = i < g.n[0] - 1 ? cf : 0.0;
+    }
+#pragma unroll
+    for (int l = 1; l < DIM; ++l) {
+        const int cl = l == 1 ? j : k;
+        const double cf = ((cl == 0 || cl == g.n[l] - 1) ? 1.0 : 0.5) * g.ih2[l];
+        const bool lo = cl > 0, hi = cl < g.n[l] - 1;
+        s.jn[2 * l] = lo ? idx - g.stride[l] : idx;
+        s.cf[2 * l] = lo ? cf : 0.0;
+        s.jn[2 * l + 1] = hi ? idx + g.stride[l] : idx;
+        s.cf[2 * l + 1] = hi ? cf : 0.0;
+    }
+    return s;
+}
+
 struct NodeMap {
     unsigned n0, n1;
     FastDiv d0, d1;

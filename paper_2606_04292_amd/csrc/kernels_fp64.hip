@@ -172,24 +172,42 @@ __device__ __forceinline__ double ngs_point(const Geo &g, const Law &L, double a
     }
 }
 
+// Update of unknown (i, j, k) stored at idx, its axis-0 neighbours at xl and
+// xl + 1 (a grid's levels have parity-split rows, see stencil_split; the
+// workspace arrays are padded, so both are always loaded, as one pair).
+template <int MODEL, bool SINK, int DIM>
+__device__ __forceinline__ void ngs_cell_at(const Geo &g, const Law &L, double a,
+                                            const double *beta, double lambdaU, const double *K,
+                                            const double *gv, double *psi, int i, int j, int k,
+                                            long long idx, long long xl, int colour)
+{
+    const Stencil<DIM> st = stencil_split<DIM>(g, i, j, k, idx, xl);
+    const double Ki = K[idx];
+    const double x0 = psi[idx];
+    const double f = gv[idx];
+    double Kn[2 * DIM], pn[2 * DIM];
+    const double2_u kx = load_pair(K + xl), px = load_pair(psi + xl);
+    Kn[0] = kx.x;
+    Kn[1] = kx.y;
+    pn[0] = px.x;
+    pn[1] = px.y;
+#pragma unroll
+    for (int q = 2; q < 2 * DIM; ++q) {
+        Kn[q] = K[st.jn[q]];
+        pn[q] = psi[st.jn[q]];
+    }
+    psi[idx] = ngs_point<MODEL, SINK, DIM>(g, L, a, beta, lambdaU, st, Ki, Kn, pn, f, x0, i, j, k,
+                                           idx, colour);
+}
+
 template <int MODEL, bool SINK, int DIM>
 __device__ __forceinline__ void ngs_cell(const Geo &g, const Law &L, double a, const double *beta,
                                          double lambdaU, const double *K, const double *gv,
                                          double *psi, int i, int j, int k, int colour)
 {
     const long long idx = lin(g, i, j, k);
-    const Stencil<DIM> st = stencil<DIM, true>(g, i, j, k, idx);   // workspace arrays are padded
-    const double Ki = K[idx];
-    const double x0 = psi[idx];
-    const double f = gv[idx];
-    double Kn[2 * DIM], pn[2 * DIM];
-#pragma unroll
-    for (int q = 0; q < 2 * DIM; ++q) {
-        Kn[q] = K[st.jn[q]];
-        pn[q] = psi[st.jn[q]];
-    }
-    psi[idx] = ngs_point<MODEL, SINK, DIM>(g, L, a, beta, lambdaU, st, Ki, Kn, pn, f, x0, i, j, k,
-                                           idx, colour);
+    ngs_cell_at<MODEL, SINK, DIM>(g, L, a, beta, lambdaU, K, gv, psi, i, j, k, idx,
+                                  xnb(g, i, idx, -1), colour);
 }
 
 // ---------------------------------------------------------------------------
@@ -326,10 +344,17 @@ __global__ __launch_bounds__(256) void k_sweep(Geo g, Law L, Step st, const doub
     } else if (DIM == 2) {
         j = row;
     }
-    const int i = 2 * (int)ih + (int)((j + k + colour) & 1);
+    const int par = (int)((j + k + colour) & 1);
+    const int i = 2 * (int)ih + par;
     if (i >= g.n[0]) return;
     if (dirichlet_at(g, i, (int)j, (int)k, nullptr)) return;
-    ngs_cell<MODEL, SINK, DIM>(g, L, st.a, beta, lambdaU, K, gv, psi, i, (int)j, (int)k, colour);
+    // parity-split row: node i at ih (+ xh if odd); its left neighbour i - 1
+    // at ih (i odd) or xh + ih - 1 (i even), the right one just after it
+    const long long rb = (long long)j * g.stride[1] + (long long)k * g.stride[2];
+    const long long idx = rb + ih + (par ? g.xh : 0);
+    const long long xl = rb + ih + (par ? 0 : g.xh - 1);
+    ngs_cell_at<MODEL, SINK, DIM>(g, L, st.a, beta, lambdaU, K, gv, psi, i, (int)j, (int)k, idx, xl,
+                                  colour);
 }
 
 // Whole sweeps of a tiny level in one work-group (the coarsest levels, where
@@ -496,12 +521,13 @@ __global__ __launch_bounds__(512) void k_vcycle_tail(const TailArgs *A, int top,
 // Defect d = g - N(psi) and its max-norm (step 2 of the FAS algorithm)
 // ---------------------------------------------------------------------------
 
-// Two neighbouring nodes of a row per thread (i = 2 ih, 2 ih + 1): both
-// stencils are loaded together (the row's nodes i - 1 .. i + 2 and the two
-// nodes' neighbours in the off-row directions), so the two theta chains
-// overlap.  Each node's arithmetic is that of apply_N_t with XPAD.  Slots are
-// those of the colour packing (H = (n0 + 1) / 2 per row): consecutive threads
-// take consecutive even and odd positions of a parity-split row.
+// Two nodes of the same parity per thread, side by side in one half of a
+// parity-split row (positions 2q and 2q + 1 of the half: nodes i and i + 2):
+// their own values, g, and each off-row neighbour direction are one 16-byte
+// load per array, the three axis-0 neighbours (in the other half) a pair and
+// a single load; the two theta chains overlap.  Each node's arithmetic is that
+// of apply_N_t.  Slots: H = (n0 + 1) / 2 per row, the first (H + 1) / 2 for
+// the even half, the rest for the odd half.
 template <int MODEL, bool SINK, int DIM>
 __global__ __launch_bounds__(256) void k_residual_pair(Geo g, Law L, Step st, const double *beta,
                                                        const double *K, const double *gv,
@@ -514,7 +540,13 @@ __global__ __launch_bounds__(256) void k_residual_pair(Geo g, Law L, Step st, co
         (unsigned long long)xcd_block(gridDim.x / 8u) * blockDim.x + threadIdx.x;
     if (t < cm.total) {
         const unsigned row = udiv((unsigned)t, cm.dH);
-        const int i0 = 2 * (int)((unsigned)(t - (unsigned long long)row * cm.H));
+        const int slot = (int)((unsigned)(t - (unsigned long long)row * cm.H));
+        const int H = g.xh, P0 = (H + 1) / 2;
+        const int h = slot < P0 ? 0 : 1;
+        const int q = slot - h * P0;
+        const int half_len = h ? g.n[0] - H : H;
+        const bool has_b = 2 * q + 1 < half_len;
+        const int ia = 4 * q + h;                 // nodes ia and ia + 2
         int j = 0, k = 0;
         if (DIM == 3) {
             k = (int)udiv(row, cm.dN1);
@@ -522,46 +554,40 @@ __global__ __launch_bounds__(256) void k_residual_pair(Geo g, Law L, Step st, co
         } else if (DIM == 2) {
             j = (int)row;
         }
-        const long long base = (long long)j * g.stride[1] + (long long)k * g.stride[2];
-        // the row's nodes i0 - 1 .. i0 + 2 (padding keeps them in bounds); with
-        // parity-split rows i0 and i0 + 2 are adjacent in the even half and
-        // i0 - 1, i0 + 1 in the odd half
-        long long xi[4];
-        double P[4], KK[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            xi[q] = base + xpos(g, i0 - 1 + q);
-            P[q] = psi[xi[q]];
-            KK[q] = K[xi[q]];
-        }
-        const long long idx0 = xi[1], idx1 = xi[2];
-        // off-row neighbours as pairs: base (or the node itself when outside)
+        const long long rb = (long long)j * g.stride[1] + (long long)k * g.stride[2];
+        const long long idx = rb + h * H + 2 * q;          // node ia; ia + 2 at idx + 1
+        const long long xl = rb + (h ? 0 : H - 1) + 2 * q; // nodes ia - 1, ia + 1, ia + 3
+        const double2_u P = load_pair(psi + idx), KK = load_pair(K + idx), G2 = load_pair(gv + idx);
+        const double2_u PX = load_pair(psi + xl), KX = load_pair(K + xl);
+        const double PX2 = psi[xl + 2], KX2 = K[xl + 2];
+        // off-row neighbour pairs (the nodes themselves, coefficient 0, outside)
         constexpr int NO = 2 * (DIM - 1);
-        double Po[NO > 0 ? NO : 1][2], Ko[NO > 0 ? NO : 1][2], cfo[NO > 0 ? NO : 1];
+        double2_u Po[NO > 0 ? NO : 1], Ko[NO > 0 ? NO : 1];
+        double cfo[NO > 0 ? NO : 1];
 #pragma unroll
-        for (int q = 0; q < NO; ++q) {
-            const int l = 1 + q / 2;
+        for (int o = 0; o < NO; ++o) {
+            const int l = 1 + o / 2;
             const int cl = l == 1 ? j : k;
-            const bool up = q & 1;
+            const bool up = o & 1;
             const bool ok = up ? cl < g.n[l] - 1 : cl > 0;
             const long long b = ok ? (up ? g.stride[l] : -(long long)g.stride[l]) : 0;
-            Po[q][0] = psi[idx0 + b];
-            Po[q][1] = psi[idx1 + b];
-            Ko[q][0] = K[idx0 + b];
-            Ko[q][1] = K[idx1 + b];
-            cfo[q] = ok ? ((cl == 0 || cl == g.n[l] - 1) ? 1.0 : 0.5) * g.ih2[l] : 0.0;
+            Po[o] = load_pair(psi + idx + b);
+            Ko[o] = load_pair(K + idx + b);
+            cfo[o] = ok ? ((cl == 0 || cl == g.n[l] - 1) ? 1.0 : 0.5) * g.ih2[l] : 0.0;
         }
-        const double g0 = gv[idx0], g1 = gv[idx1];
         double bz = 0.0;   // root density of the row (2-D, 3-D)
         if (SINK && DIM > 1) bz = beta[DIM == 2 ? j : k];
+        const double xs[2] = {P.x, P.y}, Ks_[2] = {KK.x, KK.y}, gs[2] = {G2.x, G2.y};
+        // axis-0 neighbours: left of ia, right of ia = left of ia + 2, right of ia + 2
+        const double pw[3] = {PX.x, PX.y, PX2}, kw[3] = {KX.x, KX.y, KX2};
         double r[2] = {0.0, 0.0};
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
-            const int i = i0 + a;
-            if (i >= g.n[0] || dirichlet_at(g, i, j, k, nullptr)) continue;
-            const double x = P[1 + a], Ki = KK[1 + a];
+            const int i = ia + 2 * a;
+            if ((a == 1 && !has_b) || dirichlet_at(g, i, j, k, nullptr)) continue;
+            const double x = xs[a], Ki = Ks_[a];
             double s;
-            if constexpr (MODEL == kMulti) s = st.a * theta_only(L.soils[g.soil[a ? idx1 : idx0]], x);
+            if constexpr (MODEL == kMulti) s = st.a * theta_only(L.soils[g.soil[idx + a]], x);
             else s = st.a * theta_only_t<MODEL>(L, x);
             if (SINK) {
                 // in 1-D the row is the vertical axis: each node has its own root density
@@ -573,28 +599,31 @@ __global__ __launch_bounds__(256) void k_residual_pair(Geo g, Law L, Step st, co
             const double cx = ((i == 0 || i == g.n[0] - 1) ? 1.0 : 0.5) * g.ih2[0];
             const double cm0 = i > 0 ? cx : 0.0, cp0 = i < g.n[0] - 1 ? cx : 0.0;
             double mpsi = 0.0;
-            mpsi += cm0 * (Ki + KK[a]) * (x - P[a]);
-            mpsi += cp0 * (Ki + KK[2 + a]) * (x - P[2 + a]);
+            mpsi += cm0 * (Ki + kw[a]) * (x - pw[a]);
+            mpsi += cp0 * (Ki + kw[a + 1]) * (x - pw[a + 1]);
 #pragma unroll
-            for (int q = 0; q < NO; ++q) {
+            for (int o = 0; o < NO; ++o) {
                 // a missing neighbour is the node itself (coefficient 0)
-                const bool ok = cfo[q] != 0.0;
-                const double pn = ok ? Po[q][a] : x, kn = ok ? Ko[q][a] : Ki;
-                mpsi += cfo[q] * (Ki + kn) * (x - pn);
+                const bool ok = cfo[o] != 0.0;
+                const double pn = ok ? (a ? Po[o].y : Po[o].x) : x;
+                const double kn = ok ? (a ? Ko[o].y : Ko[o].x) : Ki;
+                mpsi += cfo[o] * (Ki + kn) * (x - pn);
             }
-            r[a] = (a ? g1 : g0) - (s + (L.xi * x + mpsi));
+            r[a] = gs[a] - (s + (L.xi * x + mpsi));
         }
         if (d) {
-            d[idx0] = r[0];
-            if (i0 + 1 < g.n[0]) d[idx1] = r[1];
+            if (has_b) store_pair(d + idx, r[0], r[1]);
+            else d[idx] = r[0];
         }
         if (mp.rhs) {
-            for (int a = 0; a < 2; ++a) {
-                if (i0 + a >= g.n[0]) break;
-                const long long ia = a ? idx1 : idx0;
-                mp.rhs[ia] = (float)r[a];
-                mp.pb[ia] = (float)P[1 + a];
-                mp.dl[ia] = 0.0f;
+            if (has_b) {
+                store_pair(mp.rhs + idx, (float)r[0], (float)r[1]);
+                store_pair(mp.pb + idx, (float)xs[0], (float)xs[1]);
+                store_pair(mp.dl + idx, 0.0f, 0.0f);
+            } else {
+                mp.rhs[idx] = (float)r[0];
+                mp.pb[idx] = (float)xs[0];
+                mp.dl[idx] = 0.0f;
             }
         }
         const double a0 = fabs(r[0]), a1 = fabs(r[1]);

@@ -35,10 +35,17 @@ __global__ __launch_bounds__(256) void k_sweep32(Geo g, Law32 L, float a, const 
     } else if (DIM == 2) {
         j = row;
     }
-    const int i = 2 * (int)ih + (int)((j + k + colour) & 1);
+    const int par = (int)((j + k + colour) & 1);
+    const int i = 2 * (int)ih + par;
     if (i >= g.n[0]) return;
     if (dirichlet_at(g, i, (int)j, (int)k, nullptr)) return;
-    ngs_cell32<MODEL, SINK, DIM, true>(g, L, a, beta, lambdaU, K, rhs, pb, dl, i, (int)j, (int)k, colour);
+    // parity-split row (see k_sweep): node at ih (+ xh if odd), left neighbour
+    // at ih (odd) or xh + ih - 1 (even), the right one just after it
+    const long long rb = (long long)j * g.stride[1] + (long long)k * g.stride[2];
+    const long long idx = rb + ih + (par ? g.xh : 0);
+    const long long xl = rb + ih + (par ? 0 : g.xh - 1);
+    ngs_cell32<MODEL, SINK, DIM, true, true>(g, L, a, beta, lambdaU, K, rhs, pb, dl, i, (int)j,
+                                             (int)k, colour, idx, xl);
 }
 
 template <int MODEL, bool SINK, int DIM>
@@ -57,7 +64,8 @@ __global__ __launch_bounds__(256) void k_sweep32_small(Geo g, Law32 L, float a, 
                 int k = r / g.n[1];
                 if (((i + j + k) & 1) != colour) continue;
                 if (dirichlet_at(g, i, j, k, nullptr)) continue;
-                ngs_cell32<MODEL, SINK, DIM, true>(g, L, a, beta, lambdaU, K, rhs, pb, dl, i, j, k, colour);
+                ngs_cell32<MODEL, SINK, DIM, true, true>(g, L, a, beta, lambdaU, K, rhs, pb, dl, i, j, k,
+                                                         colour);
             }
             __syncthreads();
         }
