@@ -124,6 +124,10 @@ Geo make_geo(const rs_grid_desc *d, int lev)
         g.bcval[f] = f < 2 * d->dim ? d->face_value[f] : 0.0;
     }
     g.pface = d->patch_face;
+    if (g.pface >= 0) {
+        g.pax = g.pface >> 1;
+        g.pat = (g.pface & 1) ? g.n[g.pax] - 1 : 0;
+    }
     int s = 1 << lev;
     for (int t = 0; t < 2; ++t) {
         g.plo[t] = (d->patch_lo[t] + s - 1) / s;

@@ -16,6 +16,48 @@ __device__ __forceinline__ int vert_index(int i, int j, int k)
     return (DIM == 1) ? i : (DIM == 2 ? j : k);
 }
 
+// New delta of unknown (i, j, k) from gathered values: the stencil, K*_i, the
+// right-hand side f = rhs_i, the old delta d0, the base state pb, and the K*
+// and current delta of the 2 DIM neighbours.
+template <int MODEL, bool SINK, int DIM>
+__device__ __forceinline__ float ngs_point32(const Geo &g, const Law32 &L, float a,
+                                             const double *beta, float lambdaU,
+                                             const Stencil<DIM> &st, float Ki, const float *Kn,
+                                             const float *dn, float f, float d0, float pbi, int i,
+                                             int j, int k, int colour)
+{
+    float mii = 0.0f;
+#pragma unroll
+    for (int q = 0; q < 2 * DIM; ++q) {
+        const float m = (float)st.cf[q] * (Ki + Kn[q]);
+        mii += m;
+        f += m * dn[q];
+    }
+    float kap;
+    if (L.kappa_rule == kKappaConst) {
+        kap = L.kappa;
+    } else if (L.kappa_rule == kKappaRel) {
+        kap = L.kappa * mii;
+    } else if (colour == 0) {
+        float usum = 0.0f;
+#pragma unroll
+        for (int q = 0; q < 2 * DIM; ++q) {
+            int d[3] = {i, j, k};
+            d[q >> 1] += (q & 1) ? 1 : -1;
+            if (st.cf[q] != 0.0 && !dirichlet_at(g, d[0], d[1], d[2], nullptr))
+                usum += (float)st.cf[q] * (Ki + Kn[q]);
+        }
+        kap = lambdaU - usum;
+    } else {
+        kap = lambdaU;
+    }
+    f += kap * d0;
+    const float c = L.xi + kap + mii;
+    const float bz = SINK ? (float)beta[vert_index<DIM>(i, j, k)] : 0.0f;
+    const Base b = base_of<MODEL>(L, pbi);
+    return local_solve32<MODEL, SINK>(L, a, bz, c, f, b, d0);
+}
+
 // New delta at unknown (i, j, k): f = rhs + sum_j m_ij delta_j + kappa delta_i,
 // c = xi + kappa + m_ii, then the scalar correction solve.  XPAD: the arrays
 // have finite padding around them (see stencil()).  SPLIT: the level has
@@ -52,39 +94,8 @@ __device__ __forceinline__ void ngs_cell32(const Geo &g, const Law32 &L, float a
             dn[q] = dl[st.jn[q]];
         }
     }
-    const float Ki = K[idx];
-    const float d0 = dl[idx];
-    float f = rhs[idx];
-    float mii = 0.0f;
-#pragma unroll
-    for (int q = 0; q < 2 * DIM; ++q) {
-        const float m = (float)st.cf[q] * (Ki + Kn[q]);
-        mii += m;
-        f += m * dn[q];
-    }
-    float kap;
-    if (L.kappa_rule == kKappaConst) {
-        kap = L.kappa;
-    } else if (L.kappa_rule == kKappaRel) {
-        kap = L.kappa * mii;
-    } else if (colour == 0) {
-        float usum = 0.0f;
-#pragma unroll
-        for (int q = 0; q < 2 * DIM; ++q) {
-            int d[3] = {i, j, k};
-            d[q >> 1] += (q & 1) ? 1 : -1;
-            if (st.cf[q] != 0.0 && !dirichlet_at(g, d[0], d[1], d[2], nullptr))
-                usum += (float)st.cf[q] * (Ki + Kn[q]);
-        }
-        kap = lambdaU - usum;
-    } else {
-        kap = lambdaU;
-    }
-    f += kap * d0;
-    const float c = L.xi + kap + mii;
-    const float bz = SINK ? (float)beta[vert_index<DIM>(i, j, k)] : 0.0f;
-    const Base b = base_of<MODEL>(L, pb[idx]);
-    dl[idx] = local_solve32<MODEL, SINK>(L, a, bz, c, f, b, d0);
+    dl[idx] = ngs_point32<MODEL, SINK, DIM>(g, L, a, beta, lambdaU, st, K[idx], Kn, dn, rhs[idx],
+                                             dl[idx], pb[idx], i, j, k, colour);
 }
 
 // N_delta(delta)_i = a dtheta + beta da + xi delta_i + sum_j m_ij (delta_i - delta_j)

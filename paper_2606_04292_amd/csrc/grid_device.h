@@ -215,6 +215,56 @@ __device__ __forceinline__ Stencil<DIM> stencil_split(const Geo &g, int i, int j
     return s;
 }
 
+// Raw buffer access to one array of a level (arrays of < 2 GiB): 32-bit byte
+// offsets from a base held in scalar registers, so a stencil's addresses cost
+// one 32-bit add each; an offset outside [0, bytes) reads 0.
+typedef int v2i32 __attribute__((ext_vector_type(2)));
+typedef int v4i32 __attribute__((ext_vector_type(4)));
+typedef double v2f64 __attribute__((ext_vector_type(2)));
+typedef float v2f32 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void *p, long long bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes,
+                                             0x00020000);
+}
+
+template <typename T> __device__ __forceinline__ T buf_ld(__amdgpu_buffer_rsrc_t r, int off);
+template <> __device__ __forceinline__ double buf_ld<double>(__amdgpu_buffer_rsrc_t r, int off)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+template <> __device__ __forceinline__ float buf_ld<float>(__amdgpu_buffer_rsrc_t r, int off)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+
+// Two adjacent values at byte offset off (dword alignment suffices).
+__device__ __forceinline__ v2f64 buf_ld2(__amdgpu_buffer_rsrc_t r, int off, double)
+{
+    return __builtin_bit_cast(v2f64, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+__device__ __forceinline__ v2f32 buf_ld2(__amdgpu_buffer_rsrc_t r, int off, float)
+{
+    return __builtin_bit_cast(v2f32, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, int off, double v)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2i32, v), r, off, 0, 0);
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, int off, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v), r, off, 0, 0);
+}
+
+// Levels whose arrays (with their padding) stay below 2 GiB take the buffer
+// paths of the sweeps.
+inline bool buffer_ok(const Geo &g, size_t elem)
+{
+    return (unsigned long long)(g.N + 64) * elem < (1ull << 31);
+}
+
 struct NodeMap {
     unsigned n0, n1;
     FastDiv d0, d1;

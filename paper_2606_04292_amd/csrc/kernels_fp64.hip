@@ -327,7 +327,11 @@ __global__ __launch_bounds__(512) void k_sweep_fused(Geo g, Law L, Step st, cons
     }
 }
 
-template <int MODEL, bool SINK, int DIM>
+// One colour of a red-black sweep, one node per lane.  BUF (levels whose
+// arrays stay below 2 GiB): the stencil is gathered through raw buffer loads
+// with 32-bit offsets (off-row neighbours outside the level read 0 and have
+// coefficient 0; the axis-0 pair reads the padding at the row's end).
+template <int MODEL, bool SINK, int DIM, bool BUF>
 __global__ __launch_bounds__(256) void k_sweep(Geo g, Law L, Step st, const double *beta,
                                                double lambdaU, const double *K, const double *gv,
                                                double *psi, int colour, ColourMap cm)
@@ -353,8 +357,34 @@ __global__ __launch_bounds__(256) void k_sweep(Geo g, Law L, Step st, const doub
     const long long rb = (long long)j * g.stride[1] + (long long)k * g.stride[2];
     const long long idx = rb + ih + (par ? g.xh : 0);
     const long long xl = rb + ih + (par ? 0 : g.xh - 1);
-    ngs_cell_at<MODEL, SINK, DIM>(g, L, st.a, beta, lambdaU, K, gv, psi, i, (int)j, (int)k, idx, xl,
-                                  colour);
+    if constexpr (BUF) {
+        const long long bytes = (g.N + 32) * (long long)sizeof(double);   // + padding
+        const __amdgpu_buffer_rsrc_t rP = buf_rsrc(psi, bytes), rK = buf_rsrc(K, bytes),
+                                     rG = buf_rsrc(gv, bytes);
+        const int vo = (int)idx * 8, vx = (int)xl * 8;
+        const Stencil<DIM> sn = stencil_split<DIM>(g, i, (int)j, (int)k, idx, xl);
+        const double Ki = buf_ld<double>(rK, vo), x0 = buf_ld<double>(rP, vo);
+        const double f = buf_ld<double>(rG, vo);
+        double Kn[2 * DIM], pn[2 * DIM];
+        const v2f64 kx = buf_ld2(rK, vx, 0.0), px = buf_ld2(rP, vx, 0.0);
+        Kn[0] = kx.x;
+        Kn[1] = kx.y;
+        pn[0] = px.x;
+        pn[1] = px.y;
+#pragma unroll
+        for (int l = 1; l < DIM; ++l) {
+            const int so = g.stride[l] * 8;
+            Kn[2 * l] = buf_ld<double>(rK, vo - so);
+            pn[2 * l] = buf_ld<double>(rP, vo - so);
+            Kn[2 * l + 1] = buf_ld<double>(rK, vo + so);
+            pn[2 * l + 1] = buf_ld<double>(rP, vo + so);
+        }
+        buf_st(rP, vo, ngs_point<MODEL, SINK, DIM>(g, L, st.a, beta, lambdaU, sn, Ki, Kn, pn, f, x0,
+                                                   i, (int)j, (int)k, idx, colour));
+    } else {
+        ngs_cell_at<MODEL, SINK, DIM>(g, L, st.a, beta, lambdaU, K, gv, psi, i, (int)j, (int)k, idx,
+                                      xl, colour);
+    }
 }
 
 // Whole sweeps of a tiny level in one work-group (the coarsest levels, where
@@ -879,10 +909,16 @@ struct SweepLaunch {
         }
         ColourMap cm = colour_map(g);
         dim3 grid(xcd_grid((cm.total + 255) / 256));
+        const bool buf = buffer_ok(g, sizeof(double));
         for (int sw = 0; sw < nsweeps; ++sw)
-            for (int colour = 0; colour < 2; ++colour)
-                hipLaunchKernelGGL((k_sweep<M, S, D>), grid, dim3(256), 0, s, g, law, st, beta,
-                                   lambdaU, K, gvec, *psi, colour, cm);
+            for (int colour = 0; colour < 2; ++colour) {
+                if (buf)
+                    hipLaunchKernelGGL((k_sweep<M, S, D, true>), grid, dim3(256), 0, s, g, law, st,
+                                       beta, lambdaU, K, gvec, *psi, colour, cm);
+                else
+                    hipLaunchKernelGGL((k_sweep<M, S, D, false>), grid, dim3(256), 0, s, g, law, st,
+                                       beta, lambdaU, K, gvec, *psi, colour, cm);
+            }
     }
 };
 

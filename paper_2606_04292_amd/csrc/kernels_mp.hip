@@ -17,7 +17,9 @@ namespace rs {
 
 namespace {
 
-template <int MODEL, bool SINK, int DIM>
+// One colour of a red-black FP32 correction sweep, one node per lane; BUF as
+// for the FP64 sweep (raw buffer loads with 32-bit offsets).
+template <int MODEL, bool SINK, int DIM, bool BUF>
 __global__ __launch_bounds__(256) void k_sweep32(Geo g, Law32 L, float a, const double *beta,
                                                  float lambdaU, const float *K, const float *rhs,
                                                  const float *pb, float *dl, int colour,
@@ -44,8 +46,34 @@ __global__ __launch_bounds__(256) void k_sweep32(Geo g, Law32 L, float a, const 
     const long long rb = (long long)j * g.stride[1] + (long long)k * g.stride[2];
     const long long idx = rb + ih + (par ? g.xh : 0);
     const long long xl = rb + ih + (par ? 0 : g.xh - 1);
-    ngs_cell32<MODEL, SINK, DIM, true, true>(g, L, a, beta, lambdaU, K, rhs, pb, dl, i, (int)j,
-                                             (int)k, colour, idx, xl);
+    if constexpr (BUF) {
+        const long long bytes = (g.N + 64) * (long long)sizeof(float);   // + padding
+        const __amdgpu_buffer_rsrc_t rK = buf_rsrc(K, bytes), rR = buf_rsrc(rhs, bytes),
+                                     rB = buf_rsrc(pb, bytes), rD = buf_rsrc(dl, bytes);
+        const int vo = (int)idx * 4, vx = (int)xl * 4;
+        const Stencil<DIM> sn = stencil_split<DIM>(g, i, (int)j, (int)k, idx, xl);
+        float Kn[2 * DIM], dn[2 * DIM];
+        const v2f32 kx = buf_ld2(rK, vx, 0.0f), dx = buf_ld2(rD, vx, 0.0f);
+        Kn[0] = kx.x;
+        Kn[1] = kx.y;
+        dn[0] = dx.x;
+        dn[1] = dx.y;
+#pragma unroll
+        for (int l = 1; l < DIM; ++l) {
+            const int so = g.stride[l] * 4;
+            Kn[2 * l] = buf_ld<float>(rK, vo - so);
+            dn[2 * l] = buf_ld<float>(rD, vo - so);
+            Kn[2 * l + 1] = buf_ld<float>(rK, vo + so);
+            dn[2 * l + 1] = buf_ld<float>(rD, vo + so);
+        }
+        const float Ki = buf_ld<float>(rK, vo), d0 = buf_ld<float>(rD, vo);
+        const float f = buf_ld<float>(rR, vo), pbi = buf_ld<float>(rB, vo);
+        buf_st(rD, vo, ngs_point32<MODEL, SINK, DIM>(g, L, a, beta, lambdaU, sn, Ki, Kn, dn, f, d0,
+                                                     pbi, i, (int)j, (int)k, colour));
+    } else {
+        ngs_cell32<MODEL, SINK, DIM, true, true>(g, L, a, beta, lambdaU, K, rhs, pb, dl, i, (int)j,
+                                                 (int)k, colour, idx, xl);
+    }
 }
 
 template <int MODEL, bool SINK, int DIM>
@@ -138,10 +166,16 @@ struct Sweep32Launch {
         }
         ColourMap cm = colour_map(g);
         dim3 grid(xcd_grid((cm.total + 255) / 256));
+        const bool buf = buffer_ok(g, sizeof(float));
         for (int sw = 0; sw < nsweeps; ++sw)
-            for (int colour = 0; colour < 2; ++colour)
-                hipLaunchKernelGGL((k_sweep32<M, S, D>), grid, dim3(256), 0, s, g, law, a, beta,
-                                   lambdaU, K, rhs, pb, dl, colour, cm);
+            for (int colour = 0; colour < 2; ++colour) {
+                if (buf)
+                    hipLaunchKernelGGL((k_sweep32<M, S, D, true>), grid, dim3(256), 0, s, g, law, a,
+                                       beta, lambdaU, K, rhs, pb, dl, colour, cm);
+                else
+                    hipLaunchKernelGGL((k_sweep32<M, S, D, false>), grid, dim3(256), 0, s, g, law, a,
+                                       beta, lambdaU, K, rhs, pb, dl, colour, cm);
+            }
     }
 };
 

@@ -41,6 +41,7 @@ struct Geo {
     int state_mask;  // bit f: face f's Dirichlet values come from the state psi^n
     double bcval[6];
     int pface;       // patch face or -1
+    int pax, pat;    // the patch face's axis and its coordinate on that axis (0 or n - 1)
     int plo[2], phi[2];
     double pval;
     const unsigned char *soil;   // soil index per node (read only under kMulti)

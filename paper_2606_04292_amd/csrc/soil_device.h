@@ -320,10 +320,12 @@ __device__ __forceinline__ double local_solve_soil(const Law &Ls, double a, doub
 __device__ __forceinline__ bool dirichlet_at(const Geo &g, int i, int j, int k, double *val,
                                              bool *from_state = nullptr)
 {
-    int c[3] = {i, j, k};
+    const int c[3] = {i, j, k};
     bool dir = false;
     double v = 0.0;
     int face = -1;
+    // every array below is indexed by constants only (the loops unroll), so
+    // the level's descriptor stays in scalar registers
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
         if (l >= g.dim) break;
@@ -335,18 +337,13 @@ __device__ __forceinline__ bool dirichlet_at(const Geo &g, int i, int j, int k, 
         }
     }
     if (g.pface >= 0) {
-        int ax = g.pface >> 1;
-        int at = (g.pface & 1) ? g.n[ax] - 1 : 0;
-        if (c[ax] == at) {
-            bool in = true;
-            int t = 0;
-#pragma unroll
-            for (int l = 0; l < 3; ++l) {
-                if (l >= g.dim) break;
-                if (l == ax) continue;
-                if (c[l] < g.plo[t] || c[l] > g.phi[t]) in = false;
-                ++t;
-            }
+        const int ax = g.pax;
+        if ((ax == 0 ? i : (ax == 1 ? j : k)) == g.pat) {
+            // the tangential axes in increasing order: (1, 2), (0, 2) or (0, 1)
+            const int t0 = ax == 0 ? j : i;
+            const int t1 = ax == 2 ? j : k;
+            bool in = t0 >= g.plo[0] && t0 <= g.phi[0];
+            if (g.dim == 3) in = in && t1 >= g.plo[1] && t1 <= g.phi[1];
             if (in) { dir = true; v = g.pval; face = -1; }
         }
     }
