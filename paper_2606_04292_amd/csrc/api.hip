@@ -276,6 +276,16 @@ struct rs_grid {
     double prof_ms;
     long long prof_launches;
     double prof_cells;
+    // Graphs of the part of a V-cycle below the finest level ([0] FP64 cycle,
+    // [1] FP32 correction cycle): captured on the private stream cap when the
+    // kernel arguments they bake in (key) change, replayed on the grid's
+    // stream.  cap null: plain launches (grids of rs_bdf_step_static, the
+    // fused sweep, RS_GRAPH=0).
+    hipStream_t cap;
+    hipGraphExec_t cg[2];
+    unsigned char cg_key[2][512];
+    double cg_updates[2];
+    int law_version;
 };
 
 namespace rs {
@@ -515,6 +525,105 @@ void sweep32_level(rs_grid *G, int l, int nsweeps)
     G->updates += (double)nsweeps * (double)f.unknowns;
 }
 
+int vcycle_level(rs_grid *G, int l, int nu1, int nu2);
+void vcycle32_level(rs_grid *G, int l, int nu1, int nu2);
+
+// The part of a V-cycle below the finest level, as plain launches: the fine
+// defect, restriction and coarse right-hand side, the cycle on level 1 and
+// below, the prolongation.  which = 1: the FP32 correction cycle, which also
+// injects the base state psi_b into the coarse levels (idempotent within an
+// outer correction).
+void coarse_cycle_plain(rs_grid *G, int which, int nu1, int nu2)
+{
+    LevelData &f = G->lev[0], &c = G->lev[1];
+    if (which == 0) {
+        launch_residual(f.geo, G->law, G->step, f.beta, f.K, f.g, f.psi, f.d, nullptr, G->stream);
+        launch_restrict(c.geo, f.geo, f.psi, f.d, c.psibar, c.g, G->stream);
+        launch_coarse_rhs(c.geo, G->law, G->step, c.beta, c.K, c.psibar, c.g, c.psi, G->stream);
+        vcycle_level(G, 1, nu1, nu2);
+        launch_prolong(f.geo, c.geo, c.psi, c.psibar, f.psi, G->stream);
+        return;
+    }
+    const float a = (float)G->step.a;
+    for (int l = 1; l < G->nlev; ++l)
+        launch_inject32(G->lev[l].geo, G->lev[l - 1].geo, G->lev[l - 1].pb32, G->lev[l].pb32,
+                        G->stream);
+    launch_residual32(f.geo, G->law32, a, f.beta, f.K32, f.rhs32, f.pb32, f.dl, f.r32, G->stream);
+    launch_restrict32(c.geo, f.geo, f.dl, f.r32, c.dbar32, c.rhs32, G->stream);
+    launch_coarse_rhs32(c.geo, G->law32, a, c.beta, c.K32, c.pb32, c.dbar32, c.rhs32, c.dl, G->stream);
+    vcycle32_level(G, 1, nu1, nu2);
+    launch_prolong32(f.geo, c.geo, c.dl, c.dbar32, f.dl, G->stream);
+}
+
+// What the coarse-cycle graph bakes into its kernel arguments.
+struct CycleKey {
+    double a, dt;
+    int order, lag_extrap, nu1, nu2, nu_coarse, law_version;
+    double lambdaU[kMaxLevels];
+};
+
+// The coarse part of a V-cycle: replays its graph (captured again when the
+// step coefficients, the law, the cycle counts or the shift change), or
+// launches it plainly on grids without graphs.  A capture that fails turns
+// the graphs off for the grid.
+int coarse_cycle(rs_grid *G, int which, int nu1, int nu2)
+{
+    if (!G->cap) {
+        coarse_cycle_plain(G, which, nu1, nu2);
+        return RS_OK;
+    }
+    CycleKey k;
+    static_assert(sizeof(CycleKey) <= sizeof(G->cg_key[0]), "key size");
+    memset(&k, 0, sizeof k);
+    k.a = G->step.a;
+    k.dt = G->step.dt;
+    k.order = G->step.order;
+    k.lag_extrap = G->step.lag_extrap;
+    k.nu1 = nu1;
+    k.nu2 = nu2;
+    k.nu_coarse = G->nu_coarse;
+    k.law_version = G->law_version;
+    for (int l = 0; l < G->nlev; ++l) k.lambdaU[l] = G->lev[l].lambdaU;
+    if (!G->cg[which] || memcmp(&k, G->cg_key[which], sizeof k) != 0) {
+        if (G->cg[which]) {
+            HIPCALL(hipStreamSynchronize(G->stream));   // a replay may still run
+            HIPCALL(hipGraphExecDestroy(G->cg[which]));
+            G->cg[which] = nullptr;
+        }
+        hipStream_t s = G->stream;
+        const bool prof = G->prof_on;
+        const double u = G->updates;
+        hipGraph_t gr = nullptr;
+        bool ok = hipStreamBeginCapture(G->cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        if (ok) {
+            G->stream = G->cap;
+            G->prof_on = false;
+            coarse_cycle_plain(G, which, nu1, nu2);
+            ok = hipStreamEndCapture(G->cap, &gr) == hipSuccess && gr;
+            G->stream = s;
+            G->prof_on = prof;
+        }
+        G->cg_updates[which] = G->updates - u;
+        G->updates = u;
+        if (ok) ok = hipGraphInstantiate(&G->cg[which], gr, nullptr, nullptr, 0) == hipSuccess;
+        if (gr) (void)hipGraphDestroy(gr);
+        (void)hipGetLastError();
+        if (!ok) {
+            // no graphs for this grid from now on
+            G->cg[which] = nullptr;
+            coarse_cycle_plain(G, which, nu1, nu2);
+            HIPCALL(hipGetLastError());
+            (void)hipStreamDestroy(G->cap);
+            G->cap = nullptr;
+            return RS_OK;
+        }
+        memcpy(G->cg_key[which], &k, sizeof k);
+    }
+    HIPCALL(hipGraphLaunch(G->cg[which], G->stream));
+    G->updates += G->cg_updates[which];
+    return RS_OK;
+}
+
 // FP32 FAS V-cycle on the correction equation (same structure as the FP64 one).
 void vcycle32_level(rs_grid *G, int l, int nu1, int nu2)
 {
@@ -522,6 +631,12 @@ void vcycle32_level(rs_grid *G, int l, int nu1, int nu2)
     const float a = (float)G->step.a;
     if (l == G->nlev - 1) {
         sweep32_level(G, l, G->nu_coarse);
+        return;
+    }
+    if (l == 0) {
+        sweep32_level(G, 0, nu1);
+        (void)coarse_cycle(G, 1, nu1, nu2);
+        sweep32_level(G, 0, nu2);
         return;
     }
     LevelData &c = G->lev[l + 1];
@@ -537,13 +652,10 @@ void vcycle32_level(rs_grid *G, int l, int nu1, int nu2)
 // One outer defect correction: the defect kernel has already written the FP32
 // right-hand side fl32(r), the base state fl32(psi) and delta = 0 on the finest
 // level (fine_norm with mp_start); FP32 cycles solve the correction equation
-// and psi += delta in FP64.
+// (each injecting psi_b into the coarse levels) and psi += delta in FP64.
 void mp_correction(rs_grid *G, int inner, int nu1, int nu2)
 {
     LevelData &f = G->lev[0];
-    for (int l = 1; l < G->nlev; ++l)
-        launch_inject32(G->lev[l].geo, G->lev[l - 1].geo, G->lev[l - 1].pb32, G->lev[l].pb32,
-                        G->stream);
     for (int c = 0; c < inner; ++c) vcycle32_level(G, 0, nu1, nu2);
     launch_apply_delta(f.geo.N, f.dl, f.psi, G->stream);
 }
@@ -563,6 +675,12 @@ int vcycle_level(rs_grid *G, int l, int nu1, int nu2)
         return RS_OK;
     }
     if (l == G->nlev - 1) return sweep_level(G, l, G->nu_coarse);
+    if (l == 0) {
+        int e = sweep_level(G, 0, nu1);
+        if (!e) e = coarse_cycle(G, 0, nu1, nu2);
+        if (!e) e = sweep_level(G, 0, nu2);
+        return e;
+    }
     LevelData &c = G->lev[l + 1];
     int e = sweep_level(G, l, nu1);
     if (e) return e;
@@ -762,6 +880,12 @@ int rs_create_grid(const rs_grid_desc *d, int precision, void *ws_dev, size_t ws
         return fail(RS_EHIP, "hipHostMalloc failed");
     }
     e = grid_view(G, d, precision, L, (char *)ws_dev, (hipStream_t)stream, bits, tail);
+    const char *gv = getenv("RS_GRAPH");
+    const bool fused = G->nlev > 0 && G->lev[0].psi_alt;
+    if (!e && !(gv && gv[0] == '0') && !fused && hipStreamCreate(&G->cap) != hipSuccess) {
+        (void)hipGetLastError();
+        G->cap = nullptr;
+    }
     if (e) {
         (void)hipStreamSynchronize((hipStream_t)stream);
         (void)hipHostFree(tail);
@@ -777,6 +901,9 @@ void rs_destroy_grid(rs_grid *G)
 {
     if (!G) return;
     (void)hipStreamSynchronize(G->stream);   // queued copies read the pinned buffers
+    for (int w = 0; w < 2; ++w)
+        if (G->cg[w]) (void)hipGraphExecDestroy(G->cg[w]);
+    if (G->cap) (void)hipStreamDestroy(G->cap);
     for (hipEvent_t ev : G->prof_ev) (void)hipEventDestroy(ev);
     if (G->host_bits) (void)hipHostFree(G->host_bits);
     if (G->tail_host) (void)hipHostFree(G->tail_host);
@@ -843,6 +970,7 @@ int rs_set_constitutive(rs_grid *G, const rs_constitutive *c)
         HIPCALL(hipGetLastError());
     }
     G->law_set = true;
+    G->law_version += 1;
     return RS_OK;
 }
 
