@@ -59,12 +59,14 @@ __device__ __forceinline__ float ngs_point32(const Geo &g, const Law32 &L, float
 }
 
 // New delta at unknown (i, j, k): f = rhs + sum_j m_ij delta_j + kappa delta_i,
-// c = xi + kappa + m_ii, then the scalar correction solve.  XPAD: the arrays
+// c = xi + kappa + m_ii, then the scalar correction solve; true unless the
+// stored delta moved by at most 4 FP32 ulp (FP32 rounding keeps a converged
+// nonlinear update from settling bitwise).  XPAD: the arrays
 // have finite padding around them (see stencil()).  SPLIT: the level has
 // parity-split rows and padded arrays; the axis-0 neighbours are loaded as
 // one pair from xl (idx and xl < 0: computed here).
 template <int MODEL, bool SINK, int DIM, bool XPAD = false, bool SPLIT = false>
-__device__ __forceinline__ void ngs_cell32(const Geo &g, const Law32 &L, float a,
+__device__ __forceinline__ bool ngs_cell32(const Geo &g, const Law32 &L, float a,
                                            const double *beta, float lambdaU, const float *K,
                                            const float *rhs, const float *pb, float *dl, int i,
                                            int j, int k, int colour, long long idx = -1,
@@ -94,8 +96,11 @@ __device__ __forceinline__ void ngs_cell32(const Geo &g, const Law32 &L, float a
             dn[q] = dl[st.jn[q]];
         }
     }
-    dl[idx] = ngs_point32<MODEL, SINK, DIM>(g, L, a, beta, lambdaU, st, K[idx], Kn, dn, rhs[idx],
-                                             dl[idx], pb[idx], i, j, k, colour);
+    const float d0 = dl[idx];
+    const float d1 = ngs_point32<MODEL, SINK, DIM>(g, L, a, beta, lambdaU, st, K[idx], Kn, dn,
+                                                   rhs[idx], d0, pb[idx], i, j, k, colour);
+    dl[idx] = d1;
+    return !(fabsf(d1 - d0) <= 4.0f * 1.1920929e-7f * fabsf(d1));
 }
 
 // N_delta(delta)_i = a dtheta + beta da + xi delta_i + sum_j m_ij (delta_i - delta_j)

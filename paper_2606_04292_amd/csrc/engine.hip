@@ -498,20 +498,27 @@ __global__ __launch_bounds__(256) void e_transfer32(const EList *DL, const ESlot
 
 __device__ void tail_sweeps(const ESlot &S, float a, const ELevel &Lv, const Arrs &A, int n)
 {
-    for (int sw = 0; sw < n; ++sw)
+    for (int sw = 0; sw < n; ++sw) {
+        int changed = 0;
         for (int colour = 0; colour < 2; ++colour) {
             for (unsigned long long t = threadIdx.x; t < Lv.cm.total; t += blockDim.x) {
                 int i, j, k;
                 if (!colour_ijk(Lv.geo, Lv.cm, t, colour, i, j, k)) continue;
                 if (dirichlet_at(Lv.geo, i, j, k, nullptr)) continue;
                 law_dim(S.law.model, Lv.geo.dim, [&](auto M, auto Dm) {
-                    ngs_cell32<decltype(M)::value, false, decltype(Dm)::value>(
+                    changed |= ngs_cell32<decltype(M)::value, false, decltype(Dm)::value>(
                         Lv.geo, S.law32, a, nullptr, 0.0f, A.K32, A.rhs, A.pb, A.dl, i, j, k,
                         colour);
                 });
             }
-            __syncthreads();
+            // a sweep that moved no value by more than FP32 rounding (4 ulp)
+            // has converged in FP32 (the correction solve only sets the outer
+            // FP64 iteration's contraction): the sweeps left would shuffle
+            // rounding
+            if (colour == 0) __syncthreads();
+            else if (!__syncthreads_or(changed)) return;
         }
+    }
 }
 
 // The V-cycle from level top down to the coarsest and back, one work-group;

@@ -176,7 +176,7 @@ __device__ __forceinline__ double ngs_point(const Geo &g, const Law &L, double a
 // xl + 1 (a grid's levels have parity-split rows, see stencil_split; the
 // workspace arrays are padded, so both are always loaded, as one pair).
 template <int MODEL, bool SINK, int DIM>
-__device__ __forceinline__ void ngs_cell_at(const Geo &g, const Law &L, double a,
+__device__ __forceinline__ bool ngs_cell_at(const Geo &g, const Law &L, double a,
                                             const double *beta, double lambdaU, const double *K,
                                             const double *gv, double *psi, int i, int j, int k,
                                             long long idx, long long xl, int colour)
@@ -196,18 +196,21 @@ __device__ __forceinline__ void ngs_cell_at(const Geo &g, const Law &L, double a
         Kn[q] = K[st.jn[q]];
         pn[q] = psi[st.jn[q]];
     }
-    psi[idx] = ngs_point<MODEL, SINK, DIM>(g, L, a, beta, lambdaU, st, Ki, Kn, pn, f, x0, i, j, k,
-                                           idx, colour);
+    const double x1 = ngs_point<MODEL, SINK, DIM>(g, L, a, beta, lambdaU, st, Ki, Kn, pn, f, x0, i,
+                                                  j, k, idx, colour);
+    psi[idx] = x1;
+    return !(x1 == x0);
 }
 
+// The update of unknown (i, j, k); true if it changed the stored value.
 template <int MODEL, bool SINK, int DIM>
-__device__ __forceinline__ void ngs_cell(const Geo &g, const Law &L, double a, const double *beta,
+__device__ __forceinline__ bool ngs_cell(const Geo &g, const Law &L, double a, const double *beta,
                                          double lambdaU, const double *K, const double *gv,
                                          double *psi, int i, int j, int k, int colour)
 {
     const long long idx = lin(g, i, j, k);
-    ngs_cell_at<MODEL, SINK, DIM>(g, L, a, beta, lambdaU, K, gv, psi, i, j, k, idx,
-                                  xnb(g, i, idx, -1), colour);
+    return ngs_cell_at<MODEL, SINK, DIM>(g, L, a, beta, lambdaU, K, gv, psi, i, j, k, idx,
+                                         xnb(g, i, idx, -1), colour);
 }
 
 // ---------------------------------------------------------------------------
@@ -396,6 +399,7 @@ __global__ __launch_bounds__(256) void k_sweep_small(Geo g, Law L, Step st, cons
 {
     const int N = (int)g.N;
     for (int s = 0; s < nsweeps; ++s) {
+        int changed = 0;
         for (int colour = 0; colour < 2; ++colour) {
             for (int t = threadIdx.x; t < N; t += blockDim.x) {
                 int i = t % g.n[0];
@@ -404,9 +408,13 @@ __global__ __launch_bounds__(256) void k_sweep_small(Geo g, Law L, Step st, cons
                 int k = r / g.n[1];
                 if (((i + j + k) & 1) != colour) continue;
                 if (dirichlet_at(g, i, j, k, nullptr)) continue;
-                ngs_cell<MODEL, SINK, DIM>(g, L, st.a, beta, lambdaU, K, gv, psi, i, j, k, colour);
+                changed |= ngs_cell<MODEL, SINK, DIM>(g, L, st.a, beta, lambdaU, K, gv, psi, i, j, k,
+                                                      colour);
             }
-            __syncthreads();
+            // a sweep that changed no value has reached its fixed point: the
+            // sweeps left would repeat it exactly
+            if (colour == 0) __syncthreads();
+            else if (!__syncthreads_or(changed)) return;
         }
     }
 }
@@ -443,17 +451,21 @@ template <int MODEL, bool SINK, int DIM>
 __device__ void tail_sweeps64(const TailLevel &T, const Law &L, double a, int n)
 {
     const ColourMap cm = tail_cm(T);
-    for (int sw = 0; sw < n; ++sw)
+    for (int sw = 0; sw < n; ++sw) {
+        int changed = 0;
         for (int colour = 0; colour < 2; ++colour) {
             for (unsigned long long t = threadIdx.x; t < cm.total; t += blockDim.x) {
                 int i, j, k;
                 if (!colour_ijk(T.g, cm, t, colour, i, j, k)) continue;
                 if (dirichlet_at(T.g, i, j, k, nullptr)) continue;
-                ngs_cell<MODEL, SINK, DIM>(T.g, L, a, T.beta, T.lambdaU, T.K, T.gv, T.psi, i, j, k,
-                                           colour);
+                changed |= ngs_cell<MODEL, SINK, DIM>(T.g, L, a, T.beta, T.lambdaU, T.K, T.gv, T.psi,
+                                                      i, j, k, colour);
             }
-            __syncthreads();
+            // a sweep that changed no value is a fixed point (see k_sweep_small)
+            if (colour == 0) __syncthreads();
+            else if (!__syncthreads_or(changed)) return;
         }
+    }
 }
 
 // Levels lds_from..last live in LDS for the duration of the cycle (psi, K*, g,

@@ -84,6 +84,7 @@ __global__ __launch_bounds__(256) void k_sweep32_small(Geo g, Law32 L, float a, 
 {
     const int N = (int)g.N;
     for (int s = 0; s < nsweeps; ++s) {
+        int changed = 0;
         for (int colour = 0; colour < 2; ++colour) {
             for (int t = threadIdx.x; t < N; t += blockDim.x) {
                 int i = t % g.n[0];
@@ -92,10 +93,14 @@ __global__ __launch_bounds__(256) void k_sweep32_small(Geo g, Law32 L, float a, 
                 int k = r / g.n[1];
                 if (((i + j + k) & 1) != colour) continue;
                 if (dirichlet_at(g, i, j, k, nullptr)) continue;
-                ngs_cell32<MODEL, SINK, DIM, true, true>(g, L, a, beta, lambdaU, K, rhs, pb, dl, i, j, k,
-                                                         colour);
+                changed |= ngs_cell32<MODEL, SINK, DIM, true, true>(g, L, a, beta, lambdaU, K, rhs, pb,
+                                                                    dl, i, j, k, colour);
             }
-            __syncthreads();
+            // a sweep that moved no value by more than FP32 rounding (4 ulp) has
+            // converged in FP32: the correction solve only sets the outer
+            // FP64 iteration's contraction, the rest would shuffle rounding
+            if (colour == 0) __syncthreads();
+            else if (!__syncthreads_or(changed)) return;
         }
     }
 }
