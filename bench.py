@@ -40,16 +40,18 @@ TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "sweep_fp64_block3d_haverkamp_2
 COUNTERS_PROFILE = os.path.join(ROOT, "profiles", "sweep_fp64_block3d_haverkamp_257_counters.md")
 
 
-# The translation unit of the FP64 sweep kernel: the traffic counters stay
-# valid while these sources are unchanged.
+# The translation units of the FP64 and FP32 sweep kernels: their counters
+# stay valid while these sources are unchanged.
 SWEEP_SOURCES = ["kernels_fp64.hip", "rs_internal.h", "soil_device.h", "grid_device.h",
                  "transfer.h", "cell64.h"]
+SWEEP32_SOURCES = ["kernels_mp.hip", "rs_internal.h", "soil_device.h", "grid_device.h",
+                   "transfer.h", "soil_mp.h", "cell32.h"]
 
 
-def kernel_sources_sha256():
+def kernel_sources_sha256(sources=SWEEP_SOURCES):
     import hashlib
     h = hashlib.sha256()
-    for name in SWEEP_SOURCES:
+    for name in sources:
         p = os.path.join(ROOT, "paper_2606_04292_amd", "csrc", name)
         h.update(name.encode())
         with open(p, "rb") as f:
@@ -57,7 +59,7 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def profiled_value(path, key):
+def profiled_value(path, key, sources=SWEEP_SOURCES):
     """The number recorded as `key=value kernel_sources_sha256=...` in a
     committed counter summary, or None when the summary is missing or the
     kernel sources changed since the counters were taken."""
@@ -67,20 +69,20 @@ def profiled_value(path, key):
             m = re.search(key + r"=([0-9.]+) kernel_sources_sha256=([0-9a-f]+)", f.read())
     except OSError:
         return None
-    if not m or m.group(2) != kernel_sources_sha256():
+    if not m or m.group(2) != kernel_sources_sha256(sources):
         return None
     return float(m.group(1))
 
 
-def profiled_traffic():
+def profiled_traffic(key="sweep_traffic_bytes", sources=SWEEP_SOURCES):
     """Calibrated HBM bytes (read + write) per finest-level sweep launch."""
-    v = profiled_value(TRAFFIC_PROFILE, "sweep_traffic_bytes")
+    v = profiled_value(TRAFFIC_PROFILE, key, sources)
     return None if v is None else int(v)
 
 
-def profiled_valu_busy():
+def profiled_valu_busy(key="sweep_valu_busy_pct", sources=SWEEP_SOURCES):
     """VALUBusy (%) of the finest-level sweep launches."""
-    return profiled_value(COUNTERS_PROFILE, "sweep_valu_busy_pct")
+    return profiled_value(COUNTERS_PROFILE, key, sources)
 
 
 def time_loop(G, w, psi0, steps, opts, label):
@@ -160,6 +162,7 @@ def gpu_run(args):
         t32 = ms32 * 1e-3 / max(l32, 1)
         b32 = BYTES_PER_UPDATE_32 * c32 / max(l32, 1)
         mbad = [k + 1 for k, x in enumerate(msteps) if x[0] != rsl.RS_OK]
+        tr32 = profiled_traffic("sweep32_traffic_bytes", SWEEP32_SOURCES)
         mixed = {"ms_per_step": round(el2 * 1e3 / args.steps, 3),
                  "speedup_vs_fp64": round(elapsed / el2, 3),
                  "fp32_cell_updates_per_s": sum(x[3] for x in msteps) / el2,
@@ -172,6 +175,11 @@ def gpu_run(args):
                                          "frac": round(b32 / t32 / 1e9 / HBM_PEAK_GBS, 4),
                                          "kernel": "k_sweep32 (finest level, one colour per launch)",
                                          "bytes_per_update": BYTES_PER_UPDATE_32,
+                                         "traffic": tr32,
+                                         "traffic_per_algorithmic": (round(tr32 / b32, 3)
+                                                                     if tr32 else None),
+                                         "valu_busy_pct": profiled_valu_busy(
+                                             "sweep32_valu_busy_pct", SWEEP32_SOURCES),
                                          "avg_launch_us": round(t32 * 1e6, 2), "launches": l32},
                  "note": "the same %d steps from t = 0 to the same tolerance; rel_err_vs_fp64 = "
                          "max|psi_MP - psi_FP64| / max|psi_FP64| after the last step" % args.steps}

@@ -399,7 +399,6 @@ __global__ __launch_bounds__(256) void k_sweep_small(Geo g, Law L, Step st, cons
 {
     const int N = (int)g.N;
     for (int s = 0; s < nsweeps; ++s) {
-        int changed = 0;
         for (int colour = 0; colour < 2; ++colour) {
             for (int t = threadIdx.x; t < N; t += blockDim.x) {
                 int i = t % g.n[0];
@@ -408,13 +407,9 @@ __global__ __launch_bounds__(256) void k_sweep_small(Geo g, Law L, Step st, cons
                 int k = r / g.n[1];
                 if (((i + j + k) & 1) != colour) continue;
                 if (dirichlet_at(g, i, j, k, nullptr)) continue;
-                changed |= ngs_cell<MODEL, SINK, DIM>(g, L, st.a, beta, lambdaU, K, gv, psi, i, j, k,
-                                                      colour);
+                ngs_cell<MODEL, SINK, DIM>(g, L, st.a, beta, lambdaU, K, gv, psi, i, j, k, colour);
             }
-            // a sweep that changed no value has reached its fixed point: the
-            // sweeps left would repeat it exactly
-            if (colour == 0) __syncthreads();
-            else if (!__syncthreads_or(changed)) return;
+            __syncthreads();
         }
     }
 }
@@ -451,21 +446,17 @@ template <int MODEL, bool SINK, int DIM>
 __device__ void tail_sweeps64(const TailLevel &T, const Law &L, double a, int n)
 {
     const ColourMap cm = tail_cm(T);
-    for (int sw = 0; sw < n; ++sw) {
-        int changed = 0;
+    for (int sw = 0; sw < n; ++sw)
         for (int colour = 0; colour < 2; ++colour) {
             for (unsigned long long t = threadIdx.x; t < cm.total; t += blockDim.x) {
                 int i, j, k;
                 if (!colour_ijk(T.g, cm, t, colour, i, j, k)) continue;
                 if (dirichlet_at(T.g, i, j, k, nullptr)) continue;
-                changed |= ngs_cell<MODEL, SINK, DIM>(T.g, L, a, T.beta, T.lambdaU, T.K, T.gv, T.psi,
-                                                      i, j, k, colour);
+                ngs_cell<MODEL, SINK, DIM>(T.g, L, a, T.beta, T.lambdaU, T.K, T.gv, T.psi, i, j, k,
+                                           colour);
             }
-            // a sweep that changed no value is a fixed point (see k_sweep_small)
-            if (colour == 0) __syncthreads();
-            else if (!__syncthreads_or(changed)) return;
+            __syncthreads();
         }
-    }
 }
 
 // Levels lds_from..last live in LDS for the duration of the cycle (psi, K*, g,
