@@ -270,8 +270,12 @@ int rs_end_step(rs_grid *g);
 
 /* One full time step: begin_step, V-cycles (RS_FP64) or FP32 correction
  * cycles inside FP64 defect correction (RS_MIXED) until the tolerance, then
- * end_step.  Synchronises.  On RS_ENOTCONV / RS_ENONFINITE the iterate is
- * left in place and the history is NOT advanced. */
+ * end_step.  FP64 cycles on grids with more than one work-group's worth of
+ * fine nodes take the stopping test on the defect each cycle forms after its
+ * pre-smoothing (for the restriction), and end the step there with that
+ * iterate; the test of the section 3.2 criterion itself is unchanged.
+ * Synchronises.  On RS_ENOTCONV / RS_ENONFINITE the iterate is left in place
+ * and the history is NOT advanced. */
 int rs_bdf_step(rs_grid *g, double dt, int order, const rs_solve_opts *o, rs_step_stats *st);
 
 /* Inspection: copy / overwrite one FP64 field of a level (device arrays of

@@ -528,16 +528,16 @@ void sweep32_level(rs_grid *G, int l, int nsweeps)
 int vcycle_level(rs_grid *G, int l, int nu1, int nu2);
 void vcycle32_level(rs_grid *G, int l, int nu1, int nu2);
 
-// The part of a V-cycle below the finest level, as plain launches: the fine
-// defect, restriction and coarse right-hand side, the cycle on level 1 and
-// below, the prolongation.  which = 1: the FP32 correction cycle, which also
-// injects the base state psi_b into the coarse levels (idempotent within an
-// outer correction).
+// The part of a V-cycle below the finest level, as plain launches: the
+// restriction of the fine iterate and of its defect (FP64: already in the
+// level's d), the coarse right-hand side, the cycle on level 1 and below, the
+// prolongation.  which = 1: the FP32 correction cycle, which first forms its
+// inner defect and injects the base state psi_b into the coarse levels
+// (idempotent within an outer correction).
 void coarse_cycle_plain(rs_grid *G, int which, int nu1, int nu2)
 {
     LevelData &f = G->lev[0], &c = G->lev[1];
     if (which == 0) {
-        launch_residual(f.geo, G->law, G->step, f.beta, f.K, f.g, f.psi, f.d, nullptr, G->stream);
         launch_restrict(c.geo, f.geo, f.psi, f.d, c.psibar, c.g, G->stream);
         launch_coarse_rhs(c.geo, G->law, G->step, c.beta, c.K, c.psibar, c.g, c.psi, G->stream);
         vcycle_level(G, 1, nu1, nu2);
@@ -677,7 +677,9 @@ int vcycle_level(rs_grid *G, int l, int nu1, int nu2)
     if (l == G->nlev - 1) return sweep_level(G, l, G->nu_coarse);
     if (l == 0) {
         int e = sweep_level(G, 0, nu1);
-        if (!e) e = coarse_cycle(G, 0, nu1, nu2);
+        if (e) return e;
+        launch_residual(f.geo, G->law, G->step, f.beta, f.K, f.g, f.psi, f.d, nullptr, G->stream);
+        e = coarse_cycle(G, 0, nu1, nu2);
         if (!e) e = sweep_level(G, 0, nu2);
         return e;
     }
@@ -1156,7 +1158,39 @@ int rs_bdf_step(rs_grid *G, double dt, int order, const rs_solve_opts *o, rs_ste
         e = fine_norm(G, &r, nullptr, true);   // defect vector for the first correction
         if (e) return e;
     }
+    // FP64 V-cycles on grids whose finest level is not part of the
+    // one-work-group cycle take the stopping test where the cycle forms the
+    // fine defect anyway, after the pre-smoothing: a step ends there, with
+    // that iterate, once its defect meets the test (one fine defect pass per
+    // cycle instead of two).
+    const bool test_in_cycle = !mixed && G->nlev > 1 && G->tail_top > 0;
     while (std::isfinite(r) && r > o->tol_abs && cycles < o->max_cycles) {
+        if (test_in_cycle && !(o->fmg && cycles == 0)) {
+            LevelData &f = G->lev[0];
+            e = sweep_level(G, 0, o->nu1);
+            if (e) return e;
+            double rn;
+            e = fine_norm(G, &rn, f.d);
+            if (e) return e;
+            ++cycles;
+            if (nh < 64) hist[nh++] = rn;
+            r = rn;
+            if (o->stagnation) {
+                if (rn < best) {
+                    best = rn;
+                    slow = 0;
+                } else if (++slow >= 2) {
+                    stagnated = true;
+                    break;
+                }
+            }
+            if (!(std::isfinite(rn) && rn > o->tol_abs) || cycles >= o->max_cycles) break;
+            e = coarse_cycle(G, 0, o->nu1, o->nu2);
+            if (!e) e = sweep_level(G, 0, o->nu2);
+            if (e) return e;
+            HIPCALL(hipGetLastError());
+            continue;
+        }
         if (o->fmg && cycles == 0) {
             e = fmg_cycle(G, o->nu1, o->nu2);
             if (e) return e;
