@@ -558,7 +558,8 @@ def config_leg(args, cfg):
                           stagnation=1)
     out = {"config": cfg, "workload": "%s: %s nodes, %s, dt %g s, %d steps, V(%d,%d), every step "
                                       "to %s" % (
-               w.name, "x".join(str(v) for v in w.grid.n), "BDF1" if w.order == 1 else "BDF2",
+               w.name, "x".join(str(v) for v in w.grid.n),
+               "BDF1" if w.order == 1 else "BDF2 history, conductivity lagged at psi^n",
                w.dt, w.steps, w.nu1, w.nu2,
                "the rounding floor" if tol == 0 else "tol %.0e or the rounding floor" % tol)}
     finals = {}
@@ -768,7 +769,8 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "%s: %d^3 nodes, Haverkamp, BDF2 dt=%g s, steps 1-%d of the "
+        "config": {"workload": "%s: %d^3 nodes, Haverkamp, BDF2 history with the conductivity "
+                               "lagged at psi^n (first order in time), dt=%g s, steps 1-%d of the "
                                "%d-step drainage from t = 0, FAS V(%d,%d), red-black NGS, at most "
                                "%d Newton steps/cell, tol %.0e or the rounding floor" % (
                                    w.name, args.n, w.dt, min(args.steps, w.steps), w.steps,
