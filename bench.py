@@ -196,7 +196,7 @@ def gpu_run(args):
                   "traffic_source": os.path.relpath(TRAFFIC_PROFILE, ROOT),
                   "valu_busy_pct": profiled_valu_busy(),
                   "counters_source": os.path.relpath(COUNTERS_PROFILE, ROOT),
-                  "kernel": "k_sweep (finest level, one colour per launch)",
+                  "kernel": "k_sweep_pair (finest level, one colour per launch, two nodes per lane)",
                   "avg_launch_us": round(avg_launch_s * 1e6, 2),
                   "bytes_per_launch": bytes_per_launch, "launches": launches,
                   "sweep_updates_per_s": sweep_cells / (sweep_ms * 1e-3)},

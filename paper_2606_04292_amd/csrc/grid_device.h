@@ -257,6 +257,12 @@ __device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, int off, float 
 {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v), r, off, 0, 0);
 }
+// Two adjacent values at byte offset off (dword alignment suffices).
+__device__ __forceinline__ void buf_st2(__amdgpu_buffer_rsrc_t r, int off, double a, double b)
+{
+    const v2f64 v = {a, b};
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4i32, v), r, off, 0, 0);
+}
 
 // Levels whose arrays (with their padding) stay below 2 GiB take the buffer
 // paths of the sweeps.

@@ -124,14 +124,22 @@ __global__ __launch_bounds__(256) void k_lambda_u(Geo g, const double *K, unsign
 // Red-black NGS (eq. iterative / eq. point-update)
 // ---------------------------------------------------------------------------
 
-// New value of unknown (i, j, k) from gathered values (eq. point-update): the
-// stencil, K*_i, g_i, the old value x0 and the K* and current psi of the 2 DIM
-// neighbours (outside the domain: zero coefficient, any finite value).
-template <int MODEL, bool SINK, int DIM>
-__device__ __forceinline__ double ngs_point(const Geo &g, const Law &L, double a, const double *beta,
-                                            double lambdaU, const Stencil<DIM> &st, double Ki,
-                                            const double *Kn, const double *pn, double f, double x0,
-                                            int i, int j, int k, long long idx, int colour)
+// The scalars of one unknown's local problem (eq. point-update): the
+// coefficient c = xi + kappa + m_ii of its own value, the right-hand side f
+// (g_i plus the neighbour couplings plus kappa x0) and its root density.
+struct PointEq {
+    double cc, f, b;
+};
+
+// Reduces the stencil of unknown (i, j, k): K*_i, g_i, the old value x0 and
+// the K* and current psi of the 2 DIM neighbours (outside the domain: zero
+// coefficient, any finite value).  REMARK = false: the caller has excluded the
+// Remark's kappa rule.
+template <bool SINK, int DIM, bool REMARK = true>
+__device__ __forceinline__ PointEq ngs_reduce(const Geo &g, const Law &L, const double *beta,
+                                              double lambdaU, const Stencil<DIM> &st, double Ki,
+                                              const double *Kn, const double *pn, double f,
+                                              double x0, int i, int j, int k, int colour)
 {
     double mii = 0.0;
 #pragma unroll
@@ -143,7 +151,7 @@ __device__ __forceinline__ double ngs_point(const Geo &g, const Law &L, double a
     double kap;
     if (L.kappa_rule == kKappaConst) {
         kap = L.kappa;
-    } else if (L.kappa_rule == kKappaRel) {
+    } else if (!REMARK || L.kappa_rule == kKappaRel) {
         kap = L.kappa * mii;
     } else if (colour == 0) {
         double usum = 0.0;
@@ -158,18 +166,39 @@ __device__ __forceinline__ double ngs_point(const Geo &g, const Law &L, double a
     } else {
         kap = lambdaU;
     }
-    f += kap * x0;
-    const double cc = L.xi + kap + mii;
+    PointEq e;
+    e.f = f + kap * x0;
+    e.cc = L.xi + kap + mii;
     const int vk = (DIM == 1) ? i : (DIM == 2 ? j : k);
-    const double b = SINK ? beta[vk] : 0.0;
+    e.b = SINK ? beta[vk] : 0.0;
+    return e;
+}
+
+// The safeguarded Newton solve of a reduced point problem.
+template <int MODEL, bool SINK>
+__device__ __forceinline__ double ngs_solve(const Geo &g, const Law &L, double a, const PointEq &e,
+                                            double x0, long long idx)
+{
     if constexpr (MODEL == kMulti) {
         const Law &Ls = L.soils[g.soil[idx]];
-        return (L.newton == 3) ? local_solve_soil<SINK, 3>(Ls, a, b, cc, f, x0)
-                               : local_solve_soil<SINK, 0>(Ls, a, b, cc, f, x0);
+        return (L.newton == 3) ? local_solve_soil<SINK, 3>(Ls, a, e.b, e.cc, e.f, x0)
+                               : local_solve_soil<SINK, 0>(Ls, a, e.b, e.cc, e.f, x0);
     } else {
-        return (L.newton == 3) ? local_solve_t<MODEL, SINK, 3>(L, a, b, cc, f, x0)
-                               : local_solve_t<MODEL, SINK, 0>(L, a, b, cc, f, x0);
+        return (L.newton == 3) ? local_solve_t<MODEL, SINK, 3>(L, a, e.b, e.cc, e.f, x0)
+                               : local_solve_t<MODEL, SINK, 0>(L, a, e.b, e.cc, e.f, x0);
     }
+}
+
+// New value of unknown (i, j, k) from gathered values (eq. point-update).
+template <int MODEL, bool SINK, int DIM>
+__device__ __forceinline__ double ngs_point(const Geo &g, const Law &L, double a, const double *beta,
+                                            double lambdaU, const Stencil<DIM> &st, double Ki,
+                                            const double *Kn, const double *pn, double f, double x0,
+                                            int i, int j, int k, long long idx, int colour)
+{
+    const PointEq e = ngs_reduce<SINK, DIM>(g, L, beta, lambdaU, st, Ki, Kn, pn, f, x0, i, j, k,
+                                            colour);
+    return ngs_solve<MODEL, SINK>(g, L, a, e, x0, idx);
 }
 
 // Update of unknown (i, j, k) stored at idx, its axis-0 neighbours at xl and
@@ -388,6 +417,91 @@ __global__ __launch_bounds__(256) void k_sweep(Geo g, Law L, Step st, const doub
         ngs_cell_at<MODEL, SINK, DIM>(g, L, st.a, beta, lambdaU, K, gv, psi, i, (int)j, (int)k, idx,
                                       xl, colour);
     }
+}
+
+// One colour of a red-black sweep, two nodes of that colour per lane: half-row
+// positions 2q and 2q + 1 (nodes i and i + 2), through raw buffer loads as in
+// k_sweep (levels below 2 GiB).  Own values, g and each off-row direction are
+// one 16-byte load per array, the three axis-0 neighbours (in the other half)
+// a pair and a single.  Both stencils are reduced to their point problems
+// before the first solve starts, so the second node holds three values, not
+// its stencil, through the first solve; the solves run one after the other.
+// The per-node arithmetic is that of k_sweep; the kappa rule is CONST or REL
+// (the launcher sends the Remark's rule to k_sweep).  Slots: (xh + 1) / 2 per
+// row.
+template <int MODEL, bool SINK, int DIM>
+__global__ __launch_bounds__(256) void k_sweep_pair(Geo g, Law L, Step st, const double *beta,
+                                                    double lambdaU, const double *K,
+                                                    const double *gv, double *psi, int colour,
+                                                    ColourMap cm)
+{
+    const unsigned long long t =
+        (unsigned long long)xcd_block_dir(gridDim.x / 8u, colour & 1) * blockDim.x + threadIdx.x;
+    if (t >= cm.total) return;
+    const unsigned row = udiv((unsigned)t, cm.dH);
+    const int q = (int)((unsigned)(t - (unsigned long long)row * cm.H));
+    unsigned j = 0, k = 0;
+    if (DIM == 3) {
+        k = udiv(row, cm.dN1);
+        j = row - k * cm.n1;
+    } else if (DIM == 2) {
+        j = row;
+    }
+    const int par = (int)((j + k + colour) & 1);
+    const int len = par ? g.n[0] - g.xh : g.xh;   // nodes of this parity in the row
+    if (2 * q >= len) return;
+    const bool has_b = 2 * q + 1 < len;
+    const int ia = 4 * q + par;                   // nodes ia and ia + 2
+    const long long rb = (long long)j * g.stride[1] + (long long)k * g.stride[2];
+    const long long idx = rb + (par ? g.xh : 0) + 2 * q;
+    const long long xl = rb + (par ? 0 : g.xh - 1) + 2 * q;   // ia - 1, ia + 1, ia + 3
+    const bool dir_a = dirichlet_at(g, ia, (int)j, (int)k, nullptr);
+    const bool dir_b = !has_b || dirichlet_at(g, ia + 2, (int)j, (int)k, nullptr);
+    if (dir_a && dir_b) return;
+    const long long bytes = (g.N + 32) * (long long)sizeof(double);   // + padding
+    const __amdgpu_buffer_rsrc_t rP = buf_rsrc(psi, bytes), rK = buf_rsrc(K, bytes),
+                                 rG = buf_rsrc(gv, bytes);
+    const int vo = (int)idx * 8, vx = (int)xl * 8;
+    const v2f64 P = buf_ld2(rP, vo, 0.0), KK = buf_ld2(rK, vo, 0.0), G2 = buf_ld2(rG, vo, 0.0);
+    const v2f64 PX = buf_ld2(rP, vx, 0.0), KX = buf_ld2(rK, vx, 0.0);
+    const double PX2 = buf_ld<double>(rP, vx + 16), KX2 = buf_ld<double>(rK, vx + 16);
+    constexpr int NO = 2 * (DIM - 1);
+    v2f64 Po[NO > 0 ? NO : 1], Ko[NO > 0 ? NO : 1];
+#pragma unroll
+    for (int l = 1; l < DIM; ++l) {
+        const int so = g.stride[l] * 8;
+        Po[2 * l - 2] = buf_ld2(rP, vo - so, 0.0);
+        Ko[2 * l - 2] = buf_ld2(rK, vo - so, 0.0);
+        Po[2 * l - 1] = buf_ld2(rP, vo + so, 0.0);
+        Ko[2 * l - 1] = buf_ld2(rK, vo + so, 0.0);
+    }
+    const double pw[3] = {PX.x, PX.y, PX2}, kw[3] = {KX.x, KX.y, KX2};
+    PointEq e[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        const int i = ia + 2 * a;
+        const Stencil<DIM> sn = stencil_split<DIM>(g, i, (int)j, (int)k, idx + a, xl + a);
+        double Kn[2 * DIM], pn[2 * DIM];
+        Kn[0] = kw[a];
+        Kn[1] = kw[a + 1];
+        pn[0] = pw[a];
+        pn[1] = pw[a + 1];
+#pragma unroll
+        for (int o = 0; o < NO; ++o) {
+            Kn[2 + o] = a ? Ko[o].y : Ko[o].x;
+            pn[2 + o] = a ? Po[o].y : Po[o].x;
+        }
+        e[a] = ngs_reduce<SINK, DIM, false>(g, L, beta, lambdaU, sn, a ? KK.y : KK.x, Kn, pn,
+                                     a ? G2.y : G2.x, a ? P.y : P.x, i, (int)j, (int)k, colour);
+    }
+    const double xa = dir_a ? P.x : ngs_solve<MODEL, SINK>(g, L, st.a, e[0], P.x, idx);
+    __builtin_amdgcn_sched_barrier(0);
+    if (!has_b) {
+        buf_st(rP, vo, xa);
+        return;
+    }
+    const double xb = dir_b ? P.y : ngs_solve<MODEL, SINK>(g, L, st.a, e[1], P.y, idx + 1);
+    buf_st2(rP, vo, xa, xb);
 }
 
 // Whole sweeps of a tiny level in one work-group (the coarsest levels, where
@@ -873,6 +987,19 @@ bool fused_enabled()
     return e && strcmp(e, "fused") == 0;
 }
 
+// Two nodes per lane in the colour sweeps of the large buffer-path levels
+// (at least 2^21 nodes: half as many lanes still fill the chip, and the lane's
+// two solves in sequence cost more than they save on small levels, whose
+// sweeps are latency-bound); RS_SWEEP=single keeps one node per lane on every
+// level, RS_SWEEP=pair takes two on every buffer-path level.
+bool pair_sweep_level(const Geo &g)
+{
+    const char *e = getenv("RS_SWEEP");
+    if (e && strcmp(e, "single") == 0) return false;
+    if (e && strcmp(e, "pair") == 0) return true;
+    return g.N >= (1ll << 21);
+}
+
 FusedMap fused_map(const Geo &g)
 {
     FusedMap m;
@@ -913,6 +1040,18 @@ struct SweepLaunch {
         ColourMap cm = colour_map(g);
         dim3 grid(xcd_grid((cm.total + 255) / 256));
         const bool buf = buffer_ok(g, sizeof(double));
+        if (buf && law.kappa_rule != kKappaRemark && pair_sweep_level(g)) {
+            ColourMap pm = cm;
+            pm.H = (cm.H + 1) / 2;
+            pm.dH = make_fastdiv(pm.H);
+            pm.total = (unsigned long long)pm.H * g.n[1] * g.n[2];
+            dim3 pgrid(xcd_grid((pm.total + 255) / 256));
+            for (int sw = 0; sw < nsweeps; ++sw)
+                for (int colour = 0; colour < 2; ++colour)
+                    hipLaunchKernelGGL((k_sweep_pair<M, S, D>), pgrid, dim3(256), 0, s, g, law, st,
+                                       beta, lambdaU, K, gvec, *psi, colour, pm);
+            return;
+        }
         for (int sw = 0; sw < nsweeps; ++sw)
             for (int colour = 0; colour < 2; ++colour) {
                 if (buf)

@@ -1,0 +1,93 @@
+"""The two-nodes-per-lane colour sweep (k_sweep_pair) on every level.
+
+By default the library takes it on levels of at least 2^21 nodes only (the
+257^3 block's two finest levels, the root box); RS_SWEEP=pair sends every
+buffer-path level to it, so the parity cases of test_gpu_parity.py exercise
+it on 1-D, 2-D and 3-D levels with ragged half-rows (odd and even n0),
+Dirichlet nodes on either lane of a pair, sinks and layered media.  Each
+sweep is checked against the oracle's red-black sweep from identical inputs
+(1e-12, as for the one-node sweep), and against the one-node sweep
+(RS_SWEEP=single), which makes the same per-node arithmetic: the compiler may
+contract multiply-adds differently in the two kernels, so they agree to a few
+units in the last place.  The Remark's kappa rule always takes the one-node
+sweep.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2606_04292_amd as rsl
+from tests.test_gpu_parity import CASES, NAMES, TOL_SWEEP, advance, np_, rel, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def _sweep_all_levels(torch, w, pn, pm, mode, monkeypatch):
+    monkeypatch.setenv("RS_SWEEP", mode)
+    S = oracle.Solver(w, oracle.ORDER_RB)
+    S.set_state(pn, pm, 1)
+    S.begin_step()
+    G = rsl.Grid(w)
+    G.set_state(torch.as_tensor(pn), torch.as_tensor(pm), nstep=1)
+    G.begin_step()
+    rng = np.random.default_rng(11)
+    out = []
+    for lev in range(S.nlev):
+        kinds = S.kinds(lev).astype(bool)
+        psi = S.psi(lev)
+        psi = np.where(kinds, psi, psi + rng.uniform(-0.05, 0.05, size=psi.shape))
+        S.set(oracle.FIELD_PSI, psi, lev)
+        G.set_field(rsl.FIELD_PSI, torch.as_tensor(psi), lev)
+        G.set_field(rsl.FIELD_KSTAR, torch.as_tensor(S.get(oracle.FIELD_KSTAR, lev)), lev)
+        G.set_field(rsl.FIELD_G, torch.as_tensor(S.get(oracle.FIELD_G, lev)), lev)
+        S.sweep(2, lev)
+        G.sweep(2, lev)
+        got = np_(G.psi(lev))
+        out.append(got)
+        e = rel(got, S.psi(lev))
+        say("  %s level" % mode, lev, "shape", S.shapes[lev], "rel", e)
+        assert e <= TOL_SWEEP, (mode, lev, e)
+    G.close()
+    return out
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_pair_sweep_matches_oracle_and_one_node_sweep(torch_cuda, name, monkeypatch):
+    w = CASES[name]
+    say("pair sweep", name, w.grid.n)
+    pn, pm = advance(w, 1)
+    pair = _sweep_all_levels(torch_cuda, w, pn, pm, "pair", monkeypatch)
+    single = _sweep_all_levels(torch_cuda, w, pn, pm, "single", monkeypatch)
+    for lev, (a, b) in enumerate(zip(pair, single)):
+        assert np.abs(a - b).max() <= 8 * np.finfo(np.float64).eps * np.abs(b).max(), lev
+
+
+def test_pair_sweep_vcycle_and_step(torch_cuda, monkeypatch):
+    """A converged step of the shrunken drainage block with the pair sweep on
+    every level equals the oracle's step (1e-10)."""
+    torch = torch_cuda
+    from paper_2606_04292_amd import workloads as W
+    monkeypatch.setenv("RS_SWEEP", "pair")
+    w = W.shrink(W.config3(), 33)
+    pn, pm = advance(w, 2)
+    G = rsl.Grid(w)
+    G.set_state(torch.as_tensor(pn), torch.as_tensor(pm), nstep=2)
+    opts = rsl.solve_opts(w.nu1, w.nu2, w.nu_coarse, max_cycles=200, tol_abs=0.0, stagnation=1)
+    code, st = G.bdf_step(opts=opts)
+    assert code == rsl.RS_OK, rsl.lib().rs_last_error()
+    S = oracle.Solver(w, oracle.ORDER_RB)
+    S.set_state(pn, pm, 2)
+    S.begin_step()
+    oracle.solve_to_floor(S, 400, 0.0)
+    S.end_step()
+    e = rel(np_(G.get_state()[0]), S.get(oracle.FIELD_PSI_N))
+    say("pair sweep step: cycles", st.cycles, "rel", e)
+    assert e <= 1e-10, e
+    G.close()
