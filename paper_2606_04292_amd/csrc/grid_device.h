@@ -74,6 +74,20 @@ inline ColourMap colour_map(const Geo &g)
     return m;
 }
 
+// Slots of the pair kernels of a level with parity-split rows: xh per row
+// (position m of the even half, with the even node after it and the odd
+// node between them), rows over axes 1 and 2.
+inline ColourMap pair_map(const Geo &g)
+{
+    ColourMap m;
+    m.H = (unsigned)g.xh;
+    m.dH = make_fastdiv(m.H);
+    m.n1 = (unsigned)g.n[1];
+    m.dN1 = make_fastdiv(m.n1);
+    m.total = (unsigned long long)m.H * g.n[1] * g.n[2];
+    return m;
+}
+
 // Memory position of node i within its row (see Geo::xs): i itself, or with
 // the row split by parity (i >> 1) + (i & 1) xh.  Defined for i = -1 and
 // i = n0 too (a row's neighbouring value, or the padding around an array).

@@ -2,6 +2,9 @@
 // FP32 level data.
 #pragma once
 
+#include <stdlib.h>
+#include <string.h>
+
 #include "rs_internal.h"
 #include "soil_device.h"
 #include "grid_device.h"
@@ -248,10 +251,239 @@ __global__ __launch_bounds__(256) void k_prolong(Geo gf, Geo gc, const T *psi_c,
     }
 }
 
+// Levels with parity-split rows (Geo::xs = 1 on both levels): one thread per
+// coarse pair (2m, 2m + 1) of a row.  Their fine centres 4m and 4m + 2 are
+// the even positions 2m, 2m + 1 of a fine row, their odd taps 4m - 1 .. 4m + 3
+// the odd positions 2m - 1 .. 2m + 1: per fine row a pair, a pair and a single
+// load per array.  Each coarse node's sum is that of restrict_at.  Slots:
+// xh of the coarse level per row.
+template <int DIM, typename T>
+__global__ __launch_bounds__(256) void k_restrict_pair(Geo gc, Geo gf, const T *psi_f,
+                                                       const T *d_f, T *psibar_c, T *g_c,
+                                                       ColourMap cm)
+{
+    const unsigned long long t =
+        (unsigned long long)xcd_block(gridDim.x / 8u) * blockDim.x + threadIdx.x;
+    if (t >= cm.total) return;
+    const unsigned row = udiv((unsigned)t, cm.dH);
+    const int m = (int)((unsigned)(t - (unsigned long long)row * cm.H));
+    int J1 = 0, J2 = 0;
+    if (DIM == 3) {
+        J2 = (int)udiv(row, cm.dN1);
+        J1 = (int)row - J2 * (int)cm.n1;
+    } else if (DIM == 2) {
+        J1 = (int)row;
+    }
+    const bool has_b = 2 * m + 1 < gc.n[0];
+    const int F1 = 2 * J1, F2 = 2 * J2;
+    // fine row offsets of the taps along axes 1 and 2 (mirrored at the ends)
+    long long ro[3][3];
+#pragma unroll
+    for (int l = 1; l < 3; ++l) {
+        const int F = l == 1 ? F1 : F2;
+        const int n = gf.n[l];
+        const int lo = F == 0 ? 1 : F - 1, hi = F == n - 1 ? n - 2 : F + 1;
+        const long long st = gf.stride[l];
+        ro[l][0] = (long long)lo * st;
+        ro[l][1] = (long long)F * st;
+        ro[l][2] = (long long)hi * st;
+    }
+    const long long ce = 2 * m, od = gf.xh + 2 * m - 1;   // even pair, odd window
+    const T wt[3] = {T(0.25), T(0.5), T(0.25)};
+    T sp[2] = {T(0), T(0)}, sd[2] = {T(0), T(0)};
+    T pin[2] = {T(0), T(0)};   // fine values at the centres of the middle row
+    // all rows of taps in flight together (one plane at a time was slower:
+    // 102 against 71 us for the FP64 restriction at 129^3)
+#pragma unroll
+    for (int o2 = 0; o2 < (DIM > 2 ? 3 : 1); ++o2) {
+        const T w2 = DIM > 2 ? wt[o2] : T(1);
+        const long long b2 = DIM > 2 ? ro[2][o2] : 0;
+#pragma unroll
+        for (int o1 = 0; o1 < (DIM > 1 ? 3 : 1); ++o1) {
+            const T w1 = DIM > 1 ? wt[o1] : T(1);
+            const long long b1 = b2 + (DIM > 1 ? ro[1][o1] : 0);
+            const auto pc = load_pair(psi_f + b1 + ce), dc = load_pair(d_f + b1 + ce);
+            const auto po = load_pair(psi_f + b1 + od), dq = load_pair(d_f + b1 + od);
+            const T po2 = psi_f[b1 + od + 2], dq2 = d_f[b1 + od + 2];
+            if ((DIM < 3 || o2 == 1) && (DIM < 2 || o1 == 1)) {
+                pin[0] = pc.x;
+                pin[1] = pc.y;
+            }
+            // node a: taps 4m - 1, 4m, 4m + 1; node b: 4m + 1, 4m + 2, 4m + 3
+            const T pl[2] = {po.x, po.y}, pr[2] = {po.y, po2};
+            const T dl[2] = {dq.x, dq.y}, dr[2] = {dq.y, dq2};
+            const T pm[2] = {pc.x, pc.y}, dm[2] = {dc.x, dc.y};
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                const int F0 = 4 * m + 2 * a;
+                const bool first = F0 == 0, last = F0 == gf.n[0] - 1;
+                const T P3[3] = {first ? pr[a] : pl[a], pm[a], last ? pl[a] : pr[a]};
+                const T D3[3] = {first ? dr[a] : dl[a], dm[a], last ? dl[a] : dr[a]};
+#pragma unroll
+                for (int o0 = 0; o0 < 3; ++o0) {
+                    const T w = wt[o0] * w1 * w2;
+                    sp[a] += w * P3[o0];
+                    sd[a] += w * D3[o0];
+                }
+            }
+        }
+    }
+    const long long rc = (long long)J1 * gc.stride[1] + (long long)J2 * gc.stride[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        if (a == 1 && !has_b) break;
+        const int I0 = 2 * m + a;
+        const long long I = rc + (a ? gc.xh + m : m);
+        if (dirichlet_at(gc, I0, J1, J2, nullptr)) {
+            psibar_c[I] = pin[a];
+            g_c[I] = T(0);
+        } else {
+            psibar_c[I] = sp[a];
+            g_c[I] = sd[a];
+        }
+    }
+}
+
+// Prolongation on levels with parity-split rows: one thread per coarse pair
+// slot m of a row.  Its coarse corners 2m, 2m + 1, 2m + 2 along axis 0 are the
+// even positions m, m + 1 (a pair) and the odd position m; the fine nodes
+// 4m .. 4m + 3 it updates are the even positions 2m, 2m + 1 and the odd
+// positions 2m, 2m + 1 (a pair each).  Fine node 4m + 2a + b takes the taps
+// (2m + a, 2m + a + 1) with weights (1, 0) for b = 0 and (1/2, 1/2) for b = 1,
+// as in k_prolong, summed in the same order.  A pair is stored as a pair only
+// when both of its nodes lie in the row (a Dirichlet node of it gets its own
+// value back: no other thread writes it).
+template <int DIM, typename T, bool FULL = false>
+__global__ __launch_bounds__(256) void k_prolong_pair(Geo gf, Geo gc, const T *psi_c,
+                                                      const T *psibar_c, T *psi_f, ColourMap cm)
+{
+    const unsigned long long t =
+        (unsigned long long)xcd_block(gridDim.x / 8u) * blockDim.x + threadIdx.x;
+    if (t >= cm.total) return;
+    const unsigned row = udiv((unsigned)t, cm.dH);
+    const int m = (int)((unsigned)(t - (unsigned long long)row * cm.H));
+    int Ic[3] = {0, 0, 0};
+    if (DIM == 3) {
+        Ic[2] = (int)udiv(row, cm.dN1);
+        Ic[1] = (int)row - Ic[2] * (int)cm.n1;
+    } else if (DIM == 2) {
+        Ic[1] = (int)row;
+    }
+    long long co[3][2];
+#pragma unroll
+    for (int l = 1; l < 3; ++l) {
+        const int lo = Ic[l];
+        const int hi = lo + 1 < gc.n[l] ? lo + 1 : lo;
+        co[l][0] = (long long)lo * gc.stride[l];
+        co[l][1] = (long long)hi * gc.stride[l];
+    }
+    constexpr int N2 = DIM > 2 ? 2 : 1, N1 = DIM > 1 ? 2 : 1;
+    // E at coarse 2m, 2m + 1, 2m + 2 (the last past the row's end when 2m + 2
+    // >= n0: weight 0 or no fine node)
+    T E[N2][N1][3];
+#pragma unroll
+    for (int q2 = 0; q2 < N2; ++q2)
+#pragma unroll
+        for (int q1 = 0; q1 < N1; ++q1) {
+            const long long J = (DIM > 2 ? co[2][q2] : 0) + (DIM > 1 ? co[1][q1] : 0);
+            const auto ce = load_pair(psi_c + J + m);
+            const T c1 = psi_c[J + gc.xh + m];
+            if (FULL) {
+                E[q2][q1][0] = ce.x;
+                E[q2][q1][1] = c1;
+                E[q2][q1][2] = ce.y;
+            } else {
+                const auto be = load_pair(psibar_c + J + m);
+                const T b1 = psibar_c[J + gc.xh + m];
+                E[q2][q1][0] = ce.x - be.x;
+                E[q2][q1][1] = c1 - b1;
+                E[q2][q1][2] = ce.y - be.y;
+            }
+        }
+    const int n0 = gf.n[0];
+#pragma unroll
+    for (int a2 = 0; a2 < N2; ++a2) {
+        const int f2 = 2 * Ic[2] + a2;
+        if (f2 >= gf.n[2]) continue;
+#pragma unroll
+        for (int a1 = 0; a1 < N1; ++a1) {
+            const int f1 = 2 * Ic[1] + a1;
+            if (f1 >= gf.n[1]) continue;
+            const long long fr = (long long)f1 * gf.stride[1] + (long long)f2 * gf.stride[2];
+            // fine 4m + 2a + b at position (b ? xh : 0) + 2m + a; the old
+            // values are kept at Dirichlet nodes (also under FULL)
+            T v[2][2];   // [b][a]
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const auto o = load_pair(psi_f + fr + (b ? gf.xh : 0) + 2 * m);
+                v[b][0] = o.x;
+                v[b][1] = o.y;
+            }
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                bool in[2];
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    const int f0 = 4 * m + 2 * a + b;
+                    in[a] = f0 < n0;
+                    if (!in[a] || dirichlet_at(gf, f0, f1, f2, nullptr)) continue;
+                    const T w0[2] = {b ? T(0.5) : T(1), b ? T(0.5) : T(0)};
+                    const T w1[2] = {a1 ? T(0.5) : T(1), a1 ? T(0.5) : T(0)};
+                    const T w2[2] = {a2 ? T(0.5) : T(1), a2 ? T(0.5) : T(0)};
+                    T e = T(0);
+#pragma unroll
+                    for (int q2 = 0; q2 < N2; ++q2)
+#pragma unroll
+                        for (int q1 = 0; q1 < N1; ++q1)
+#pragma unroll
+                            for (int q0 = 0; q0 < 2; ++q0)
+                                e += w0[q0] * (DIM > 1 ? w1[q1] : T(1)) *
+                                     (DIM > 2 ? w2[q2] : T(1)) * E[q2][q1][a + q0];
+                    v[b][a] = FULL ? e : v[b][a] + e;
+                }
+                const long long p = fr + (b ? gf.xh : 0) + 2 * m;
+                if (in[1]) {
+                    store_pair(psi_f + p, v[b][0], v[b][1]);
+                } else if (in[0]) {
+                    psi_f[p] = v[b][0];
+                }
+            }
+        }
+    }
+}
+
+// The pair transfers pay on coarse levels of at least 2^18 nodes (on smaller
+// ones, latency-bound, they were slower).  Measured at 129^3, us per launch,
+// one node per lane -> pairs: FP64 restriction 86.4 -> 71.4, prolongation
+// 72.5 -> 53.8; FP32 62.9 -> 34.0 and 29.6 -> 26.6.  RS_TRANSFER=pair takes
+// them on every level with split rows, RS_TRANSFER=single on none.
+inline bool pair_transfer(const Geo &gc, const Geo &gf)
+{
+    if (gc.xs != 1 || gf.xs != 1) return false;
+    const char *e = getenv("RS_TRANSFER");
+    if (e && strcmp(e, "pair") == 0) return true;
+    if (e && strcmp(e, "single") == 0) return false;
+    return gc.N >= (1ll << 18);
+}
+
 template <typename T>
 inline void launch_restrict_t(const Geo &gc, const Geo &gf, const T *psi_f, const T *d_f,
                               T *psibar_c, T *g_c, hipStream_t s)
 {
+    if (pair_transfer(gc, gf)) {
+        const ColourMap cm = pair_map(gc);
+        const dim3 pg(xcd_grid((cm.total + 255) / 256));
+        if (gc.dim == 1)
+            hipLaunchKernelGGL((k_restrict_pair<1, T>), pg, dim3(256), 0, s, gc, gf, psi_f, d_f,
+                               psibar_c, g_c, cm);
+        else if (gc.dim == 2)
+            hipLaunchKernelGGL((k_restrict_pair<2, T>), pg, dim3(256), 0, s, gc, gf, psi_f, d_f,
+                               psibar_c, g_c, cm);
+        else
+            hipLaunchKernelGGL((k_restrict_pair<3, T>), pg, dim3(256), 0, s, gc, gf, psi_f, d_f,
+                               psibar_c, g_c, cm);
+        return;
+    }
     const dim3 grid(xcd_grid(((unsigned long long)gc.N + 255) / 256));
     const NodeMap nm = node_map(gc);
     if (gc.dim == 1)
@@ -266,6 +498,20 @@ template <typename T, bool FULL = false>
 inline void launch_prolong_t(const Geo &gf, const Geo &gc, const T *psi_c, const T *psibar_c,
                              T *psi_f, hipStream_t s)
 {
+    if (pair_transfer(gc, gf)) {
+        const ColourMap cm = pair_map(gc);
+        const dim3 pg(xcd_grid((cm.total + 255) / 256));
+        if (gf.dim == 1)
+            hipLaunchKernelGGL((k_prolong_pair<1, T, FULL>), pg, dim3(256), 0, s, gf, gc, psi_c,
+                               psibar_c, psi_f, cm);
+        else if (gf.dim == 2)
+            hipLaunchKernelGGL((k_prolong_pair<2, T, FULL>), pg, dim3(256), 0, s, gf, gc, psi_c,
+                               psibar_c, psi_f, cm);
+        else
+            hipLaunchKernelGGL((k_prolong_pair<3, T, FULL>), pg, dim3(256), 0, s, gf, gc, psi_c,
+                               psibar_c, psi_f, cm);
+        return;
+    }
     const dim3 grid(xcd_grid(((unsigned long long)gc.N + 255) / 256));
     const NodeMap nm = node_map(gc);
     if (gf.dim == 1)

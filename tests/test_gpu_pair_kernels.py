@@ -1,4 +1,7 @@
-"""The two-nodes-per-lane colour sweep (k_sweep_pair) on every level.
+"""The kernels that take two nodes per lane, on every level.
+
+The colour sweep (k_sweep_pair) and the grid transfers by coarse pairs
+(k_restrict_pair, k_prolong_pair) run by default on large levels only.
 
 By default the library takes it on levels of at least 2^21 nodes only (the
 257^3 block's two finest levels, the root box); RS_SWEEP=pair sends every
@@ -10,14 +13,17 @@ sweep is checked against the oracle's red-black sweep from identical inputs
 (RS_SWEEP=single), which makes the same per-node arithmetic: the compiler may
 contract multiply-adds differently in the two kernels, so they agree to a few
 units in the last place.  The Remark's kappa rule always takes the one-node
-sweep.
+sweep.  RS_TRANSFER=pair sends every level with parity-split rows to the pair
+transfers: V-cycles (FP64 restriction and prolongation), FMG (the
+interpolation that assigns) and mixed-precision steps (FP32 transfers) are
+compared with the oracle as in the other parity tests.
 """
 import numpy as np
 import pytest
 
 import oracle
 import paper_2606_04292_amd as rsl
-from tests.test_gpu_parity import CASES, NAMES, TOL_SWEEP, advance, np_, rel, say
+from tests.test_gpu_parity import CASES, FLOOR_CYCLES, NAMES, TOL_SWEEP, advance, np_, rel, say
 
 pytestmark = pytest.mark.gpu
 
@@ -90,4 +96,61 @@ def test_pair_sweep_vcycle_and_step(torch_cuda, monkeypatch):
     e = rel(np_(G.get_state()[0]), S.get(oracle.FIELD_PSI_N))
     say("pair sweep step: cycles", st.cycles, "rel", e)
     assert e <= 1e-10, e
+    G.close()
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_pair_transfers_vcycle_and_fmg_parity(torch_cuda, name, monkeypatch):
+    """Two V-cycles, then one FMG cycle from the same start, with the pair
+    sweep and pair transfers on every level, against the oracle (1e-12)."""
+    torch = torch_cuda
+    monkeypatch.setenv("RS_SWEEP", "pair")
+    monkeypatch.setenv("RS_TRANSFER", "pair")
+    w = CASES[name]
+    say("pair transfers", name, w.grid.n)
+    pn, pm = advance(w, 1)
+    for mode in ("vcycle", "fmg"):
+        S = oracle.Solver(w, oracle.ORDER_RB)
+        S.set_state(pn, pm, 1)
+        S.begin_step()
+        G = rsl.Grid(w)
+        G.set_state(torch.as_tensor(pn), torch.as_tensor(pm), nstep=1)
+        G.begin_step()
+        for c in range(2 if mode == "vcycle" else 1):
+            if mode == "vcycle":
+                S.vcycle()
+                G.vcycle()
+            else:
+                S.fmg()
+                G.fmg()
+            e = rel(np_(G.psi()), S.psi())
+            say("  %s %d rel" % (mode, c), e)
+            assert e <= TOL_SWEEP, (mode, c, e)
+        G.close()
+
+
+MP_PAIR = ["c1_col4097", "c2_slice65", "c3_block33", "c4_root33x17", "st_vg33"]
+
+
+@pytest.mark.parametrize("name", [n for n in MP_PAIR if n in CASES])
+def test_pair_transfers_mixed_steps(torch_cuda, name, monkeypatch):
+    """Mixed-precision steps (FP32 correction cycles with the pair transfers
+    on every level) to the rounding floor against the FP64 oracle (1e-10)."""
+    monkeypatch.setenv("RS_SWEEP", "pair")
+    monkeypatch.setenv("RS_TRANSFER", "pair")
+    w = CASES[name]
+    say("pair transfers, mixed", name)
+    S = oracle.Solver(w, oracle.ORDER_RB)
+    G = rsl.Grid(w, precision=rsl.RS_MIXED)
+    opts = rsl.solve_opts(w.nu1, w.nu2, w.nu_coarse, max_cycles=FLOOR_CYCLES, tol_abs=0.0,
+                          stagnation=1, mp_inner_cycles=1)
+    for step in range(2):
+        S.begin_step()
+        oracle.solve_to_floor(S, FLOOR_CYCLES, 0.0)
+        S.end_step()
+        code, st = G.bdf_step(opts=opts)
+        assert code == rsl.RS_OK, rsl.lib().rs_last_error()
+        e = rel(np_(G.get_state()[0]), S.get(oracle.FIELD_PSI_N))
+        say("  step", step, "corrections", st.cycles, "rel", e)
+        assert e <= 1e-10, (step, e)
     G.close()
