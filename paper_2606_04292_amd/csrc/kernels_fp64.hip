@@ -359,6 +359,39 @@ __global__ __launch_bounds__(512) void k_sweep_fused(Geo g, Law L, Step st, cons
     }
 }
 
+// The update of unknown (i, j, k) at idx (axis-0 neighbours at xl, xl + 1),
+// its stencil gathered through raw buffer loads with 32-bit offsets
+// (off-row neighbours outside the level read 0 and have coefficient 0; the
+// axis-0 pair reads the padding at the row's end).
+template <int MODEL, bool SINK, int DIM>
+__device__ __forceinline__ void sweep_node_buf(const Geo &g, const Law &L, double a,
+                                               const double *beta, double lambdaU,
+                                               __amdgpu_buffer_rsrc_t rP, __amdgpu_buffer_rsrc_t rK,
+                                               __amdgpu_buffer_rsrc_t rG, int i, int j, int k,
+                                               long long idx, long long xl, int colour)
+{
+    const int vo = (int)idx * 8, vx = (int)xl * 8;
+    const Stencil<DIM> sn = stencil_split<DIM>(g, i, j, k, idx, xl);
+    const double Ki = buf_ld<double>(rK, vo), x0 = buf_ld<double>(rP, vo);
+    const double f = buf_ld<double>(rG, vo);
+    double Kn[2 * DIM], pn[2 * DIM];
+    const v2f64 kx = buf_ld2(rK, vx, 0.0), px = buf_ld2(rP, vx, 0.0);
+    Kn[0] = kx.x;
+    Kn[1] = kx.y;
+    pn[0] = px.x;
+    pn[1] = px.y;
+#pragma unroll
+    for (int l = 1; l < DIM; ++l) {
+        const int so = g.stride[l] * 8;
+        Kn[2 * l] = buf_ld<double>(rK, vo - so);
+        pn[2 * l] = buf_ld<double>(rP, vo - so);
+        Kn[2 * l + 1] = buf_ld<double>(rK, vo + so);
+        pn[2 * l + 1] = buf_ld<double>(rP, vo + so);
+    }
+    buf_st(rP, vo, ngs_point<MODEL, SINK, DIM>(g, L, a, beta, lambdaU, sn, Ki, Kn, pn, f, x0, i, j,
+                                               k, idx, colour));
+}
+
 // One colour of a red-black sweep, one node per lane.  BUF (levels whose
 // arrays stay below 2 GiB): the stencil is gathered through raw buffer loads
 // with 32-bit offsets (off-row neighbours outside the level read 0 and have
@@ -391,28 +424,9 @@ __global__ __launch_bounds__(256) void k_sweep(Geo g, Law L, Step st, const doub
     const long long xl = rb + ih + (par ? 0 : g.xh - 1);
     if constexpr (BUF) {
         const long long bytes = (g.N + 32) * (long long)sizeof(double);   // + padding
-        const __amdgpu_buffer_rsrc_t rP = buf_rsrc(psi, bytes), rK = buf_rsrc(K, bytes),
-                                     rG = buf_rsrc(gv, bytes);
-        const int vo = (int)idx * 8, vx = (int)xl * 8;
-        const Stencil<DIM> sn = stencil_split<DIM>(g, i, (int)j, (int)k, idx, xl);
-        const double Ki = buf_ld<double>(rK, vo), x0 = buf_ld<double>(rP, vo);
-        const double f = buf_ld<double>(rG, vo);
-        double Kn[2 * DIM], pn[2 * DIM];
-        const v2f64 kx = buf_ld2(rK, vx, 0.0), px = buf_ld2(rP, vx, 0.0);
-        Kn[0] = kx.x;
-        Kn[1] = kx.y;
-        pn[0] = px.x;
-        pn[1] = px.y;
-#pragma unroll
-        for (int l = 1; l < DIM; ++l) {
-            const int so = g.stride[l] * 8;
-            Kn[2 * l] = buf_ld<double>(rK, vo - so);
-            pn[2 * l] = buf_ld<double>(rP, vo - so);
-            Kn[2 * l + 1] = buf_ld<double>(rK, vo + so);
-            pn[2 * l + 1] = buf_ld<double>(rP, vo + so);
-        }
-        buf_st(rP, vo, ngs_point<MODEL, SINK, DIM>(g, L, st.a, beta, lambdaU, sn, Ki, Kn, pn, f, x0,
-                                                   i, (int)j, (int)k, idx, colour));
+        sweep_node_buf<MODEL, SINK, DIM>(g, L, st.a, beta, lambdaU, buf_rsrc(psi, bytes),
+                                         buf_rsrc(K, bytes), buf_rsrc(gv, bytes), i, (int)j,
+                                         (int)k, idx, xl, colour);
     } else {
         ngs_cell_at<MODEL, SINK, DIM>(g, L, st.a, beta, lambdaU, K, gv, psi, i, (int)j, (int)k, idx,
                                       xl, colour);
@@ -502,6 +516,176 @@ __global__ __launch_bounds__(256) void k_sweep_pair(Geo g, Law L, Step st, const
     }
     const double xb = dir_b ? P.y : ngs_solve<MODEL, SINK>(g, L, st.a, e[1], P.y, idx + 1);
     buf_st2(rP, vo, xa, xb);
+}
+
+// One colour of a red-black sweep of a 3-D level, marching along axis 2 with
+// the other colour staged in LDS.  A work-group owns kZmRows rows (axis 1) x
+// 128 positions (one segment of the colour's half-rows) x zc planes; lane q of
+// row ly updates positions 2q and 2q + 1 of the segment.  Every stencil
+// neighbour of a node is of the other colour: its axis-0 neighbours sit in the
+// other half of its own row, its axis-1 and axis-2 neighbours at its own
+// position in the other-colour half of the adjacent rows.  The LDS ring holds,
+// for the planes z - 1, z, z + 1, the other-colour psi and K* of the rows
+// j0 - 1 .. j0 + kZmRows over positions -1 .. 128 of the segment, filled with
+// coalesced loads; plane z + 2 (and the node's own psi, K*, g of plane z + 1)
+// are loaded into registers while plane z is solved.  Each value of the other
+// colour is fetched from memory about 1.5 times (rows of the halo), not 6.
+// Half-rows of 128 s or 128 s + 1 positions only (n0 = 256 s or 256 s + 1):
+// the one position past the last segment (the node n0 - 1) is updated after
+// the march by the last segment's group, from global memory.  The per-node
+// arithmetic is that of k_sweep; kappa CONST or REL.
+constexpr int kZmRows = 4;
+constexpr int kZmW = 132;   // LDS row: position -1 at index 1 (pairs 16-byte aligned)
+
+struct ZmMap {
+    int nsx, nsy, ncz, zc;   // segments, row stripes, plane chunks, planes per chunk
+    int nwg, per;            // work-groups, logical groups per XCD
+};
+
+template <int MODEL, bool SINK>
+__global__ __launch_bounds__(256) void k_sweep_zm(Geo g, Law L, Step st, const double *beta,
+                                                  const double *K, const double *gv, double *psi,
+                                                  int colour, ZmMap zm)
+{
+    __shared__ double sP[3][kZmRows + 2][kZmW], sK[3][kZmRows + 2][kZmW];
+    const unsigned b = xcd_block_dir((unsigned)zm.per, colour & 1);
+    if ((int)b >= zm.nwg) return;
+    const int sx = (int)b % zm.nsx;
+    const int rest = (int)b / zm.nsx;
+    const int sy = rest % zm.nsy, cz = rest / zm.nsy;
+    const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
+    const int xh = g.xh;
+    const int j0 = sy * kZmRows, z0 = cz * zm.zc, z1 = min(z0 + zm.zc, n2);
+    const int tid = threadIdx.x, ly = tid >> 6, q = tid & 63;
+    const int j = j0 + ly;
+    const int p0 = 128 * sx;   // first position of the segment
+    const long long bytes = (g.N + 32) * (long long)sizeof(double);
+    const __amdgpu_buffer_rsrc_t rP = buf_rsrc(psi, bytes), rK = buf_rsrc(K, bytes),
+                                 rG = buf_rsrc(gv, bytes);
+    const long long s1 = g.stride[1], s2 = g.stride[2];
+
+    // halo element f < (kZmRows + 2) * 130 of plane z: row j0 - 1 + f / 130,
+    // position p0 - 1 + f % 130 of that row's other-colour half
+    constexpr int NF = (kZmRows + 2) * 130, NU = (NF + 255) / 256;
+    auto fetch = [&](int z, double *vp, double *vk) {
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            const int f = tid + 256 * u;
+            const int rr = f / 130, e = f - rr * 130;
+            const int jj = j0 - 1 + rr, pos = p0 - 1 + e;
+            const int par = (jj + z + colour + 1) & 1;   // other colour's parity of i in the row
+            const int len = par ? n0 - xh : xh;
+            double a = 0.0, c = 0.0;
+            if (f < NF && jj >= 0 && jj < n1 && z >= 0 && z < n2 && pos >= 0 && pos < len) {
+                const int off = (int)(((long long)jj * s1 + (long long)z * s2 + (par ? xh : 0) + pos) * 8);
+                a = buf_ld<double>(rP, off);
+                c = buf_ld<double>(rK, off);
+            }
+            vp[u] = a;
+            vk[u] = c;
+        }
+    };
+    auto stash = [&](int slot, const double *vp, const double *vk) {
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            const int f = tid + 256 * u;
+            if (f < NF) {
+                const int rr = f / 130, e = f - rr * 130;
+                sP[slot][rr][e + 1] = vp[u];
+                sK[slot][rr][e + 1] = vk[u];
+            }
+        }
+    };
+    // own values (psi, K*, g pairs) of the lane's two nodes in plane z
+    auto own = [&](int z, v2f64 &P, v2f64 &KK, v2f64 &G2) {
+        if (j < n1 && z < n2) {
+            const int par = (j + z + colour) & 1;
+            const int vo = (int)(((long long)j * s1 + (long long)z * s2 + (par ? xh : 0) + p0 + 2 * q) * 8);
+            P = buf_ld2(rP, vo, 0.0);
+            KK = buf_ld2(rK, vo, 0.0);
+            G2 = buf_ld2(rG, vo, 0.0);
+        }
+    };
+
+    double vp[NU], vk[NU];
+    for (int z = z0 - 1; z <= z0 + 1; ++z) {
+        fetch(z, vp, vk);
+        stash((z + 3) % 3, vp, vk);
+    }
+    v2f64 P = {0.0, 0.0}, KK = {0.0, 0.0}, G2 = {0.0, 0.0};
+    own(z0, P, KK, G2);
+    __syncthreads();
+
+    for (int z = z0; z < z1; ++z) {
+        const bool more = z + 1 < z1;   // a next plane in the chunk
+        if (more) fetch(z + 2, vp, vk);
+        v2f64 Pn = P, Kn2 = KK, Gn = G2;
+        if (more) own(z + 1, Pn, Kn2, Gn);
+        if (j < n1) {
+            const int par = (j + z + colour) & 1;
+            const int ia = 2 * (p0 + 2 * q) + par;   // nodes ia and ia + 2
+            const bool dir_a = dirichlet_at(g, ia, j, z, nullptr);
+            const bool dir_b = dirichlet_at(g, ia + 2, j, z, nullptr);
+            if (!(dir_a && dir_b)) {
+                const int sm = (z + 2) % 3, sc = z % 3, sp = (z + 1) % 3;
+                PointEq e[2];
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    const int i = ia + 2 * a;
+                    // LDS index of position p0 - 1 + t is t + 1
+                    const int xo = 2 * q + par + a + 1, yo = 2 * q + a + 2;
+                    const Stencil<3> sn = stencil_split<3>(g, i, j, z, 0, 0);
+                    double Kn[6], pn[6];
+                    Kn[0] = sK[sc][ly + 1][xo];
+                    pn[0] = sP[sc][ly + 1][xo];
+                    Kn[1] = sK[sc][ly + 1][xo + 1];
+                    pn[1] = sP[sc][ly + 1][xo + 1];
+                    Kn[2] = sK[sc][ly][yo];
+                    pn[2] = sP[sc][ly][yo];
+                    Kn[3] = sK[sc][ly + 2][yo];
+                    pn[3] = sP[sc][ly + 2][yo];
+                    Kn[4] = sK[sm][ly + 1][yo];
+                    pn[4] = sP[sm][ly + 1][yo];
+                    Kn[5] = sK[sp][ly + 1][yo];
+                    pn[5] = sP[sp][ly + 1][yo];
+                    e[a] = ngs_reduce<SINK, 3, false>(g, L, beta, 0.0, sn, a ? KK.y : KK.x, Kn, pn,
+                                                      a ? G2.y : G2.x, a ? P.y : P.x, i, j, z,
+                                                      colour);
+                    // one node's twelve LDS values live at a time
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                const long long idx =
+                    (long long)j * s1 + (long long)z * s2 + (par ? xh : 0) + p0 + 2 * q;
+                const double xa = dir_a ? P.x : ngs_solve<MODEL, SINK>(g, L, st.a, e[0], P.x, idx);
+                const double xb =
+                    dir_b ? P.y : ngs_solve<MODEL, SINK>(g, L, st.a, e[1], P.y, idx + 1);
+                buf_st2(rP, (int)(idx * 8), xa, xb);
+            }
+        }
+        __syncthreads();                        // plane z - 1 no longer read
+        if (more) stash((z + 2) % 3, vp, vk);   // its slot takes plane z + 2
+        __syncthreads();
+        P = Pn;
+        KK = Kn2;
+        G2 = Gn;
+    }
+
+    // the node past the last segment (n0 - 1 when n0 = 256 s + 1)
+    if (sx == zm.nsx - 1) {
+        const int pe = 128 * zm.nsx;
+        for (int t = tid; t < kZmRows * (z1 - z0); t += 256) {
+            const int jj = j0 + (t % kZmRows), z = z0 + t / kZmRows;
+            if (jj >= n1) continue;
+            const int par = (jj + z + colour) & 1;
+            if (pe >= (par ? n0 - xh : xh)) continue;
+            const int i = 2 * pe + par;
+            if (dirichlet_at(g, i, jj, z, nullptr)) continue;
+            const long long rb = (long long)jj * s1 + (long long)z * s2;
+            sweep_node_buf<MODEL, SINK, 3>(g, L, st.a, beta, 0.0, rP, rK, rG, i, jj, z,
+                                           rb + pe + (par ? xh : 0), rb + pe + (par ? 0 : xh - 1),
+                                           colour);
+        }
+    }
 }
 
 // Whole sweeps of a tiny level in one work-group (the coarsest levels, where
@@ -1000,6 +1184,43 @@ bool pair_sweep_level(const Geo &g)
     return g.N >= (1ll << 21);
 }
 
+// The z-marching LDS sweep: 3-D levels whose rows are split by parity into
+// halves of 128 s and 128 s (+ 1) positions; planes per chunk from RS_ZM_ZC
+// (default 16).
+bool zm_level(const Geo &g)
+{
+    if (g.dim != 3 || g.xs != 1) return false;
+    const int lo = g.n[0] - g.xh, hi = g.xh;   // odd and even half lengths
+    return lo >= 128 && lo % 128 == 0 && hi - lo <= 1;
+}
+
+ZmMap zm_map(const Geo &g)
+{
+    ZmMap m;
+    m.zc = 16;
+    if (const char *e = getenv("RS_ZM_ZC")) {
+        const int v = atoi(e);
+        if (v >= 1 && v <= 64) m.zc = v;
+    }
+    m.nsx = (g.n[0] - g.xh) / 128;
+    m.nsy = (g.n[1] + kZmRows - 1) / kZmRows;
+    m.ncz = (g.n[2] + m.zc - 1) / m.zc;
+    m.nwg = m.nsx * m.nsy * m.ncz;
+    m.per = (m.nwg + 7) / 8;
+    return m;
+}
+
+// Opt-in (RS_SWEEP=zm): at 257^3 it takes 134 / 143 / 165 us per colour with
+// 8 / 16 / 32 planes per chunk against 91 us for k_sweep_pair.  The march
+// serialises a group's planes behind two barriers each, the lanes of a group
+// wait for its slowest Newton solve at every plane, and the 150 VGPRs it holds
+// (prefetched plane, own values, two stencils) leave 3 waves per SIMD.
+bool zm_enabled()
+{
+    const char *e = getenv("RS_SWEEP");
+    return e && strcmp(e, "zm") == 0;
+}
+
 FusedMap fused_map(const Geo &g)
 {
     FusedMap m;
@@ -1040,6 +1261,14 @@ struct SweepLaunch {
         ColourMap cm = colour_map(g);
         dim3 grid(xcd_grid((cm.total + 255) / 256));
         const bool buf = buffer_ok(g, sizeof(double));
+        if (D == 3 && buf && law.kappa_rule != kKappaRemark && zm_level(g) && zm_enabled()) {
+            const ZmMap zm = zm_map(g);
+            for (int sw = 0; sw < nsweeps; ++sw)
+                for (int colour = 0; colour < 2; ++colour)
+                    hipLaunchKernelGGL((k_sweep_zm<M, S>), dim3(8 * zm.per), dim3(256), 0, s, g,
+                                       law, st, beta, K, gvec, *psi, colour, zm);
+            return;
+        }
         if (buf && law.kappa_rule != kKappaRemark && pair_sweep_level(g)) {
             ColourMap pm = cm;
             pm.H = (cm.H + 1) / 2;

@@ -154,3 +154,88 @@ def test_pair_transfers_mixed_steps(torch_cuda, name, monkeypatch):
         say("  step", step, "corrections", st.cycles, "rel", e)
         assert e <= 1e-10, (step, e)
     G.close()
+
+
+def _slab(n, law_from, seed, smooth=False):
+    """A 3-D slab whose rows have 256 s + 1 nodes (the z-marching sweep's
+    shape): spacing 1/256 along every axis, Dirichlet bottom, no-flux elsewhere,
+    a start state drawn per node (or a smooth one: the injected coarse K* needs
+    it for the cycle to converge)."""
+    from paper_2606_04292_amd import workloads as W
+    h = 1.0 / 256
+    g = W.GridSpec(dim=3, n=list(n), L=[(m - 1) * h for m in n],
+                   face_bc=[W.BC_NOFLUX] * 4 + [W.BC_DIRICHLET, W.BC_NOFLUX],
+                   face_value=[0.0] * 4 + [-1.0, 0.0])
+    if smooth:
+        x = np.linspace(0.0, 1.0, n[0])
+        psi0 = np.broadcast_to(-1.0 + 0.4 * np.sin(np.pi * x), g.shape).copy()
+    else:
+        psi0 = -0.5 - 2.0 * np.random.default_rng(seed).random(g.shape)
+    base = law_from()
+    return W.Workload("slab_%dx%dx%d" % tuple(n), g, base.law, psi0, dt=base.dt, steps=3,
+                      order=2)
+
+
+SLABS = {
+    "hk_257x17x9": ((257, 17, 9), "config3", 1),
+    "vg_sink_257x17x9": ((257, 17, 9), "config4", 2),
+    "hk_513x9x9": ((513, 9, 9), "config3", 3),
+}
+
+
+@pytest.mark.parametrize("zc", ["16", "4"])
+@pytest.mark.parametrize("name", sorted(SLABS))
+def test_zm_sweep_matches_oracle_and_other_sweeps(torch_cuda, name, zc, monkeypatch):
+    """The z-marching LDS sweep (RS_SWEEP=zm) on slabs with a partial row
+    stripe, partial plane chunks (RS_ZM_ZC), one or two 128-position segments
+    and the node past the last segment: two sweeps on the finest level against
+    the oracle (1e-12) and against the pair and one-node sweeps (8 ulp)."""
+    from paper_2606_04292_amd import workloads as W
+    torch = torch_cuda
+    n, cfg, seed = SLABS[name]
+    w = _slab(n, getattr(W, cfg), seed)
+    monkeypatch.setenv("RS_ZM_ZC", zc)
+    pn = w.psi0.copy()
+    S = oracle.Solver(w, oracle.ORDER_RB)
+    S.set_state(pn, pn, 1)
+    S.begin_step()
+    S.sweep(2, 0)
+    ref = S.psi(0)
+    got = {}
+    for mode in ("zm", "pair", "single"):
+        monkeypatch.setenv("RS_SWEEP", mode)
+        G = rsl.Grid(w)
+        G.set_state(torch.as_tensor(pn), torch.as_tensor(pn), nstep=1)
+        G.begin_step()
+        G.sweep(2, 0)
+        got[mode] = np_(G.psi(0))
+        G.close()
+        e = rel(got[mode], ref)
+        say("  %s %s zc %s rel %.2e" % (name, mode, zc, e))
+        assert e <= TOL_SWEEP, (mode, e)
+    tol = 8 * np.finfo(np.float64).eps * np.abs(ref).max()
+    assert np.abs(got["zm"] - got["pair"]).max() <= tol
+    assert np.abs(got["zm"] - got["single"]).max() <= tol
+
+
+def test_zm_sweep_converged_steps(torch_cuda, monkeypatch):
+    """Two converged BDF steps of a slab with the z-marching sweep on its
+    finest level against the oracle (1e-10)."""
+    from paper_2606_04292_amd import workloads as W
+    monkeypatch.setenv("RS_SWEEP", "zm")
+    monkeypatch.setenv("RS_ZM_ZC", "4")
+    w = _slab((257, 17, 9), W.config3, 4, smooth=True)
+    S = oracle.Solver(w, oracle.ORDER_RB)
+    G = rsl.Grid(w)
+    opts = rsl.solve_opts(w.nu1, w.nu2, w.nu_coarse, max_cycles=FLOOR_CYCLES, tol_abs=0.0,
+                          stagnation=1)
+    for step in range(2):
+        S.begin_step()
+        oracle.solve_to_floor(S, FLOOR_CYCLES, 0.0)
+        S.end_step()
+        code, st = G.bdf_step(opts=opts)
+        assert code == rsl.RS_OK, rsl.lib().rs_last_error()
+        e = rel(np_(G.get_state()[0]), S.get(oracle.FIELD_PSI_N))
+        say("  zm step", step, "cycles", st.cycles, "rel", e)
+        assert e <= 1e-10, (step, e)
+    G.close()
