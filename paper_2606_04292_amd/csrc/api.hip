@@ -629,6 +629,15 @@ void vcycle32_level(rs_grid *G, int l, int nu1, int nu2)
 {
     LevelData &f = G->lev[l];
     const float a = (float)G->step.a;
+    if (l >= 1 && l >= G->tail_top && l < G->nlev - 1) {
+        // the rest of the correction cycle on small levels: one work-group
+        launch_vcycle_tail32(G->tail_dev, l, G->nlev - 1, G->law32, a, nu1, nu2, G->nu_coarse,
+                             G->desc.dim, G->stream);
+        for (int q = l; q < G->nlev - 1; ++q)
+            G->updates += (double)(nu1 + nu2) * (double)G->lev[q].unknowns;
+        G->updates += (double)G->nu_coarse * (double)G->lev[G->nlev - 1].unknowns;
+        return;
+    }
     if (l == G->nlev - 1) {
         sweep32_level(G, l, G->nu_coarse);
         return;
@@ -814,6 +823,13 @@ int grid_view(rs_grid *G, const rs_grid_desc *d, int precision, const Layout &L,
         T.psibar = v.psibar;
         T.beta = v.beta;
         T.lambdaU = 0.0;
+        T.dl = v.dl;
+        T.K32 = v.K32;
+        T.rhs32 = v.rhs32;
+        T.pb32 = v.pb32;
+        T.r32 = v.r32;
+        T.dbar32 = v.dbar32;
+        T.lambdaU32 = 0.0f;
     }
     HIPCALL(hipMemcpyAsync(G->tail_dev, G->tail_host, sizeof(TailArgs), hipMemcpyHostToDevice,
                            G->stream));
@@ -1037,6 +1053,7 @@ int rs_begin_step(rs_grid *G, double dt, int order)
             memcpy(&v, &G->host_bits[1 + l], sizeof v);
             G->lev[l].lambdaU = v;
             G->tail_host->lv[l].lambdaU = v;   // the stream is idle: the last copy is done
+            G->tail_host->lv[l].lambdaU32 = (float)v;
         }
         if (G->tail_top < G->nlev)
             HIPCALL(hipMemcpyAsync(G->tail_dev, G->tail_host, sizeof(TailArgs),

@@ -328,6 +328,29 @@ __device__ __forceinline__ bool colour_ijk(const Geo &g, const ColourMap &cm,
     return i < g.n[0];
 }
 
+// Colour slots and node order of a level of the one-work-group cycle.
+__device__ __forceinline__ ColourMap tail_cm(const TailLevel &T)
+{
+    ColourMap m;
+    m.total = (unsigned long long)T.cm_total;
+    m.H = T.H;
+    m.dH = FastDiv{T.dH_m, T.dH_s};
+    m.n1 = T.n1;
+    m.dN1 = FastDiv{T.dN1_m, T.dN1_s};
+    return m;
+}
+
+__device__ __forceinline__ NodeMap tail_nm(const TailLevel &T)
+{
+    NodeMap m;
+    m.n0 = T.n0;
+    m.n1 = T.nn1;
+    m.d0 = FastDiv{T.d0_m, T.d0_s};
+    m.d1 = FastDiv{T.d1_m, T.d1_s};
+    m.xh = T.g.xh;
+    return m;
+}
+
 inline dim3 node_grid(const Geo &g)
 {
     return dim3((g.n[0] + kBX - 1) / kBX, (g.n[1] + kBY - 1) / kBY, g.n[2]);

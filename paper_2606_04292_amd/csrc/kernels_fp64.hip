@@ -718,28 +718,6 @@ __global__ __launch_bounds__(256) void k_sweep_small(Geo g, Law L, Step st, cons
 // with work-group barriers between the steps instead of launches.
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ ColourMap tail_cm(const TailLevel &T)
-{
-    ColourMap m;
-    m.total = (unsigned long long)T.cm_total;
-    m.H = T.H;
-    m.dH = FastDiv{T.dH_m, T.dH_s};
-    m.n1 = T.n1;
-    m.dN1 = FastDiv{T.dN1_m, T.dN1_s};
-    return m;
-}
-
-__device__ __forceinline__ NodeMap tail_nm(const TailLevel &T)
-{
-    NodeMap m;
-    m.n0 = T.n0;
-    m.n1 = T.nn1;
-    m.d0 = FastDiv{T.d0_m, T.d0_s};
-    m.d1 = FastDiv{T.d1_m, T.d1_s};
-    m.xh = T.g.xh;
-    return m;
-}
-
 template <int MODEL, bool SINK, int DIM>
 __device__ void tail_sweeps64(const TailLevel &T, const Law &L, double a, int n)
 {

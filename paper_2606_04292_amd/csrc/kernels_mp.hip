@@ -156,6 +156,88 @@ __global__ __launch_bounds__(256) void k_apply_delta(long long N, const float *d
     if (t < N) psi64[t] += (double)dl[t];
 }
 
+// FP32 red-black sweeps of one level inside the one-work-group cycle, with the
+// exit of k_sweep32_small (a sweep that moved no value by more than 4 FP32 ulp).
+template <int MODEL, bool SINK, int DIM>
+__device__ void tail_sweeps32(const TailLevel &T, const Law32 &L, float a, int n)
+{
+    const ColourMap cm = tail_cm(T);
+    for (int sw = 0; sw < n; ++sw) {
+        int changed = 0;
+        for (int colour = 0; colour < 2; ++colour) {
+            for (unsigned long long t = threadIdx.x; t < cm.total; t += blockDim.x) {
+                int i, j, k;
+                if (!colour_ijk(T.g, cm, t, colour, i, j, k)) continue;
+                if (dirichlet_at(T.g, i, j, k, nullptr)) continue;
+                changed |= ngs_cell32<MODEL, SINK, DIM, true, true>(T.g, L, a, T.beta, T.lambdaU32,
+                                                                    T.K32, T.rhs32, T.pb32, T.dl,
+                                                                    i, j, k, colour);
+            }
+            if (colour == 0) __syncthreads();
+            else if (!__syncthreads_or(changed)) return;
+        }
+    }
+}
+
+// The FP32 correction cycle from level top (all of whose levels hold at most
+// kTailNodes nodes) down to level last and back, in one work-group, with the
+// per-node arithmetic of the launched kernels: sweeps, inner defect
+// (k_residual32), full weighting of delta and of the defect, coarse
+// right-hand side (k_coarse_rhs32), the coarsest sweeps, prolongation.
+template <int MODEL, bool SINK, int DIM>
+__global__ __launch_bounds__(512) void k_vcycle_tail32(const TailArgs *A, int top, int last,
+                                                       Law32 L, float a, int nu1, int nu2, int nuc)
+{
+    __shared__ TailLevel SL[kMaxLevels];
+    for (int l = top + (int)threadIdx.x; l <= last; l += (int)blockDim.x) SL[l] = A->lv[l];
+    __syncthreads();
+    for (int l = top; l < last; ++l) {
+        const TailLevel &F = SL[l], &C = SL[l + 1];
+        tail_sweeps32<MODEL, SINK, DIM>(F, L, a, nu1);
+        const NodeMap nf = tail_nm(F), nc = tail_nm(C);
+        for (unsigned long long t = threadIdx.x; t < (unsigned long long)F.g.N; t += blockDim.x) {
+            int i, j, k;
+            node_ijk(nf, t, i, j, k);
+            float v = 0.0f;
+            if (!dirichlet_at(F.g, i, j, k, nullptr))
+                v = F.rhs32[t] - apply_Nd<MODEL, SINK, DIM, true>(F.g, L, a, F.beta, F.K32, F.pb32,
+                                                                   F.dl, i, j, k, (long long)t);
+            F.r32[t] = v;
+        }
+        __syncthreads();
+        for (unsigned long long t = threadIdx.x; t < (unsigned long long)C.g.N; t += blockDim.x) {
+            int i, j, k;
+            node_ijk(nc, t, i, j, k);
+            restrict_at<DIM, float, true>(C.g, F.g, F.dl, F.r32, C.dbar32, C.rhs32, i, j, k);
+        }
+        __syncthreads();
+        for (unsigned long long t = threadIdx.x; t < (unsigned long long)C.g.N; t += blockDim.x) {
+            int i, j, k;
+            node_ijk(nc, t, i, j, k);
+            if (!dirichlet_at(C.g, i, j, k, nullptr))
+                C.rhs32[t] = apply_Nd<MODEL, SINK, DIM, true>(C.g, L, a, C.beta, C.K32, C.pb32,
+                                                              C.dbar32, i, j, k, (long long)t) +
+                             C.rhs32[t];
+            C.dl[t] = C.dbar32[t];
+        }
+        __syncthreads();
+    }
+    tail_sweeps32<MODEL, SINK, DIM>(SL[last], L, a, nuc);
+    __syncthreads();
+    for (int l = last - 1; l >= top; --l) {
+        const TailLevel &F = SL[l], &C = SL[l + 1];
+        const NodeMap nf = tail_nm(F);
+        for (unsigned long long t = threadIdx.x; t < (unsigned long long)F.g.N; t += blockDim.x) {
+            int i, j, k;
+            node_ijk(nf, t, i, j, k);
+            prolong_at<DIM, float>(F.g, C.g, C.dl, C.dbar32, F.dl, i, j, k);
+        }
+        __syncthreads();
+        tail_sweeps32<MODEL, SINK, DIM>(F, L, a, nu2);
+        __syncthreads();
+    }
+}
+
 unsigned blocks_for(long long N) { return (unsigned)((N + 255) / 256); }
 
 struct Sweep32Launch {
@@ -255,6 +337,22 @@ void launch_sweep32(const Geo &g, const Law32 &law, float a, const double *beta,
     if (nsweeps <= 0) return;
     dispatch(dispatch_key(law), g.dim,
              Sweep32Launch{g, law, a, beta, lambdaU, K, rhs, pb, dl, nsweeps, s});
+}
+
+struct Tail32Launch {
+    const TailArgs *A; int top, last; const Law32 &law; float a; int nu1, nu2, nuc; hipStream_t s;
+    template <int M, bool S, int D>
+    void go()
+    {
+        hipLaunchKernelGGL((k_vcycle_tail32<M, S, D>), dim3(1), dim3(512), 0, s, A, top, last, law,
+                           a, nu1, nu2, nuc);
+    }
+};
+
+void launch_vcycle_tail32(const TailArgs *args_dev, int top, int last, const Law32 &law, float a,
+                          int nu1, int nu2, int nuc, int dim, hipStream_t s)
+{
+    dispatch(dispatch_key(law), dim, Tail32Launch{args_dev, top, last, law, a, nu1, nu2, nuc, s});
 }
 
 void launch_residual32(const Geo &g, const Law32 &law, float a, const double *beta, const float *K,

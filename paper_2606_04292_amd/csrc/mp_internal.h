@@ -22,5 +22,9 @@ void launch_prolong32(const Geo &gf, const Geo &gc, const float *dl_c, const flo
 void launch_inject32(const Geo &gc, const Geo &gf, const float *vf, float *vc, hipStream_t s);
 void launch_to_f32(long long N, const double *src, float *dst, hipStream_t s);
 void launch_apply_delta(long long N, const float *dl, double *psi64, hipStream_t s);
+// The FP32 correction cycle from level top (all of whose levels hold at most
+// kTailNodes nodes) down to level last and back, in one work-group.
+void launch_vcycle_tail32(const TailArgs *args_dev, int top, int last, const Law32 &law, float a,
+                          int nu1, int nu2, int nuc, int dim, hipStream_t s);
 
 }  // namespace rs

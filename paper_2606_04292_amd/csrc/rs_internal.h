@@ -90,6 +90,10 @@ struct TailLevel {
     double *psi, *K, *gv, *d, *psibar;
     const double *beta;
     double lambdaU;
+    // FP32 correction cycle (mixed grids; null otherwise): delta, K*, rhs,
+    // base state, inner defect, restricted delta
+    float *dl, *K32, *rhs32, *pb32, *r32, *dbar32;
+    float lambdaU32;
 };
 
 struct TailArgs {
