@@ -16,6 +16,60 @@ __device__ __forceinline__ int vert_index(int i, int j, int k)
     return (DIM == 1) ? i : (DIM == 2 ? j : k);
 }
 
+// The scalars of one unknown's correction problem: c = xi + kappa + m_ii, the
+// right-hand side f (rhs plus the neighbour couplings plus kappa delta_i) and
+// the root density.  cf: the stencil coefficients in FP32.  REMARK = false:
+// the caller has excluded the Remark's kappa rule.
+struct PointEq32 {
+    float c, f, bz;
+};
+
+template <bool SINK, int DIM, bool REMARK = true>
+__device__ __forceinline__ PointEq32 ngs_reduce32(const Geo &g, const Law32 &L, const double *beta,
+                                                  float lambdaU, const float *cf, float Ki,
+                                                  const float *Kn, const float *dn, float f,
+                                                  float d0, int i, int j, int k, int colour)
+{
+    float mii = 0.0f;
+#pragma unroll
+    for (int q = 0; q < 2 * DIM; ++q) {
+        const float m = cf[q] * (Ki + Kn[q]);
+        mii += m;
+        f += m * dn[q];
+    }
+    float kap;
+    if (L.kappa_rule == kKappaConst) {
+        kap = L.kappa;
+    } else if (!REMARK || L.kappa_rule == kKappaRel) {
+        kap = L.kappa * mii;
+    } else if (colour == 0) {
+        float usum = 0.0f;
+#pragma unroll
+        for (int q = 0; q < 2 * DIM; ++q) {
+            int d[3] = {i, j, k};
+            d[q >> 1] += (q & 1) ? 1 : -1;
+            if (cf[q] != 0.0f && !dirichlet_at(g, d[0], d[1], d[2], nullptr))
+                usum += cf[q] * (Ki + Kn[q]);
+        }
+        kap = lambdaU - usum;
+    } else {
+        kap = lambdaU;
+    }
+    PointEq32 e;
+    e.f = f + kap * d0;
+    e.c = L.xi + kap + mii;
+    e.bz = SINK ? (float)beta[vert_index<DIM>(i, j, k)] : 0.0f;
+    return e;
+}
+
+template <int MODEL, bool SINK>
+__device__ __forceinline__ float ngs_solve32(const Law32 &L, float a, const PointEq32 &e, float d0,
+                                             float pbi)
+{
+    const Base b = base_of<MODEL>(L, pbi);
+    return local_solve32<MODEL, SINK>(L, a, e.bz, e.c, e.f, b, d0);
+}
+
 // New delta of unknown (i, j, k) from gathered values: the stencil, K*_i, the
 // right-hand side f = rhs_i, the old delta d0, the base state pb, and the K*
 // and current delta of the 2 DIM neighbours.
@@ -26,36 +80,12 @@ __device__ __forceinline__ float ngs_point32(const Geo &g, const Law32 &L, float
                                              const float *dn, float f, float d0, float pbi, int i,
                                              int j, int k, int colour)
 {
-    float mii = 0.0f;
+    float cf[2 * DIM];
 #pragma unroll
-    for (int q = 0; q < 2 * DIM; ++q) {
-        const float m = (float)st.cf[q] * (Ki + Kn[q]);
-        mii += m;
-        f += m * dn[q];
-    }
-    float kap;
-    if (L.kappa_rule == kKappaConst) {
-        kap = L.kappa;
-    } else if (L.kappa_rule == kKappaRel) {
-        kap = L.kappa * mii;
-    } else if (colour == 0) {
-        float usum = 0.0f;
-#pragma unroll
-        for (int q = 0; q < 2 * DIM; ++q) {
-            int d[3] = {i, j, k};
-            d[q >> 1] += (q & 1) ? 1 : -1;
-            if (st.cf[q] != 0.0 && !dirichlet_at(g, d[0], d[1], d[2], nullptr))
-                usum += (float)st.cf[q] * (Ki + Kn[q]);
-        }
-        kap = lambdaU - usum;
-    } else {
-        kap = lambdaU;
-    }
-    f += kap * d0;
-    const float c = L.xi + kap + mii;
-    const float bz = SINK ? (float)beta[vert_index<DIM>(i, j, k)] : 0.0f;
-    const Base b = base_of<MODEL>(L, pbi);
-    return local_solve32<MODEL, SINK>(L, a, bz, c, f, b, d0);
+    for (int q = 0; q < 2 * DIM; ++q) cf[q] = (float)st.cf[q];
+    const PointEq32 e =
+        ngs_reduce32<SINK, DIM>(g, L, beta, lambdaU, cf, Ki, Kn, dn, f, d0, i, j, k, colour);
+    return ngs_solve32<MODEL, SINK>(L, a, e, d0, pbi);
 }
 
 // New delta at unknown (i, j, k): f = rhs + sum_j m_ij delta_j + kappa delta_i,

@@ -76,6 +76,98 @@ __global__ __launch_bounds__(256) void k_sweep32(Geo g, Law32 L, float a, const 
     }
 }
 
+// One colour of the FP32 correction sweep, two nodes of that colour per lane
+// (half-row positions 2q and 2q + 1, nodes i and i + 2), as k_sweep_pair does
+// for FP64: own values one 8-byte load per array, each off-row direction one
+// pair, the axis-0 neighbours a pair and a single; the off-row stencil
+// coefficients are formed once for both nodes.  Both point problems are
+// reduced before the first solve.  Kappa CONST or REL.  Slots: (xh + 1) / 2
+// per row.
+template <int MODEL, bool SINK, int DIM>
+__global__ __launch_bounds__(256) void k_sweep32_pair(Geo g, Law32 L, float a, const double *beta,
+                                                      const float *K, const float *rhs,
+                                                      const float *pb, float *dl, int colour,
+                                                      ColourMap cm)
+{
+    const unsigned long long t =
+        (unsigned long long)xcd_block_dir(gridDim.x / 8u, colour & 1) * blockDim.x + threadIdx.x;
+    if (t >= cm.total) return;
+    const unsigned row = udiv((unsigned)t, cm.dH);
+    const int q = (int)((unsigned)(t - (unsigned long long)row * cm.H));
+    unsigned j = 0, k = 0;
+    if (DIM == 3) {
+        k = udiv(row, cm.dN1);
+        j = row - k * cm.n1;
+    } else if (DIM == 2) {
+        j = row;
+    }
+    const int par = (int)((j + k + colour) & 1);
+    const int len = par ? g.n[0] - g.xh : g.xh;
+    if (2 * q >= len) return;
+    const bool has_b = 2 * q + 1 < len;
+    const int ia = 4 * q + par;
+    const bool dir_a = dirichlet_at(g, ia, (int)j, (int)k, nullptr);
+    const bool dir_b = !has_b || dirichlet_at(g, ia + 2, (int)j, (int)k, nullptr);
+    if (dir_a && dir_b) return;
+    const long long rb = (long long)j * g.stride[1] + (long long)k * g.stride[2];
+    const long long idx = rb + (par ? g.xh : 0) + 2 * q;
+    const long long xl = rb + (par ? 0 : g.xh - 1) + 2 * q;
+    const long long bytes = (g.N + 64) * (long long)sizeof(float);   // + padding
+    const __amdgpu_buffer_rsrc_t rK = buf_rsrc(K, bytes), rR = buf_rsrc(rhs, bytes),
+                                 rB = buf_rsrc(pb, bytes), rD = buf_rsrc(dl, bytes);
+    const int vo = (int)idx * 4, vx = (int)xl * 4;
+    const v2f32 D = buf_ld2(rD, vo, 0.0f), KK = buf_ld2(rK, vo, 0.0f), R2 = buf_ld2(rR, vo, 0.0f),
+                B2 = buf_ld2(rB, vo, 0.0f);
+    const v2f32 DX = buf_ld2(rD, vx, 0.0f), KX = buf_ld2(rK, vx, 0.0f);
+    const float DX2 = buf_ld<float>(rD, vx + 8), KX2 = buf_ld<float>(rK, vx + 8);
+    constexpr int NO = 2 * (DIM - 1);
+    v2f32 Do[NO > 0 ? NO : 1], Ko[NO > 0 ? NO : 1];
+    float cfo[NO > 0 ? NO : 1];
+#pragma unroll
+    for (int l = 1; l < DIM; ++l) {
+        const int so = g.stride[l] * 4;
+        Do[2 * l - 2] = buf_ld2(rD, vo - so, 0.0f);
+        Ko[2 * l - 2] = buf_ld2(rK, vo - so, 0.0f);
+        Do[2 * l - 1] = buf_ld2(rD, vo + so, 0.0f);
+        Ko[2 * l - 1] = buf_ld2(rK, vo + so, 0.0f);
+        const int cl = l == 1 ? (int)j : (int)k;
+        const float cf = (float)(((cl == 0 || cl == g.n[l] - 1) ? 1.0 : 0.5) * g.ih2[l]);
+        cfo[2 * l - 2] = cl > 0 ? cf : 0.0f;
+        cfo[2 * l - 1] = cl < g.n[l] - 1 ? cf : 0.0f;
+    }
+    const float dw[3] = {DX.x, DX.y, DX2}, kw[3] = {KX.x, KX.y, KX2};
+    PointEq32 e[2];
+#pragma unroll
+    for (int a2 = 0; a2 < 2; ++a2) {
+        const int i = ia + 2 * a2;
+        float cf[2 * DIM], Kn[2 * DIM], dn[2 * DIM];
+        const float cx = (float)(((i == 0 || i == g.n[0] - 1) ? 1.0 : 0.5) * g.ih2[0]);
+        cf[0] = i > 0 ? cx : 0.0f;
+        cf[1] = i < g.n[0] - 1 ? cx : 0.0f;
+        Kn[0] = kw[a2];
+        Kn[1] = kw[a2 + 1];
+        dn[0] = dw[a2];
+        dn[1] = dw[a2 + 1];
+#pragma unroll
+        for (int o = 0; o < NO; ++o) {
+            cf[2 + o] = cfo[o];
+            Kn[2 + o] = a2 ? Ko[o].y : Ko[o].x;
+            dn[2 + o] = a2 ? Do[o].y : Do[o].x;
+        }
+        e[a2] = ngs_reduce32<SINK, DIM, false>(g, L, beta, 0.0f, cf, a2 ? KK.y : KK.x, Kn, dn,
+                                              a2 ? R2.y : R2.x, a2 ? D.y : D.x, i, (int)j, (int)k,
+                                              colour);
+    }
+    const float xa = dir_a ? D.x : ngs_solve32<MODEL, SINK>(L, a, e[0], D.x, B2.x);
+    if (!has_b) {
+        buf_st(rD, vo, xa);
+        return;
+    }
+    const float xb = dir_b ? D.y : ngs_solve32<MODEL, SINK>(L, a, e[1], D.y, B2.y);
+    const v2f32 out = {xa, xb};
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2i32, out), rD, vo, 0, 0);
+}
+
 template <int MODEL, bool SINK, int DIM>
 __global__ __launch_bounds__(256) void k_sweep32_small(Geo g, Law32 L, float a, const double *beta,
                                                        float lambdaU, const float *K,
@@ -240,6 +332,16 @@ __global__ __launch_bounds__(512) void k_vcycle_tail32(const TailArgs *A, int to
 
 unsigned blocks_for(long long N) { return (unsigned)((N + 255) / 256); }
 
+// Two nodes per lane in the FP32 sweeps of levels of at least 2^21 nodes
+// (RS_SWEEP32=single / pair: one on every level / two on every buffer level).
+bool pair32_level(const Geo &g)
+{
+    const char *e = getenv("RS_SWEEP32");
+    if (e && strcmp(e, "single") == 0) return false;
+    if (e && strcmp(e, "pair") == 0) return true;
+    return g.N >= (1ll << 21);
+}
+
 struct Sweep32Launch {
     const Geo &g; const Law32 &law; float a; const double *beta; float lambdaU; const float *K;
     const float *rhs; const float *pb; float *dl; int nsweeps; hipStream_t s;
@@ -254,6 +356,18 @@ struct Sweep32Launch {
         ColourMap cm = colour_map(g);
         dim3 grid(xcd_grid((cm.total + 255) / 256));
         const bool buf = buffer_ok(g, sizeof(float));
+        if (buf && law.kappa_rule != kKappaRemark && pair32_level(g)) {
+            ColourMap pm = cm;
+            pm.H = (cm.H + 1) / 2;
+            pm.dH = make_fastdiv(pm.H);
+            pm.total = (unsigned long long)pm.H * g.n[1] * g.n[2];
+            const dim3 pgrid(xcd_grid((pm.total + 255) / 256));
+            for (int sw = 0; sw < nsweeps; ++sw)
+                for (int colour = 0; colour < 2; ++colour)
+                    hipLaunchKernelGGL((k_sweep32_pair<M, S, D>), pgrid, dim3(256), 0, s, g, law, a,
+                                       beta, K, rhs, pb, dl, colour, pm);
+            return;
+        }
         for (int sw = 0; sw < nsweeps; ++sw)
             for (int colour = 0; colour < 2; ++colour) {
                 if (buf)

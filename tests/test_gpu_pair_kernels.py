@@ -13,7 +13,8 @@ sweep is checked against the oracle's red-black sweep from identical inputs
 (RS_SWEEP=single), which makes the same per-node arithmetic: the compiler may
 contract multiply-adds differently in the two kernels, so they agree to a few
 units in the last place.  The Remark's kappa rule always takes the one-node
-sweep.  RS_TRANSFER=pair sends every level with parity-split rows to the pair
+sweep.  RS_SWEEP32=pair does the same for the FP32 correction sweep
+(k_sweep32_pair).  RS_TRANSFER=pair sends every level with parity-split rows to the pair
 transfers: V-cycles (FP64 restriction and prolongation), FMG (the
 interpolation that assigns) and mixed-precision steps (FP32 transfers) are
 compared with the oracle as in the other parity tests.
@@ -134,9 +135,11 @@ MP_PAIR = ["c1_col4097", "c2_slice65", "c3_block33", "c4_root33x17", "st_vg33"]
 
 @pytest.mark.parametrize("name", [n for n in MP_PAIR if n in CASES])
 def test_pair_transfers_mixed_steps(torch_cuda, name, monkeypatch):
-    """Mixed-precision steps (FP32 correction cycles with the pair transfers
-    on every level) to the rounding floor against the FP64 oracle (1e-10)."""
+    """Mixed-precision steps (FP32 correction cycles with the pair sweeps and
+    pair transfers on every level) to the rounding floor against the FP64
+    oracle (1e-10)."""
     monkeypatch.setenv("RS_SWEEP", "pair")
+    monkeypatch.setenv("RS_SWEEP32", "pair")
     monkeypatch.setenv("RS_TRANSFER", "pair")
     w = CASES[name]
     say("pair transfers, mixed", name)
