@@ -332,14 +332,15 @@ __global__ __launch_bounds__(512) void k_vcycle_tail32(const TailArgs *A, int to
 
 unsigned blocks_for(long long N) { return (unsigned)((N + 255) / 256); }
 
-// Two nodes per lane in the FP32 sweeps of levels of at least 2^21 nodes
-// (RS_SWEEP32=single / pair: one on every level / two on every buffer level).
+// Two nodes per lane in the FP32 sweeps of levels of at least 2^22 nodes (at
+// 129^3 one node per lane is faster: 11.0 against 11.8 us); RS_SWEEP32=single
+// / pair: one on every level / two on every buffer-path level.
 bool pair32_level(const Geo &g)
 {
     const char *e = getenv("RS_SWEEP32");
     if (e && strcmp(e, "single") == 0) return false;
     if (e && strcmp(e, "pair") == 0) return true;
-    return g.N >= (1ll << 21);
+    return g.N >= (1ll << 22);
 }
 
 struct Sweep32Launch {

@@ -3,8 +3,8 @@
 The colour sweep (k_sweep_pair) and the grid transfers by coarse pairs
 (k_restrict_pair, k_prolong_pair) run by default on large levels only.
 
-By default the library takes it on levels of at least 2^21 nodes only (the
-257^3 block's two finest levels, the root box); RS_SWEEP=pair sends every
+By default the library takes the pair sweep on levels of at least 2^22 nodes
+only (the 257^3 block's finest level, the root box); RS_SWEEP=pair sends every
 buffer-path level to it, so the parity cases of test_gpu_parity.py exercise
 it on 1-D, 2-D and 3-D levels with ragged half-rows (odd and even n0),
 Dirichlet nodes on either lane of a pair, sinks and layered media.  Each
