@@ -173,7 +173,7 @@ def gpu_run(args):
                  "fp32_sweep_roofline": {"bound": "hbm", "achieved": round(b32 / t32 / 1e9, 1),
                                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                          "frac": round(b32 / t32 / 1e9 / HBM_PEAK_GBS, 4),
-                                         "kernel": "k_sweep32 (finest level, one colour per launch)",
+                                         "kernel": "k_sweep32_pair (finest level, one colour per launch, two nodes per lane)",
                                          "bytes_per_update": BYTES_PER_UPDATE_32,
                                          "traffic": tr32,
                                          "traffic_per_algorithmic": (round(tr32 / b32, 3)

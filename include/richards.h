@@ -171,7 +171,9 @@ typedef struct rs_solve_opts {
     int nu1, nu2, nu_coarse, max_cycles;
     double tol_abs;       /* stop when ||g - N(psi)||_inf <= tol_abs */
     int stagnation;       /* also stop at the rounding floor: two cycles in a row
-                             that set no new minimum of the norm.  RS_OK if the norm
+                             that set no new minimum of the norm (the norm after an
+                             FMG cycle, and the first norm a step takes inside a
+                             cycle, start the comparison afresh).  RS_OK if the norm
                              of the last iterate (the one kept) is within 16 ulp of
                              the largest sum of magnitudes of one node's defect terms
                              (|g|, a|theta|, sink, xi|psi_i|, m_ij (|psi_i| + |psi_j|)

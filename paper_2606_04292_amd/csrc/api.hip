@@ -1181,6 +1181,11 @@ int rs_bdf_step(rs_grid *G, double dt, int order, const rs_solve_opts *o, rs_ste
     // that iterate, once its defect meets the test (one fine defect pass per
     // cycle instead of two).
     const bool test_in_cycle = !mixed && G->nlev > 1 && G->tail_top > 0;
+    // The stagnation test compares the norms the cycles measure with each
+    // other: the first norm taken inside a cycle (after its pre-smoothing,
+    // before any coarse correction) and the norm after an FMG cycle (which
+    // replaces the iterate) start the comparison afresh.
+    bool fresh = true;
     while (std::isfinite(r) && r > o->tol_abs && cycles < o->max_cycles) {
         if (test_in_cycle && !(o->fmg && cycles == 0)) {
             LevelData &f = G->lev[0];
@@ -1193,7 +1198,7 @@ int rs_bdf_step(rs_grid *G, double dt, int order, const rs_solve_opts *o, rs_ste
             if (nh < 64) hist[nh++] = rn;
             r = rn;
             if (o->stagnation) {
-                if (rn < best) {
+                if (fresh || rn < best) {
                     best = rn;
                     slow = 0;
                 } else if (++slow >= 2) {
@@ -1201,6 +1206,7 @@ int rs_bdf_step(rs_grid *G, double dt, int order, const rs_solve_opts *o, rs_ste
                     break;
                 }
             }
+            fresh = false;
             if (!(std::isfinite(rn) && rn > o->tol_abs) || cycles >= o->max_cycles) break;
             e = coarse_cycle(G, 0, o->nu1, o->nu2);
             if (!e) e = sweep_level(G, 0, o->nu2);
@@ -1208,7 +1214,8 @@ int rs_bdf_step(rs_grid *G, double dt, int order, const rs_solve_opts *o, rs_ste
             HIPCALL(hipGetLastError());
             continue;
         }
-        if (o->fmg && cycles == 0) {
+        const bool after_fmg = o->fmg && cycles == 0;
+        if (after_fmg) {
             e = fmg_cycle(G, o->nu1, o->nu2);
             if (e) return e;
         } else if (mixed) {
@@ -1225,7 +1232,7 @@ int rs_bdf_step(rs_grid *G, double dt, int order, const rs_solve_opts *o, rs_ste
         if (nh < 64) hist[nh++] = rn;
         r = rn;
         if (o->stagnation) {
-            if (rn < best) {
+            if (after_fmg || rn < best) {
                 best = rn;
                 slow = 0;
             } else if (++slow >= 2) {
@@ -1233,6 +1240,7 @@ int rs_bdf_step(rs_grid *G, double dt, int order, const rs_solve_opts *o, rs_ste
                 break;
             }
         }
+        if (after_fmg) fresh = true;
     }
     int status = RS_OK;
     bool stalled = false;

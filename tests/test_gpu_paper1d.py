@@ -1,4 +1,4 @@
-"""The 1-D problems on the GPU against the oracle, converged step by step.
+"""The paper's problems on the GPU, converged step by step.
 
 * The infiltration column of section 4.1 (Haverkamp law in cm and s, 40 cm,
   psi0 = -61.5 cm, Dirichlet -20.7 cm on top, Lambda_kappa = 0.1 I, xi = 0,
@@ -6,6 +6,8 @@
   N = 2048).
 * The 257-node van Genuchten column with lexicographic NGS, 50 BDF1 steps of
   60 s, V(2,2), three Newton steps per cell.
+* The two-layer medium of section 4.2 (257^2, FMG(10,10) start, 175 steps):
+  every step converges under the stagnation stop.
 
 The GPU sweeps in red-black order, the paper (and this column's
 configuration) in lexicographic order.  The two orderings share the fixed
@@ -77,3 +79,24 @@ def test_vg_column_fifty_steps_match_lexicographic_oracle():
     assert w.steps == 50 and w.order == 1 and w.law.newton_iters == 3
     say("vG column 257, 50 BDF1 steps against the lexicographic oracle")
     _run(w, w.steps, (oracle.ORDER_LEX,))
+
+
+def test_two_layer_medium_fmg_steps_all_converge():
+    """The paper's two-layer medium (257^2, 175 steps of 0.01 day, an FMG(10,10)
+    cycle then V(10,10) cycles to 1e-10 with the stagnation stop): every step
+    ends RS_OK with its defect at most 1e-10.  Regression: an FMG cycle that
+    raises the norm above the step's start must not be read as a stall."""
+    import torch
+    assert torch.cuda.is_available()
+    w = W.two_layer_vg(257)
+    G = rsl.Grid(w)
+    opts = rsl.solve_opts(w.nu1, w.nu2, w.nu_coarse, max_cycles=200, tol_abs=1e-10,
+                          stagnation=1, fmg=1)
+    worst = 0.0
+    for step in range(w.steps):
+        code, st = G.bdf_step(opts=opts)
+        assert code == rsl.RS_OK, (step + 1, rsl.lib().rs_last_error())
+        assert st.res <= 1e-10, (step + 1, st.res)
+        worst = max(worst, st.res)
+    say("two-layer medium:", w.steps, "steps, worst final defect %.2e" % worst)
+    G.close()
