@@ -80,6 +80,7 @@ struct Base {
     bool sat;        // psi_b >= 0
     float q, den;    // Haverkamp: Q_b, alpha + Q_b; vGM: P_b, X_b = 1 + P_b
     float se;        // vGM: Se_b
+    float ipsi, iden;   // 1 / (-psi_b), 1 / den (unsaturated base states)
 };
 
 template <int MODEL>
@@ -91,6 +92,8 @@ __device__ __forceinline__ Base base_of(const Law32 &L, float pb)
     b.q = 0.0f;
     b.den = 1.0f;
     b.se = 1.0f;
+    b.ipsi = 0.0f;
+    b.iden = 1.0f;
     if (MODEL == kLinear || b.sat) return b;
     if (MODEL == kHaverkamp) {
         b.q = f_exp(L.hk_beta * f_ln(-L.unit * pb));
@@ -100,6 +103,8 @@ __device__ __forceinline__ Base base_of(const Law32 &L, float pb)
         b.den = 1.0f + b.q;
         b.se = f_exp(-L.vg_m * f_log1p(b.q));
     }
+    b.ipsi = f_rcp(-pb);
+    b.iden = f_rcp(b.den);
     return b;
 }
 
@@ -114,9 +119,8 @@ __device__ __forceinline__ void base_room(const Law32 &L, const Base &b, float &
         up = 0.0f;
         down = L.dT;
     } else if (MODEL == kHaverkamp) {
-        const float r = f_rcp(b.den);
-        up = L.dT * b.q * r;
-        down = L.hk_alpha * L.dT * r;
+        up = L.dT * b.q * b.iden;
+        down = L.hk_alpha * L.dT * b.iden;
     } else {
         up = -L.dT * f_expm1(-L.vg_m * f_log1p(b.q));
         down = L.dT * b.se;
@@ -142,17 +146,19 @@ __device__ __forceinline__ void dtheta32(const Law32 &L, const Base &b, float de
     }
     if (MODEL == kHaverkamp) {
         if (!b.sat && !xsat) {
-            const float t = delta * f_rcp(-b.psi);
+            const float t = delta * b.ipsi;
             const float dq = b.q * f_expm1(L.hk_beta * f_log1p(-t));
             const float den = b.den + dq;
-            const float r = f_rcp(den);
-            dth = -L.hk_alpha * L.dT * dq * r * f_rcp(b.den);
             const float hu = -L.unit * x;
-            slope = L.unit * L.hk_beta * (L.hk_alpha * L.dT * r) * ((b.q + dq) * r) * f_rcp(hu);
+            // one reciprocal serves 1/den = hu w and 1/hu = den w
+            const float w = f_rcp(hu * den);
+            const float r = hu * w;
+            dth = -L.hk_alpha * L.dT * dq * r * b.iden;
+            slope = L.unit * L.hk_beta * (L.hk_alpha * L.dT * r) * ((b.q + dq) * r) * (den * w);
             return;
         }
         if (!b.sat) {          // wets up to saturation
-            dth = L.dT * b.q * f_rcp(b.den);
+            dth = L.dT * b.q * b.iden;
             slope = 0.0f;
             return;
         }
@@ -165,9 +171,9 @@ __device__ __forceinline__ void dtheta32(const Law32 &L, const Base &b, float de
     }
     // van Genuchten - Mualem
     if (!b.sat && !xsat) {
-        const float t = delta * f_rcp(-b.psi);
+        const float t = delta * b.ipsi;
         const float dp = b.q * f_expm1(L.vg_n * f_log1p(-t));
-        const float dse = b.se * f_expm1(-L.vg_m * f_log1p(dp * f_rcp(b.den)));
+        const float dse = b.se * f_expm1(-L.vg_m * f_log1p(dp * b.iden));
         dth = L.dT * dse;
         const float P = b.q + dp, X = b.den + dp, Se = b.se + dse;
         slope = L.dT * L.vg_m * L.vg_n * P * Se * f_rcp(X * (-x));
