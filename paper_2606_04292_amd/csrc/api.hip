@@ -412,10 +412,26 @@ int harvest_profile(rs_grid *G)
         HIPCALL(hipEventElapsedTime(&ms, G->prof_ev[2 * q], G->prof_ev[2 * q + 1]));
         G->prof_ms += ms;
         G->prof_launches += G->prof_launch[q];
-        G->prof_cells += (double)G->prof_sweeps[q] * (double)G->lev[0].unknowns;
+        // prof_sweeps counts colour passes: half the unknowns each
+        G->prof_cells += 0.5 * (double)G->prof_sweeps[q] * (double)G->lev[0].unknowns;
     }
     G->prof_used = 0;
     return RS_OK;
+}
+
+// A free pair of profiling events (created on first use).
+hipError_t prof_slot(rs_grid *G)
+{
+    if (2 * (G->prof_used + 1) <= G->prof_ev.size()) return hipSuccess;
+    for (int e = 0; e < 2; ++e) {
+        hipEvent_t ev;
+        const hipError_t r = hipEventCreate(&ev);
+        if (r != hipSuccess) return r;
+        G->prof_ev.push_back(ev);
+    }
+    G->prof_sweeps.push_back(0);
+    G->prof_launch.push_back(0);
+    return hipSuccess;
 }
 
 // nsweeps red-black sweeps on level l, counted, and timed on the finest level
@@ -440,7 +456,7 @@ int sweep_level(rs_grid *G, int l, int nsweeps)
                                    &f.psi_alt, nsweeps, G->stream);
     if (timed) {
         HIPCALL(hipEventRecord(G->prof_ev[2 * G->prof_used + 1], G->stream));
-        G->prof_sweeps[G->prof_used] = nsweeps;
+        G->prof_sweeps[G->prof_used] = 2 * nsweeps;
         G->prof_launch[G->prof_used] = launches;
         G->prof_used += 1;
     }
@@ -475,6 +491,41 @@ int fine_norm(rs_grid *G, double *out, double *d = nullptr, bool mp_start = fals
     if (mp_start) mp = MpStart{f.rhs32, f.pb32, f.dl};
     launch_residual(f.geo, G->law, G->step, f.beta, f.K, f.g, f.psi, d, G->scratch, G->stream, mp);
     HIPCALL(hipGetLastError());
+    return read_norm(G, out);
+}
+
+// The pre-smoothing of an FP64 cycle on the finest level and the max-norm of
+// the defect it leaves (the defect vector into d): where the level runs the
+// pair sweep, the last colour pass forms the defect of its nodes on the way
+// and one more pass that of the others; otherwise the sweeps, then the defect
+// kernel.  The same d and norm either way.
+int presmooth_norm(rs_grid *G, int nu1, double *out)
+{
+    LevelData &f = G->lev[0];
+    if (f.psi_alt || !sweep_defect_level(f.geo, G->law, nu1)) {
+        int e = sweep_level(G, 0, nu1);
+        if (e) return e;
+        return fine_norm(G, out, f.d);
+    }
+    launch_fill_u64(G->scratch, 1, 0ull, G->stream);
+    // the plain colour passes are timed like any sweep batch of the level
+    const bool timed = G->prof_on;
+    if (timed) {
+        HIPCALL(prof_slot(G));
+        HIPCALL(hipEventRecord(G->prof_ev[2 * G->prof_used], G->stream));
+    }
+    launch_sweep_defect(f.geo, G->law, G->step, f.beta, f.K, f.g, f.psi, nu1, f.d, G->scratch, 0,
+                        G->stream);
+    if (timed) {
+        HIPCALL(hipEventRecord(G->prof_ev[2 * G->prof_used + 1], G->stream));
+        G->prof_sweeps[G->prof_used] = 2 * nu1 - 1;
+        G->prof_launch[G->prof_used] = 2 * nu1 - 1;
+        G->prof_used += 1;
+    }
+    launch_sweep_defect(f.geo, G->law, G->step, f.beta, f.K, f.g, f.psi, nu1, f.d, G->scratch, 1,
+                        G->stream);
+    HIPCALL(hipGetLastError());
+    G->updates += (double)nu1 * (double)f.unknowns;
     return read_norm(G, out);
 }
 
@@ -518,7 +569,7 @@ void sweep32_level(rs_grid *G, int l, int nsweeps)
     launch_sweep32(f.geo, G->law32, (float)G->step.a, f.beta, (float)f.lambdaU, f.K32, f.rhs32,
                    f.pb32, f.dl, nsweeps, G->stream);
     if (timed && hipEventRecord(G->prof_ev[2 * G->prof_used + 1], G->stream) == hipSuccess) {
-        G->prof_sweeps[G->prof_used] = nsweeps;
+        G->prof_sweeps[G->prof_used] = 2 * nsweeps;
         G->prof_launch[G->prof_used] = f.geo.N <= 1024 ? 1 : 2 * nsweeps;
         G->prof_used += 1;
     }
@@ -1188,11 +1239,8 @@ int rs_bdf_step(rs_grid *G, double dt, int order, const rs_solve_opts *o, rs_ste
     bool fresh = true;
     while (std::isfinite(r) && r > o->tol_abs && cycles < o->max_cycles) {
         if (test_in_cycle && !(o->fmg && cycles == 0)) {
-            LevelData &f = G->lev[0];
-            e = sweep_level(G, 0, o->nu1);
-            if (e) return e;
             double rn;
-            e = fine_norm(G, &rn, f.d);
+            e = presmooth_norm(G, o->nu1, &rn);
             if (e) return e;
             ++cycles;
             if (nh < 64) hist[nh++] = rn;

@@ -201,6 +201,53 @@ __device__ __forceinline__ double ngs_point(const Geo &g, const Law &L, double a
     return ngs_solve<MODEL, SINK>(g, L, a, e, x0, idx);
 }
 
+// Defect g_i - N_i(psi) of unknown i (column i of its row) at idx from its
+// gathered values: x = psi_i, K*_i, g_i, the axis-0 neighbours (pl, kl: i - 1;
+// pr, kr: i + 1) and the off-row neighbour values with their coefficients cfo
+// (0: no neighbour; the node's own values stand in).  bz: root density of the
+// row (2-D, 3-D); in 1-D the row is the vertical axis and beta[i] is used.
+template <int MODEL, bool SINK, int DIM>
+__device__ __forceinline__ double defect_at(const Geo &g, const Law &L, double a,
+                                            const double *beta, double bz, int i, long long idx,
+                                            double x, double Ki, double gi, double pl, double pr,
+                                            double kl, double kr, const double *po,
+                                            const double *ko, const double *cfo)
+{
+    constexpr int NO = 2 * (DIM - 1);
+    double s;
+    if constexpr (MODEL == kMulti) s = a * theta_only(L.soils[g.soil[idx]], x);
+    else s = a * theta_only_t<MODEL>(L, x);
+    if (SINK) {
+        double fa, dfa;
+        feddes(L, x, fa, dfa);
+        s += ((DIM == 1) ? beta[i] : bz) * fa;
+    }
+    // neighbours in the order of stencil(): axis 0 low/high, then the others
+    const double cx = ((i == 0 || i == g.n[0] - 1) ? 1.0 : 0.5) * g.ih2[0];
+    const double cm0 = i > 0 ? cx : 0.0, cp0 = i < g.n[0] - 1 ? cx : 0.0;
+    double mpsi = 0.0;
+    mpsi += cm0 * (Ki + kl) * (x - pl);
+    mpsi += cp0 * (Ki + kr) * (x - pr);
+#pragma unroll
+    for (int o = 0; o < NO; ++o) {
+        const bool ok = cfo[o] != 0.0;
+        const double pn = ok ? po[o] : x;
+        const double kn = ok ? ko[o] : Ki;
+        mpsi += cfo[o] * (Ki + kn) * (x - pn);
+    }
+    return gi - (s + (L.xi * x + mpsi));
+}
+
+// Off-row coefficient of direction o (axis 1 + o / 2, low or high side) for a
+// node on row coordinate cl of that axis; 0 where the neighbour is missing.
+__device__ __forceinline__ double offrow_cf(const Geo &g, int o, int cl)
+{
+    const int l = 1 + o / 2;
+    const bool up = o & 1;
+    const bool ok = up ? cl < g.n[l] - 1 : cl > 0;
+    return ok ? ((cl == 0 || cl == g.n[l] - 1) ? 1.0 : 0.5) * g.ih2[l] : 0.0;
+}
+
 // Update of unknown (i, j, k) stored at idx, its axis-0 neighbours at xl and
 // xl + 1 (a grid's levels have parity-split rows, see stencil_split; the
 // workspace arrays are padded, so both are always loaded, as one pair).
@@ -516,6 +563,206 @@ __global__ __launch_bounds__(256) void k_sweep_pair(Geo g, Law L, Step st, const
     }
     const double xb = dir_b ? P.y : ngs_solve<MODEL, SINK>(g, L, st.a, e[1], P.y, idx + 1);
     buf_st2(rP, vo, xa, xb);
+}
+
+// The last colour pass of a pre-smoothing (colour 1) fused with the defect of
+// the nodes it updates: k_sweep_pair's update, then g - N(psi) at both nodes
+// (0 at Dirichlet nodes) from the new values and the neighbours already in
+// registers (all of the other colour, unchanged by this pass), stored into d,
+// and their max-norm folded into norm_bits.  The defect arithmetic is
+// defect_at, as in k_residual_pair.  Every lane reaches the block reduction.
+template <int MODEL, bool SINK, int DIM>
+__global__ __launch_bounds__(256) void k_sweep_pair_defect(Geo g, Law L, Step st,
+                                                           const double *beta, const double *K,
+                                                           const double *gv, double *psi,
+                                                           int colour, ColourMap cm, double *d,
+                                                           unsigned long long *norm_bits)
+{
+    double v = 0.0;
+    const unsigned long long t =
+        (unsigned long long)xcd_block_dir(gridDim.x / 8u, colour & 1) * blockDim.x + threadIdx.x;
+    unsigned row = 0;
+    int q = 0;
+    unsigned j = 0, k = 0;
+    int len = 0;
+    if (t < cm.total) {
+        row = udiv((unsigned)t, cm.dH);
+        q = (int)((unsigned)(t - (unsigned long long)row * cm.H));
+        if (DIM == 3) {
+            k = udiv(row, cm.dN1);
+            j = row - k * cm.n1;
+        } else if (DIM == 2) {
+            j = row;
+        }
+        len = ((j + k + colour) & 1) ? g.n[0] - g.xh : g.xh;
+    }
+    if (2 * q < len) {
+        const int par = (int)((j + k + colour) & 1);
+        const bool has_b = 2 * q + 1 < len;
+        const int ia = 4 * q + par;
+        const long long rb = (long long)j * g.stride[1] + (long long)k * g.stride[2];
+        const long long idx = rb + (par ? g.xh : 0) + 2 * q;
+        const long long xl = rb + (par ? 0 : g.xh - 1) + 2 * q;
+        const bool dir_a = dirichlet_at(g, ia, (int)j, (int)k, nullptr);
+        const bool dir_b = !has_b || dirichlet_at(g, ia + 2, (int)j, (int)k, nullptr);
+        const long long bytes = (g.N + 32) * (long long)sizeof(double);
+        const __amdgpu_buffer_rsrc_t rP = buf_rsrc(psi, bytes), rK = buf_rsrc(K, bytes),
+                                     rG = buf_rsrc(gv, bytes), rD = buf_rsrc(d, bytes);
+        const int vo = (int)idx * 8, vx = (int)xl * 8;
+        const v2f64 P = buf_ld2(rP, vo, 0.0), KK = buf_ld2(rK, vo, 0.0),
+                    G2 = buf_ld2(rG, vo, 0.0);
+        const v2f64 PX = buf_ld2(rP, vx, 0.0), KX = buf_ld2(rK, vx, 0.0);
+        const double PX2 = buf_ld<double>(rP, vx + 16), KX2 = buf_ld<double>(rK, vx + 16);
+        constexpr int NO = 2 * (DIM - 1);
+        v2f64 Po[NO > 0 ? NO : 1], Ko[NO > 0 ? NO : 1];
+#pragma unroll
+        for (int l = 1; l < DIM; ++l) {
+            const int so = g.stride[l] * 8;
+            Po[2 * l - 2] = buf_ld2(rP, vo - so, 0.0);
+            Ko[2 * l - 2] = buf_ld2(rK, vo - so, 0.0);
+            Po[2 * l - 1] = buf_ld2(rP, vo + so, 0.0);
+            Ko[2 * l - 1] = buf_ld2(rK, vo + so, 0.0);
+        }
+        const double pw[3] = {PX.x, PX.y, PX2}, kw[3] = {KX.x, KX.y, KX2};
+        double xnew[2] = {P.x, P.y};
+        if (!(dir_a && dir_b)) {
+            PointEq e[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                const int i = ia + 2 * a;
+                const Stencil<DIM> sn = stencil_split<DIM>(g, i, (int)j, (int)k, idx + a, xl + a);
+                double Kn[2 * DIM], pn[2 * DIM];
+                Kn[0] = kw[a];
+                Kn[1] = kw[a + 1];
+                pn[0] = pw[a];
+                pn[1] = pw[a + 1];
+#pragma unroll
+                for (int o = 0; o < NO; ++o) {
+                    Kn[2 + o] = a ? Ko[o].y : Ko[o].x;
+                    pn[2 + o] = a ? Po[o].y : Po[o].x;
+                }
+                e[a] = ngs_reduce<SINK, DIM, false>(g, L, beta, 0.0, sn, a ? KK.y : KK.x, Kn, pn,
+                                                    a ? G2.y : G2.x, a ? P.y : P.x, i, (int)j,
+                                                    (int)k, colour);
+            }
+            if (!dir_a) xnew[0] = ngs_solve<MODEL, SINK>(g, L, st.a, e[0], P.x, idx);
+            __builtin_amdgcn_sched_barrier(0);
+            if (!dir_b) xnew[1] = ngs_solve<MODEL, SINK>(g, L, st.a, e[1], P.y, idx + 1);
+            if (has_b) buf_st2(rP, vo, xnew[0], xnew[1]);
+            else buf_st(rP, vo, xnew[0]);
+        }
+        // the defect of both nodes at their new values
+        double bz = 0.0;
+        if (SINK && DIM > 1) bz = beta[DIM == 2 ? j : k];
+        double cfo[NO > 0 ? NO : 1];
+#pragma unroll
+        for (int o = 0; o < NO; ++o) cfo[o] = offrow_cf(g, o, o < 2 ? (int)j : (int)k);
+        double r[2] = {0.0, 0.0};
+        const double gs[2] = {G2.x, G2.y}, Ks_[2] = {KK.x, KK.y};
+        const bool dirs[2] = {dir_a, dir_b};
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            if (dirs[a]) continue;
+            double po[NO > 0 ? NO : 1], ko[NO > 0 ? NO : 1];
+#pragma unroll
+            for (int o = 0; o < NO; ++o) {
+                po[o] = a ? Po[o].y : Po[o].x;
+                ko[o] = a ? Ko[o].y : Ko[o].x;
+            }
+            r[a] = defect_at<MODEL, SINK, DIM>(g, L, st.a, beta, bz, ia + 2 * a, idx + a, xnew[a],
+                                               Ks_[a], gs[a], pw[a], pw[a + 1], kw[a], kw[a + 1],
+                                               po, ko, cfo);
+        }
+        if (has_b) buf_st2(rD, vo, r[0], r[1]);
+        else buf_st(rD, vo, r[0]);
+        const double a0 = fabs(r[0]), a1 = fabs(r[1]);
+        v = (a1 > a0 || a1 != a1) ? a1 : a0;
+    }
+    v = block_max(v);
+    if (threadIdx.x == 0) {
+        const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
+        if (bits > __hip_atomic_load(norm_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicMax(norm_bits, bits);
+    }
+}
+
+// The defect of one colour's nodes (the colour the fused pass did not
+// update), two per lane with k_sweep_pair's slots; d and the max-norm as in
+// k_residual_pair.
+template <int MODEL, bool SINK, int DIM>
+__global__ __launch_bounds__(256) void k_defect_colour(Geo g, Law L, Step st, const double *beta,
+                                                       const double *K, const double *gv,
+                                                       const double *psi, int colour, ColourMap cm,
+                                                       double *d, unsigned long long *norm_bits)
+{
+    double v = 0.0;
+    const unsigned long long t =
+        (unsigned long long)xcd_block(gridDim.x / 8u) * blockDim.x + threadIdx.x;
+    unsigned j = 0, k = 0;
+    int q = 0, len = 0;
+    if (t < cm.total) {
+        const unsigned row = udiv((unsigned)t, cm.dH);
+        q = (int)((unsigned)(t - (unsigned long long)row * cm.H));
+        if (DIM == 3) {
+            k = udiv(row, cm.dN1);
+            j = row - k * cm.n1;
+        } else if (DIM == 2) {
+            j = row;
+        }
+        len = ((j + k + colour) & 1) ? g.n[0] - g.xh : g.xh;
+    }
+    if (2 * q < len) {
+        const int par = (int)((j + k + colour) & 1);
+        const bool has_b = 2 * q + 1 < len;
+        const int ia = 4 * q + par;
+        const long long rb = (long long)j * g.stride[1] + (long long)k * g.stride[2];
+        const long long idx = rb + (par ? g.xh : 0) + 2 * q;
+        const long long xl = rb + (par ? 0 : g.xh - 1) + 2 * q;
+        const double2_u P = load_pair(psi + idx), KK = load_pair(K + idx), G2 = load_pair(gv + idx);
+        const double2_u PX = load_pair(psi + xl), KX = load_pair(K + xl);
+        const double PX2 = psi[xl + 2], KX2 = K[xl + 2];
+        constexpr int NO = 2 * (DIM - 1);
+        double2_u Po[NO > 0 ? NO : 1], Ko[NO > 0 ? NO : 1];
+        double cfo[NO > 0 ? NO : 1];
+#pragma unroll
+        for (int o = 0; o < NO; ++o) {
+            const int l = 1 + o / 2;
+            const int cl = l == 1 ? (int)j : (int)k;
+            cfo[o] = offrow_cf(g, o, cl);
+            const long long b = cfo[o] != 0.0 ? ((o & 1) ? g.stride[l] : -(long long)g.stride[l]) : 0;
+            Po[o] = load_pair(psi + idx + b);
+            Ko[o] = load_pair(K + idx + b);
+        }
+        double bz = 0.0;
+        if (SINK && DIM > 1) bz = beta[DIM == 2 ? j : k];
+        const double xs[2] = {P.x, P.y}, Ks_[2] = {KK.x, KK.y}, gs[2] = {G2.x, G2.y};
+        const double pw[3] = {PX.x, PX.y, PX2}, kw[3] = {KX.x, KX.y, KX2};
+        double r[2] = {0.0, 0.0};
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const int i = ia + 2 * a;
+            if ((a == 1 && !has_b) || dirichlet_at(g, i, (int)j, (int)k, nullptr)) continue;
+            double po[NO > 0 ? NO : 1], ko[NO > 0 ? NO : 1];
+#pragma unroll
+            for (int o = 0; o < NO; ++o) {
+                po[o] = a ? Po[o].y : Po[o].x;
+                ko[o] = a ? Ko[o].y : Ko[o].x;
+            }
+            r[a] = defect_at<MODEL, SINK, DIM>(g, L, st.a, beta, bz, i, idx + a, xs[a], Ks_[a],
+                                               gs[a], pw[a], pw[a + 1], kw[a], kw[a + 1], po, ko,
+                                               cfo);
+        }
+        if (has_b) store_pair(d + idx, r[0], r[1]);
+        else d[idx] = r[0];
+        const double a0 = fabs(r[0]), a1 = fabs(r[1]);
+        v = (a1 > a0 || a1 != a1) ? a1 : a0;
+    }
+    v = block_max(v);
+    if (threadIdx.x == 0) {
+        const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
+        if (bits > __hip_atomic_load(norm_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicMax(norm_bits, bits);
+    }
 }
 
 // One colour of a red-black sweep of a 3-D level, marching along axis 2 with
@@ -894,31 +1141,15 @@ __global__ __launch_bounds__(256) void k_residual_pair(Geo g, Law L, Step st, co
         for (int a = 0; a < 2; ++a) {
             const int i = ia + 2 * a;
             if ((a == 1 && !has_b) || dirichlet_at(g, i, j, k, nullptr)) continue;
-            const double x = xs[a], Ki = Ks_[a];
-            double s;
-            if constexpr (MODEL == kMulti) s = st.a * theta_only(L.soils[g.soil[idx + a]], x);
-            else s = st.a * theta_only_t<MODEL>(L, x);
-            if (SINK) {
-                // in 1-D the row is the vertical axis: each node has its own root density
-                double fa, dfa;
-                feddes(L, x, fa, dfa);
-                s += ((DIM == 1) ? beta[i] : bz) * fa;
-            }
-            // neighbours in the order of stencil(): axis 0 low/high, then the others
-            const double cx = ((i == 0 || i == g.n[0] - 1) ? 1.0 : 0.5) * g.ih2[0];
-            const double cm0 = i > 0 ? cx : 0.0, cp0 = i < g.n[0] - 1 ? cx : 0.0;
-            double mpsi = 0.0;
-            mpsi += cm0 * (Ki + kw[a]) * (x - pw[a]);
-            mpsi += cp0 * (Ki + kw[a + 1]) * (x - pw[a + 1]);
+            double po[NO > 0 ? NO : 1], ko[NO > 0 ? NO : 1];
 #pragma unroll
             for (int o = 0; o < NO; ++o) {
-                // a missing neighbour is the node itself (coefficient 0)
-                const bool ok = cfo[o] != 0.0;
-                const double pn = ok ? (a ? Po[o].y : Po[o].x) : x;
-                const double kn = ok ? (a ? Ko[o].y : Ko[o].x) : Ki;
-                mpsi += cfo[o] * (Ki + kn) * (x - pn);
+                po[o] = a ? Po[o].y : Po[o].x;
+                ko[o] = a ? Ko[o].y : Ko[o].x;
             }
-            r[a] = gs[a] - (s + (L.xi * x + mpsi));
+            r[a] = defect_at<MODEL, SINK, DIM>(g, L, st.a, beta, bz, i, idx + a, xs[a], Ks_[a],
+                                               gs[a], pw[a], pw[a + 1], kw[a], kw[a + 1], po, ko,
+                                               cfo);
         }
         if (d) {
             if (has_b) store_pair(d + idx, r[0], r[1]);
@@ -1271,6 +1502,43 @@ struct SweepLaunch {
     }
 };
 
+// A pre-smoothing of nsweeps sweeps on a level that runs the pair sweep, with
+// the defect of the iterate it leaves formed on the way: the last colour pass
+// also forms the defect of the nodes it updates (k_sweep_pair_defect), one
+// more pass that of the other colour (k_defect_colour); d and norm_bits get
+// what k_residual_pair would give after the sweeps.  RS_DEFECT_FUSE=0 turns
+// it off.
+bool sweep_defect_enabled()
+{
+    const char *e = getenv("RS_DEFECT_FUSE");
+    return !(e && strcmp(e, "0") == 0);
+}
+
+struct SweepDefectLaunch {
+    const Geo &g; const Law &law; const Step &st; const double *beta; const double *K;
+    const double *gvec; double *psi; int nsweeps; double *d; unsigned long long *norm_bits;
+    hipStream_t s; int phase;
+    template <int M, bool S, int D>
+    void go()
+    {
+        ColourMap pm = colour_map(g);
+        pm.H = (pm.H + 1) / 2;
+        pm.dH = make_fastdiv(pm.H);
+        pm.total = (unsigned long long)pm.H * g.n[1] * g.n[2];
+        const dim3 pgrid(xcd_grid((pm.total + 255) / 256));
+        if (phase == 0) {   // every colour pass but the last
+            for (int p = 0; p + 1 < 2 * nsweeps; ++p)
+                hipLaunchKernelGGL((k_sweep_pair<M, S, D>), pgrid, dim3(256), 0, s, g, law, st,
+                                   beta, 0.0, K, gvec, psi, p & 1, pm);
+            return;
+        }
+        hipLaunchKernelGGL((k_sweep_pair_defect<M, S, D>), pgrid, dim3(256), 0, s, g, law, st,
+                           beta, K, gvec, psi, 1, pm, d, norm_bits);
+        hipLaunchKernelGGL((k_defect_colour<M, S, D>), pgrid, dim3(256), 0, s, g, law, st, beta, K,
+                           gvec, psi, 0, pm, d, norm_bits);
+    }
+};
+
 struct CoarseRhsLaunch {
     const Geo &g; const Law &law; const Step &st; const double *beta; const double *K;
     const double *psibar; double *gvec; double *psi; hipStream_t s;
@@ -1323,6 +1591,22 @@ int launch_sweep_rb(const Geo &g, const Law &law, const Step &st, const double *
     dispatch<true>(law, g.dim, SweepLaunch{g, law, st, beta, lambdaU, K, gvec, psi, psi_alt, nsweeps, s});
     if (g.N <= 1024) return 1;
     return (g.dim == 3 && psi_alt && *psi_alt && fused_enabled()) ? nsweeps : 2 * nsweeps;
+}
+
+bool sweep_defect_level(const Geo &g, const Law &law, int nsweeps)
+{
+    if (nsweeps <= 0 || g.N <= 1024 || !buffer_ok(g, sizeof(double)) ||
+        law.kappa_rule == kKappaRemark || !pair_sweep_level(g) || !sweep_defect_enabled())
+        return false;
+    return !(g.dim == 3 && zm_level(g) && zm_enabled());
+}
+
+void launch_sweep_defect(const Geo &g, const Law &law, const Step &st, const double *beta,
+                         const double *K, const double *gvec, double *psi, int nsweeps, double *d,
+                         unsigned long long *norm_bits, int phase, hipStream_t s)
+{
+    dispatch<true>(law, g.dim,
+                   SweepDefectLaunch{g, law, st, beta, K, gvec, psi, nsweeps, d, norm_bits, s, phase});
 }
 
 bool fused_sweep_level(const Geo &g)

@@ -141,6 +141,15 @@ bool fused_sweep_level(const Geo &g);
 struct MpStart {
     float *rhs, *pb, *dl;
 };
+// nsweeps red-black sweeps of a level whose sweeps run two nodes per lane
+// (sweep_defect_level), leaving the defect of the swept iterate in d and its
+// max-norm folded into norm_bits (the caller zeroes it): phase 0 launches
+// every colour pass but the last, phase 1 the last one fused with the defect
+// of its nodes and the defect of the other colour.
+bool sweep_defect_level(const Geo &g, const Law &law, int nsweeps);
+void launch_sweep_defect(const Geo &g, const Law &law, const Step &st, const double *beta,
+                         const double *K, const double *gvec, double *psi, int nsweeps, double *d,
+                         unsigned long long *norm_bits, int phase, hipStream_t s);
 void launch_residual(const Geo &g, const Law &law, const Step &st, const double *beta,
                      const double *K, const double *gvec, const double *psi, double *d,
                      unsigned long long *norm_bits, hipStream_t s, MpStart mp = {});

@@ -242,3 +242,36 @@ def test_zm_sweep_converged_steps(torch_cuda, monkeypatch):
         say("  zm step", step, "cycles", st.cycles, "rel", e)
         assert e <= 1e-10, (step, e)
     G.close()
+
+
+FUSE_CASES = ["c1_col4097", "c2_slice65", "c3_block33", "c4_root33x17", "lay_2layer33", "st_vg33"]
+
+
+@pytest.mark.parametrize("name", [n for n in FUSE_CASES if n in CASES])
+def test_presmoothing_with_fused_defect_is_bitwise_the_plain_one(torch_cuda, name, monkeypatch):
+    """Steps whose pre-smoothing forms the defect on the way (the last colour
+    pass with k_sweep_pair_defect, the other colour with k_defect_colour)
+    give bitwise the states, cycle counts and residual histories of the plain
+    sweeps followed by k_residual_pair (RS_DEFECT_FUSE=0); the pair sweep is
+    forced on every level so that the small cases take the fused path."""
+    torch = torch_cuda
+    monkeypatch.setenv("RS_SWEEP", "pair")
+    w = CASES[name]
+    say("fused defect", name)
+    runs = {}
+    for fuse in ("1", "0"):
+        monkeypatch.setenv("RS_DEFECT_FUSE", fuse)
+        G = rsl.Grid(w)
+        opts = rsl.solve_opts(w.nu1, w.nu2, w.nu_coarse, max_cycles=FLOOR_CYCLES, tol_abs=0.0,
+                              stagnation=1)
+        out = []
+        for step in range(3):
+            code, st = G.bdf_step(opts=opts)
+            assert code == rsl.RS_OK, (fuse, step, rsl.lib().rs_last_error())
+            out.append((st.cycles, [st.res_hist[i] for i in range(st.n_hist)],
+                        np_(G.get_state()[0])))
+        G.close()
+        runs[fuse] = out
+    for (c1, h1, p1), (c0, h0, p0) in zip(runs["1"], runs["0"]):
+        assert c1 == c0 and h1 == h0
+        assert np.array_equal(p1, p0)
