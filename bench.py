@@ -125,7 +125,7 @@ def gpu_run(args):
     psi0 = torch.as_tensor(w.psi0, device="cuda:0")
     G = rsl.Grid(w, device="cuda:0")
     opts = rsl.solve_opts(w.nu1, w.nu2, w.nu_coarse, max_cycles=args.max_cycles,
-                          tol_abs=args.tol, stagnation=1)
+                          tol_abs=args.tol, stagnation=1, mp_inner_cycles=args.mp_inner)
     # warm-up: the first steps of the same time loop, then back to t = 0
     warm = time_loop(G, w, psi0, args.warmup, opts, "warmup")
     G.set_state(psi0)
@@ -167,6 +167,7 @@ def gpu_run(args):
                  "speedup_vs_fp64": round(elapsed / el2, 3),
                  "fp32_cell_updates_per_s": sum(x[3] for x in msteps) / el2,
                  "outer_corrections_per_step": [x[1] for x in msteps],
+                 "fp32_cycles_per_correction": args.mp_inner,
                  "steps_not_converged": mbad,
                  "warmup_ok": all(x[0] == rsl.RS_OK for x in mwarm),
                  "rel_err_vs_fp64": err,
@@ -554,8 +555,11 @@ def config_leg(args, cfg):
     w = {1: W.config1, 2: W.config2, 4: W.config4}[cfg]()
     psi0 = torch.as_tensor(np.ascontiguousarray(w.psi0), device="cuda:0")
     tol = args.config_tol
+    # one FP32 cycle per correction: on these grids (iterated to the rounding
+    # floor) three were slower (column 2.6 -> 3.8, slice 5.7 -> 7.1, root box
+    # 10.4 -> 14.4 ms per mixed step)
     opts = rsl.solve_opts(w.nu1, w.nu2, w.nu_coarse, max_cycles=args.max_cycles, tol_abs=tol,
-                          stagnation=1)
+                          stagnation=1, mp_inner_cycles=1)
     out = {"config": cfg, "workload": "%s: %s nodes, %s, dt %g s, %d steps, V(%d,%d), every step "
                                       "to %s" % (
                w.name, "x".join(str(v) for v in w.grid.n),
@@ -704,6 +708,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
+    ap.add_argument("--mp-inner", type=int, default=3,
+                    help="FP32 V-cycles per FP64 defect correction in the 257^3 mixed-precision leg "
+                         "(measured at 257^3: 1 / 2 / 3 / 4 / 6 give 30.7 / 27.9 / 27.0 / 27.6 / "
+                         "27.7 ms per step)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--serve-requests", type=int, default=4096)
     ap.add_argument("--serve-baseline", type=int, default=256,
