@@ -583,8 +583,7 @@ void vcycle32_level(rs_grid *G, int l, int nu1, int nu2);
 // restriction of the fine iterate and of its defect (FP64: already in the
 // level's d), the coarse right-hand side, the cycle on level 1 and below, the
 // prolongation.  which = 1: the FP32 correction cycle, which first forms its
-// inner defect and injects the base state psi_b into the coarse levels
-// (idempotent within an outer correction).
+// inner defect (the coarse levels hold the injected base state psi_b).
 void coarse_cycle_plain(rs_grid *G, int which, int nu1, int nu2)
 {
     LevelData &f = G->lev[0], &c = G->lev[1];
@@ -596,9 +595,6 @@ void coarse_cycle_plain(rs_grid *G, int which, int nu1, int nu2)
         return;
     }
     const float a = (float)G->step.a;
-    for (int l = 1; l < G->nlev; ++l)
-        launch_inject32(G->lev[l].geo, G->lev[l - 1].geo, G->lev[l - 1].pb32, G->lev[l].pb32,
-                        G->stream);
     launch_residual32(f.geo, G->law32, a, f.beta, f.K32, f.rhs32, f.pb32, f.dl, f.r32, G->stream);
     launch_restrict32(c.geo, f.geo, f.dl, f.r32, c.dbar32, c.rhs32, G->stream);
     launch_coarse_rhs32(c.geo, G->law32, a, c.beta, c.K32, c.pb32, c.dbar32, c.rhs32, c.dl, G->stream);
@@ -711,11 +707,18 @@ void vcycle32_level(rs_grid *G, int l, int nu1, int nu2)
 
 // One outer defect correction: the defect kernel has already written the FP32
 // right-hand side fl32(r), the base state fl32(psi) and delta = 0 on the finest
-// level (fine_norm with mp_start); FP32 cycles solve the correction equation
-// (each injecting psi_b into the coarse levels) and psi += delta in FP64.
+// level (fine_norm with mp_start); psi_b is injected into the coarse levels
+// once, FP32 cycles solve the correction equation and psi += delta in FP64.
 void mp_correction(rs_grid *G, int inner, int nu1, int nu2)
 {
     LevelData &f = G->lev[0];
+    Geo geo[kMaxLevels];
+    float *pb[kMaxLevels];
+    for (int l = 0; l < G->nlev; ++l) {
+        geo[l] = G->lev[l].geo;
+        pb[l] = G->lev[l].pb32;
+    }
+    launch_inject_base32(geo, pb, G->nlev, G->stream);
     for (int c = 0; c < inner; ++c) vcycle32_level(G, 0, nu1, nu2);
     launch_apply_delta(f.geo.N, f.dl, f.psi, G->stream);
 }

@@ -495,9 +495,65 @@ void launch_prolong32(const Geo &gf, const Geo &gc, const float *dl_c, const flo
     launch_prolong_t<float>(gf, gc, dl_c, dbar_c, dl_f, s);
 }
 
-void launch_inject32(const Geo &gc, const Geo &gf, const float *vf, float *vc, hipStream_t s)
+namespace {
+
+// One level of the base-state injection: its node counts, the row layout and
+// strides that lin() uses, and its array.
+struct InjLevel {
+    int n0, n1, xs, xh;
+    long long s1, s2, N;
+    float *v;
+};
+
+struct InjectPlan {
+    int nlev;
+    long long first[kMaxLevels + 1];   // first work-group of each coarse level
+    InjLevel lv[kMaxLevels];
+};
+
+__device__ __forceinline__ long long inj_pos(const InjLevel &L, int i, int j, int k)
 {
-    hipLaunchKernelGGL((k_inject_t<float>), node_grid(gc), dim3(kBX, kBY), 0, s, gc, gf, vf, vc);
+    return (long long)((i >> L.xs) + (i & 1) * L.xh) + (long long)j * L.s1 + (long long)k * L.s2;
+}
+
+// psi_b on every coarse level at once: node (i, j, k) of level l takes the
+// finest level's value at (2^l i, 2^l j, 2^l k), the composition of the
+// level-to-level injections v_H[I] = v_h[2I].  The work-groups of a level are
+// contiguous, so the level is uniform within a group.
+__global__ __launch_bounds__(256) void k_inject_base32(InjectPlan P)
+{
+    const long long b = blockIdx.x;
+    int l = 1;
+    while (l + 1 < P.nlev && b >= P.first[l + 1]) ++l;
+    const InjLevel &c = P.lv[l];
+    const long long t = (b - P.first[l]) * 256 + threadIdx.x;
+    if (t >= c.N) return;
+    const int i = (int)(t % c.n0);
+    const long long r = t / c.n0;
+    const int j = (int)(r % c.n1), k = (int)(r / c.n1);
+    c.v[inj_pos(c, i, j, k)] = P.lv[0].v[inj_pos(P.lv[0], i << l, j << l, k << l)];
+}
+
+}  // namespace
+
+void launch_inject_base32(const Geo *geo, float *const *pb, int nlev, hipStream_t s)
+{
+    if (nlev < 2) return;
+    InjectPlan P;
+    memset(&P, 0, sizeof P);
+    P.nlev = nlev;
+    long long blocks = 0;
+    for (int l = 0; l < nlev; ++l) {
+        const Geo &g = geo[l];
+        P.lv[l] = InjLevel{g.n[0], g.n[1], g.xs, g.xh, (long long)g.stride[1],
+                           (long long)g.stride[2], g.N, pb[l]};
+        if (l >= 1) {
+            P.first[l] = blocks;
+            blocks += (g.N + 255) / 256;
+        }
+    }
+    P.first[nlev] = blocks;
+    hipLaunchKernelGGL(k_inject_base32, dim3((unsigned)blocks), dim3(256), 0, s, P);
 }
 
 void launch_to_f32(long long N, const double *src, float *dst, hipStream_t s)

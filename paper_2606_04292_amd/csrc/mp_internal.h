@@ -19,7 +19,9 @@ void launch_restrict32(const Geo &gc, const Geo &gf, const float *dl_f, const fl
                        float *dbar_c, float *rhs_c, hipStream_t s);
 void launch_prolong32(const Geo &gf, const Geo &gc, const float *dl_c, const float *dbar_c,
                       float *dl_f, hipStream_t s);
-void launch_inject32(const Geo &gc, const Geo &gf, const float *vf, float *vc, hipStream_t s);
+// psi_b of levels 1 .. nlev-1 by injection from level 0, in one launch
+// (geo[l] and pb[l]: level l's geometry and FP32 base state).
+void launch_inject_base32(const Geo *geo, float *const *pb, int nlev, hipStream_t s);
 void launch_to_f32(long long N, const double *src, float *dst, hipStream_t s);
 void launch_apply_delta(long long N, const float *dl, double *psi64, hipStream_t s);
 // The FP32 correction cycle from level top (all of whose levels hold at most
