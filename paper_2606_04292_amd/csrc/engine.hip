@@ -493,10 +493,14 @@ __global__ __launch_bounds__(256) void e_transfer32(const EList *DL, const ESlot
 
 // ---------------------------------------------------------------------------
 // Small levels: one work-group per slot runs the cycle from level `wide` down
-// to the coarsest and back, with work-group barriers between the steps.
+// to the coarsest and back, with work-group barriers between the steps.  Its
+// helpers are inlined: as calls they took a stack frame and the call ABI's
+// register budget (248 VGPRs against 127), and the array pointers of the LDS
+// variant lost their address space (flat instead of LDS loads).
 // ---------------------------------------------------------------------------
 
-__device__ void tail_sweeps(const ESlot &S, float a, const ELevel &Lv, const Arrs &A, int n)
+__device__ __forceinline__ void tail_sweeps(const ESlot &S, float a, const ELevel &Lv,
+                                            const Arrs &A, int n)
 {
     for (int sw = 0; sw < n; ++sw) {
         int changed = 0;
@@ -524,8 +528,8 @@ __device__ void tail_sweeps(const ESlot &S, float a, const ELevel &Lv, const Arr
 // The V-cycle from level top down to the coarsest and back, one work-group;
 // arrs(l) gives the arrays of level l the cycle works on.
 template <typename Arr>
-__device__ void tail_cycle(const ESlot &S, float a, const ELevel *LV, int top, int last, int nu1,
-                           int nu2, int nuc, Arr &&arrs)
+__device__ __forceinline__ void tail_cycle(const ESlot &S, float a, const ELevel *LV, int top,
+                                           int last, int nu1, int nu2, int nuc, Arr &&arrs)
 {
     for (int l = top; l < last; ++l) {
         const ELevel &F = LV[l], &C = LV[l + 1];
