@@ -500,7 +500,7 @@ __global__ __launch_bounds__(256) void e_transfer32(const EList *DL, const ESlot
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ void tail_sweeps(const ESlot &S, float a, const ELevel &Lv,
-                                            const Arrs &A, int n)
+                                            const Arrs &A, int n, bool exit)
 {
     for (int sw = 0; sw < n; ++sw) {
         int changed = 0;
@@ -519,7 +519,7 @@ __device__ __forceinline__ void tail_sweeps(const ESlot &S, float a, const ELeve
             // has converged in FP32 (the correction solve only sets the outer
             // FP64 iteration's contraction): the sweeps left would shuffle
             // rounding
-            if (colour == 0) __syncthreads();
+            if (colour == 0 || !exit) __syncthreads();
             else if (!__syncthreads_or(changed)) return;
         }
     }
@@ -534,7 +534,7 @@ __device__ __forceinline__ void tail_cycle(const ESlot &S, float a, const ELevel
     for (int l = top; l < last; ++l) {
         const ELevel &F = LV[l], &C = LV[l + 1];
         const Arrs AF = arrs(l), AC = arrs(l + 1);
-        tail_sweeps(S, a, F, AF, nu1);
+        tail_sweeps(S, a, F, AF, nu1, false);
         for (unsigned long long t = threadIdx.x; t < (unsigned long long)F.geo.N; t += blockDim.x)
             resid32_node(S, a, F, AF, t);
         __syncthreads();
@@ -545,14 +545,14 @@ __device__ __forceinline__ void tail_cycle(const ESlot &S, float a, const ELevel
             crhs32_node(S, a, C, AC, t);
         __syncthreads();
     }
-    tail_sweeps(S, a, LV[last], arrs(last), nuc);
+    tail_sweeps(S, a, LV[last], arrs(last), nuc, true);
     for (int l = last - 1; l >= top; --l) {
         const ELevel &F = LV[l], &C = LV[l + 1];
         const Arrs AF = arrs(l), AC = arrs(l + 1);
         for (unsigned long long t = threadIdx.x; t < (unsigned long long)F.geo.N; t += blockDim.x)
             prolong32_node(F, C, AF, AC, t);
         __syncthreads();
-        tail_sweeps(S, a, F, AF, nu2);
+        tail_sweeps(S, a, F, AF, nu2, false);
     }
 }
 

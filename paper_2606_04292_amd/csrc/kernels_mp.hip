@@ -248,10 +248,11 @@ __global__ __launch_bounds__(256) void k_apply_delta(long long N, const float *d
     if (t < N) psi64[t] += (double)dl[t];
 }
 
-// FP32 red-black sweeps of one level inside the one-work-group cycle, with the
-// exit of k_sweep32_small (a sweep that moved no value by more than 4 FP32 ulp).
+// FP32 red-black sweeps of one level inside the one-work-group cycle; on the
+// coarsest level (exit) with the exit of k_sweep32_small (a sweep that moved no
+// value by more than 4 FP32 ulp).
 template <int MODEL, bool SINK, int DIM>
-__device__ void tail_sweeps32(const TailLevel &T, const Law32 &L, float a, int n)
+__device__ void tail_sweeps32(const TailLevel &T, const Law32 &L, float a, int n, bool exit)
 {
     const ColourMap cm = tail_cm(T);
     for (int sw = 0; sw < n; ++sw) {
@@ -265,7 +266,7 @@ __device__ void tail_sweeps32(const TailLevel &T, const Law32 &L, float a, int n
                                                                     T.K32, T.rhs32, T.pb32, T.dl,
                                                                     i, j, k, colour);
             }
-            if (colour == 0) __syncthreads();
+            if (colour == 0 || !exit) __syncthreads();
             else if (!__syncthreads_or(changed)) return;
         }
     }
@@ -285,7 +286,7 @@ __global__ __launch_bounds__(512) void k_vcycle_tail32(const TailArgs *A, int to
     __syncthreads();
     for (int l = top; l < last; ++l) {
         const TailLevel &F = SL[l], &C = SL[l + 1];
-        tail_sweeps32<MODEL, SINK, DIM>(F, L, a, nu1);
+        tail_sweeps32<MODEL, SINK, DIM>(F, L, a, nu1, false);
         const NodeMap nf = tail_nm(F), nc = tail_nm(C);
         for (unsigned long long t = threadIdx.x; t < (unsigned long long)F.g.N; t += blockDim.x) {
             int i, j, k;
@@ -314,7 +315,7 @@ __global__ __launch_bounds__(512) void k_vcycle_tail32(const TailArgs *A, int to
         }
         __syncthreads();
     }
-    tail_sweeps32<MODEL, SINK, DIM>(SL[last], L, a, nuc);
+    tail_sweeps32<MODEL, SINK, DIM>(SL[last], L, a, nuc, true);
     __syncthreads();
     for (int l = last - 1; l >= top; --l) {
         const TailLevel &F = SL[l], &C = SL[l + 1];
@@ -325,7 +326,7 @@ __global__ __launch_bounds__(512) void k_vcycle_tail32(const TailArgs *A, int to
             prolong_at<DIM, float>(F.g, C.g, C.dl, C.dbar32, F.dl, i, j, k);
         }
         __syncthreads();
-        tail_sweeps32<MODEL, SINK, DIM>(F, L, a, nu2);
+        tail_sweeps32<MODEL, SINK, DIM>(F, L, a, nu2, false);
         __syncthreads();
     }
 }
