@@ -55,7 +55,7 @@ constexpr int kWideGroups = 2048;   // work-groups of every batched multi-group 
 constexpr int kEngMaxLevels = 12;   // up to 2^11 + 1 nodes on the shortest axis
 constexpr int kMaxSlots = 4096;
 constexpr int kMaxWide = 8;
-constexpr int kTailThreads = 512;         // work-group of the small-level cycle
+constexpr int kTailThreads = 1024;        // work-group of the small-level cycle
 constexpr size_t kTailLdsMax = 152 * 1024;  // LDS the small-level cycle may use
 
 enum : int { kEmpty = 0, kBegin = 1, kActive = 2, kFinished = 3, kFailed = 4 };
@@ -577,7 +577,7 @@ __device__ __forceinline__ void block_copy(float *dst, const float *src, long lo
 // level and delta, rhs of the top one are staged in, the cycle runs on LDS,
 // and delta of the top level is written back (the wide levels' prolongation
 // reads it).
-__global__ __launch_bounds__(512) void e_tail(const EList *TL, const ESlot *slots,
+__global__ __launch_bounds__(1024) void e_tail(const EList *TL, const ESlot *slots,
                                               const EDyn *dyn, const ELevel *levels, int nu1,
                                               int nu2, int nuc)
 {
