@@ -443,6 +443,16 @@ Law32 make_law32(const Law &L)
     // a few digits: whenever the FP64 solve may stop early, the FP32 one stops
     // after a step of 1e-5 |d| (the steps it leaves out are ~1e-10 |d|).
     f.newton_tol = L.newton_tol > 0.0 ? 1e-5f : 0.0f;
+    // binom(e, k) = binom(e, k - 1) (e - k + 1) / k, in double, rounded once
+    auto binom = [](double e, float *c) {
+        double b = 1.0;
+        for (int k = 1; k <= 6; ++k) {
+            b *= (e - (k - 1)) / k;
+            c[k - 1] = (float)b;
+        }
+    };
+    binom(L.model == kHaverkamp ? L.hk_beta : L.vg_n, f.bin1);
+    binom(-L.vg_m, f.bin2);
     return f;
 }
 

@@ -14,7 +14,9 @@
 //     = -dT expm1(-m log1p(P)) (vGM);
 //   Feddes sink: exact piecewise-linear increments.
 // Transcendentals use the hardware FP32 log2/exp2; log1p and expm1 use short
-// series near zero.
+// series near zero.  The increments (1 + u)^e - 1 of the power laws take the
+// binomial series to u^6 while |u| < 1/16 (coefficients per law, set on the
+// host), else expm1(e log1p(u)).
 #pragma once
 
 #include "rs_internal.h"
@@ -72,7 +74,30 @@ struct Law32 {
     int kappa_rule;
     int newton;
     float newton_tol;   // a Newton step of at most newton_tol |d| ends the correction solve
+    // binomial coefficients binom(e, k), k = 1..6, of (1 + u)^e - 1 for the
+    // exponents of the increments: e = hk_beta (Haverkamp) or vg_n (vGM) in
+    // bin1, e = -vg_m (vGM) in bin2
+    float bin1[6], bin2[6];
 };
+
+// (1 + u)^e - 1.  For |u| < 1/16 the binomial series u (c1 + u (c2 + ... + u c6))
+// with c_k = binom(e, k): for -1 <= e <= 7, |binom(e, k)| <= |e| for k >= 7, so the
+// terms left out sum to at most |e u| |u|^6 / (1 - |u|) < 1.07 * 2^-24 |e u|, about
+// an FP32 rounding of the leading term; otherwise expm1(e log1p(u)).
+// Proportional to u, so u = 0 gives 0.
+__device__ __forceinline__ float pow1p_m1(float u, float e, const float *c)
+{
+    if (fabsf(u) < 0.0625f) {
+        float p = c[5];
+        p = fmaf(p, u, c[4]);
+        p = fmaf(p, u, c[3]);
+        p = fmaf(p, u, c[2]);
+        p = fmaf(p, u, c[1]);
+        p = fmaf(p, u, c[0]);
+        return p * u;
+    }
+    return f_expm1(e * f_log1p(u));
+}
 
 // Base-state quantities of one node (evaluated once per update).
 struct Base {
@@ -147,7 +172,7 @@ __device__ __forceinline__ void dtheta32(const Law32 &L, const Base &b, float de
     if (MODEL == kHaverkamp) {
         if (!b.sat && !xsat) {
             const float t = delta * b.ipsi;
-            const float dq = b.q * f_expm1(L.hk_beta * f_log1p(-t));
+            const float dq = b.q * pow1p_m1(-t, L.hk_beta, L.bin1);
             const float den = b.den + dq;
             const float hu = -L.unit * x;
             // one reciprocal serves 1/den = hu w and 1/hu = den w
@@ -172,8 +197,8 @@ __device__ __forceinline__ void dtheta32(const Law32 &L, const Base &b, float de
     // van Genuchten - Mualem
     if (!b.sat && !xsat) {
         const float t = delta * b.ipsi;
-        const float dp = b.q * f_expm1(L.vg_n * f_log1p(-t));
-        const float dse = b.se * f_expm1(-L.vg_m * f_log1p(dp * b.iden));
+        const float dp = b.q * pow1p_m1(-t, L.vg_n, L.bin1);
+        const float dse = b.se * pow1p_m1(dp * b.iden, -L.vg_m, L.bin2);
         dth = L.dT * dse;
         const float P = b.q + dp, X = b.den + dp, Se = b.se + dse;
         slope = L.dT * L.vg_m * L.vg_n * P * Se * f_rcp(X * (-x));
