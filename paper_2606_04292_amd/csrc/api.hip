@@ -320,6 +320,16 @@ Law make_law(const rs_constitutive *c)
     L.newton_tol = c->newton_tol;
     L.gd_alpha = c->gd_alpha;
     L.soils = nullptr;
+    // binom(e, k) = binom(e, k - 1) (e - k + 1) / k
+    auto binom = [](double e, double *b) {
+        double v = 1.0;
+        for (int k = 1; k <= 7; ++k) {
+            v *= (e - (k - 1)) / k;
+            b[k - 1] = v;
+        }
+    };
+    binom(c->model == RS_HAVERKAMP ? L.hk_beta : L.vg_n, L.bin1);
+    binom(-L.vg_m, L.bin2);
     if (c->n_soils > 0) L.model = kMulti;   // the table is attached by the grid
     return L;
 }

@@ -64,6 +64,9 @@ struct Law {
     double newton_tol;   // a Newton step of at most newton_tol |x| ends the pointwise solve
     double gd_alpha;     // Gardner exponent (per law unit of psi)
     const Law *soils;    // kMulti: device table of per-soil laws, indexed by Geo::soil
+    // binomial coefficients binom(e, k), k = 1..7, of (1 + u)^e - 1: e = hk_beta
+    // (Haverkamp) or vg_n (vGM) in bin1, e = -vg_m (vGM) in bin2
+    double bin1[7], bin2[7];
 };
 
 // Step coefficients (by value).

@@ -164,6 +164,91 @@ __device__ __forceinline__ ThetaEval theta_t(const Law &L, double x)
     return r;
 }
 
+// (1 + u)^e - 1 by the binomial series to u^7 (c[k - 1] = binom(e, k)), for
+// |u| < 2^-8: for -1 <= e <= 7, |binom(e, k)| <= |e| for k >= 8, so the terms left
+// out sum to at most |e| |u|^8 / (1 - |u|) < 2^-63 |e|.
+__device__ __forceinline__ double pow1p_m1_series(double u, const double *c)
+{
+    double p = c[6];
+    p = fma(p, u, c[5]);
+    p = fma(p, u, c[4]);
+    p = fma(p, u, c[3]);
+    p = fma(p, u, c[2]);
+    p = fma(p, u, c[1]);
+    p = fma(p, u, c[0]);
+    return p * u;
+}
+
+constexpr double kSeriesU = 0.00390625;   // 2^-8
+
+// Power terms of the last law evaluation of a pointwise Newton solve.
+struct PowState {
+    bool ok;       // the last iterate was unsaturated (Haverkamp, vGM)
+    double x;      // that iterate
+    double ix;     // 1 / x
+    double q;      // Haverkamp: Q = |u x|^beta; vGM: P = (alpha |x|)^n
+    double se;     // vGM: Se = (1 + P)^-m
+    double ix1p;   // vGM: 1 / (1 + P)
+};
+
+// theta and theta' at x within a Newton solve.  The power terms of the
+// Haverkamp and vGM laws scale from the last iterate's: Q(x) = Q(x') (1 + u)^beta
+// and P(x) = P(x') (1 + u)^n with u = x / x' - 1, then Se(x) = Se(x') (1 + v)^-m
+// with v = (P(x) - P(x')) / (1 + P(x')); each factor is taken by the binomial
+// series while its u or v is below 2^-8 in magnitude (a few units in the last
+// place, like the ln/exp series), else the powers are evaluated afresh.
+template <int MODEL>
+__device__ __forceinline__ ThetaEval theta_next(const Law &L, double x, PowState &s)
+{
+    if (MODEL != kHaverkamp && MODEL != kVgm) return theta_t<MODEL>(L, x);
+    ThetaEval r;
+    if (!(x < 0.0)) {
+        r.th = L.ts;
+        r.dth = 0.0;
+        s.ok = false;
+        return r;
+    }
+    const double u = (x - s.x) * s.ix;
+    const bool ser = s.ok && fabs(u) < kSeriesU;
+    if (MODEL == kHaverkamp) {
+        const double hu = -L.unit * x;
+        double Q;
+        if (ser) Q = fma(s.q, pow1p_m1_series(u, L.bin1), s.q);
+        else Q = rs_exp(L.hk_beta * rs_log(hu));
+        const double den = L.hk_alpha + Q;
+        const double w = rcp_1nr(hu * den);
+        const double tmr = L.hk_alpha * L.dT * (hu * w);
+        r.th = L.tr + tmr;
+        r.dth = L.unit * L.hk_beta * tmr * Q * w;
+        s.q = Q;
+        s.ix = -L.unit * (den * w);   // 1/x = -unit / hu
+    } else {
+        double P, Se;
+        bool fresh = !ser;
+        if (ser) {
+            const double dP = s.q * pow1p_m1_series(u, L.bin1);
+            const double v = dP * s.ix1p;
+            P = s.q + dP;
+            if (fabs(v) < kSeriesU) Se = fma(s.se, pow1p_m1_series(v, L.bin2), s.se);
+            else fresh = true;
+        }
+        if (fresh) {
+            P = rs_exp(L.vg_n * rs_log(-L.vg_alpha * x));
+            Se = rs_exp(-L.vg_m * rs_log1p(P));
+        }
+        const double w = rcp_1nr((1.0 + P) * (-x));
+        r.th = L.tr + L.dT * Se;
+        r.dth = L.dT * L.vg_m * L.vg_n * P * Se * w;
+        s.q = P;
+        s.se = Se;
+        s.ix = -(1.0 + P) * w;
+        s.ix1p = -x * w;
+    }
+    s.x = x;
+    s.ok = true;
+    return r;
+}
+
 template <int MODEL>
 __device__ __forceinline__ double theta_only_t(const Law &L, double x)
 {
@@ -247,9 +332,16 @@ __device__ __forceinline__ double local_solve_t(const Law &L, double a, double b
     }
     double x = x0;
     bool done = false;
+    PowState ps;
+    ps.ok = false;
+    ps.x = 0.0;
+    ps.ix = 0.0;
+    ps.q = 0.0;
+    ps.se = 1.0;
+    ps.ix1p = 0.0;
     const int iters = NEWTON > 0 ? NEWTON : L.newton;
     for (int k = 0; k < iters; ++k) {
-        ThetaEval t = theta_t<MODEL>(L, x);
+        ThetaEval t = theta_next<MODEL>(L, x, ps);
         double F = a * t.th + c * x - f;
         double dF = a * t.dth + c;
         if (SINK) {
