@@ -463,7 +463,7 @@ __global__ __launch_bounds__(256) void k_sweep(Geo g, Law L, Step st, const doub
     const int par = (int)((j + k + colour) & 1);
     const int i = 2 * (int)ih + par;
     if (i >= g.n[0]) return;
-    if (dirichlet_at(g, i, (int)j, (int)k, nullptr)) return;
+    if (dirichlet_t<DIM>(g, i, (int)j, (int)k)) return;
     // parity-split row: node i at ih (+ xh if odd); its left neighbour i - 1
     // at ih (i odd) or xh + ih - 1 (i even), the right one just after it
     const long long rb = (long long)j * g.stride[1] + (long long)k * g.stride[2];
@@ -516,8 +516,8 @@ __global__ __launch_bounds__(256) void k_sweep_pair(Geo g, Law L, Step st, const
     const long long rb = (long long)j * g.stride[1] + (long long)k * g.stride[2];
     const long long idx = rb + (par ? g.xh : 0) + 2 * q;
     const long long xl = rb + (par ? 0 : g.xh - 1) + 2 * q;   // ia - 1, ia + 1, ia + 3
-    const bool dir_a = dirichlet_at(g, ia, (int)j, (int)k, nullptr);
-    const bool dir_b = !has_b || dirichlet_at(g, ia + 2, (int)j, (int)k, nullptr);
+    const bool dir_a = dirichlet_t<DIM>(g, ia, (int)j, (int)k);
+    const bool dir_b = !has_b || dirichlet_t<DIM>(g, ia + 2, (int)j, (int)k);
     if (dir_a && dir_b) return;
     const long long bytes = (g.N + 32) * (long long)sizeof(double);   // + padding
     const __amdgpu_buffer_rsrc_t rP = buf_rsrc(psi, bytes), rK = buf_rsrc(K, bytes),
@@ -603,8 +603,8 @@ __global__ __launch_bounds__(256) void k_sweep_pair_defect(Geo g, Law L, Step st
         const long long rb = (long long)j * g.stride[1] + (long long)k * g.stride[2];
         const long long idx = rb + (par ? g.xh : 0) + 2 * q;
         const long long xl = rb + (par ? 0 : g.xh - 1) + 2 * q;
-        const bool dir_a = dirichlet_at(g, ia, (int)j, (int)k, nullptr);
-        const bool dir_b = !has_b || dirichlet_at(g, ia + 2, (int)j, (int)k, nullptr);
+        const bool dir_a = dirichlet_t<DIM>(g, ia, (int)j, (int)k);
+        const bool dir_b = !has_b || dirichlet_t<DIM>(g, ia + 2, (int)j, (int)k);
         const long long bytes = (g.N + 32) * (long long)sizeof(double);
         const __amdgpu_buffer_rsrc_t rP = buf_rsrc(psi, bytes), rK = buf_rsrc(K, bytes),
                                      rG = buf_rsrc(gv, bytes), rD = buf_rsrc(d, bytes);
@@ -741,7 +741,7 @@ __global__ __launch_bounds__(256) void k_defect_colour(Geo g, Law L, Step st, co
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
             const int i = ia + 2 * a;
-            if ((a == 1 && !has_b) || dirichlet_at(g, i, (int)j, (int)k, nullptr)) continue;
+            if ((a == 1 && !has_b) || dirichlet_t<DIM>(g, i, (int)j, (int)k)) continue;
             double po[NO > 0 ? NO : 1], ko[NO > 0 ? NO : 1];
 #pragma unroll
             for (int o = 0; o < NO; ++o) {

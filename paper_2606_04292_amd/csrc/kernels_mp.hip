@@ -40,7 +40,7 @@ __global__ __launch_bounds__(256) void k_sweep32(Geo g, Law32 L, float a, const 
     const int par = (int)((j + k + colour) & 1);
     const int i = 2 * (int)ih + par;
     if (i >= g.n[0]) return;
-    if (dirichlet_at(g, i, (int)j, (int)k, nullptr)) return;
+    if (dirichlet_t<DIM>(g, i, (int)j, (int)k)) return;
     // parity-split row (see k_sweep): node at ih (+ xh if odd), left neighbour
     // at ih (odd) or xh + ih - 1 (even), the right one just after it
     const long long rb = (long long)j * g.stride[1] + (long long)k * g.stride[2];
@@ -106,8 +106,8 @@ __global__ __launch_bounds__(256) void k_sweep32_pair(Geo g, Law32 L, float a, c
     if (2 * q >= len) return;
     const bool has_b = 2 * q + 1 < len;
     const int ia = 4 * q + par;
-    const bool dir_a = dirichlet_at(g, ia, (int)j, (int)k, nullptr);
-    const bool dir_b = !has_b || dirichlet_at(g, ia + 2, (int)j, (int)k, nullptr);
+    const bool dir_a = dirichlet_t<DIM>(g, ia, (int)j, (int)k);
+    const bool dir_b = !has_b || dirichlet_t<DIM>(g, ia + 2, (int)j, (int)k);
     if (dir_a && dir_b) return;
     const long long rb = (long long)j * g.stride[1] + (long long)k * g.stride[2];
     const long long idx = rb + (par ? g.xh : 0) + 2 * q;

@@ -444,6 +444,27 @@ __device__ __forceinline__ bool dirichlet_at(const Geo &g, int i, int j, int k, 
     return dir;
 }
 
+// dirichlet_at's test (without the value) on a level of DIM axes, every
+// descriptor field read unconditionally, so that the reads issue together
+// instead of one scalar-load round trip per branch.
+template <int DIM>
+__device__ __forceinline__ bool dirichlet_t(const Geo &g, int i, int j, int k)
+{
+    const int c[3] = {i, j, k};
+    bool dir = false;
+#pragma unroll
+    for (int l = 0; l < DIM; ++l)
+        dir = dir | ((c[l] == 0) & (g.bc[2 * l] == kBcDirichlet)) |
+              ((c[l] == g.n[l] - 1) & (g.bc[2 * l + 1] == kBcDirichlet));
+    const int ax = g.pax;
+    const int cp = ax == 0 ? i : (ax == 1 ? j : k);
+    const int t0 = ax == 0 ? j : i;
+    const int t1 = ax == 2 ? j : k;
+    bool in = (g.pface >= 0) & (cp == g.pat) & (t0 >= g.plo[0]) & (t0 <= g.phi[0]);
+    if (DIM == 3) in = in & (t1 >= g.plo[1]) & (t1 <= g.phi[1]);
+    return dir | in;
+}
+
 // Division of a 32-bit index by a run-time constant d (Granlund-Montgomery):
 // with l = ceil(log2 d) and p = 31 + l, m = ceil(2^p / d) satisfies
 // m d - 2^p = e < d <= 2^l, so t m / 2^p = t/d + t e / (d 2^p) < t/d + 1/d for
