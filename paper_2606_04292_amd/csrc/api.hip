@@ -692,7 +692,9 @@ void vcycle32_level(rs_grid *G, int l, int nu1, int nu2)
                              G->desc.dim, G->stream);
         for (int q = l; q < G->nlev - 1; ++q)
             G->updates += (double)(nu1 + nu2) * (double)G->lev[q].unknowns;
-        G->updates += (double)G->nu_coarse * (double)G->lev[G->nlev - 1].unknowns;
+        // the coarsest level's loop may stop after its first sweep (4-ulp exit):
+        // counted as one sweep
+        G->updates += (double)G->lev[G->nlev - 1].unknowns;
         return;
     }
     if (l == G->nlev - 1) {
@@ -744,7 +746,9 @@ int vcycle_level(rs_grid *G, int l, int nu1, int nu2)
                            G->desc.dim, nodes, G->stream);
         for (int q = l; q < G->nlev - 1; ++q)
             G->updates += (double)(nu1 + nu2) * (double)G->lev[q].unknowns;
-        G->updates += (double)G->nu_coarse * (double)G->lev[G->nlev - 1].unknowns;
+        // the coarsest level's loop may stop after its first sweep (4-ulp exit):
+        // counted as one sweep
+        G->updates += (double)G->lev[G->nlev - 1].unknowns;
         return RS_OK;
     }
     if (l == G->nlev - 1) return sweep_level(G, l, G->nu_coarse);

@@ -275,10 +275,11 @@ __device__ __forceinline__ bool ngs_cell_at(const Geo &g, const Law &L, double a
     const double x1 = ngs_point<MODEL, SINK, DIM>(g, L, a, beta, lambdaU, st, Ki, Kn, pn, f, x0, i,
                                                   j, k, idx, colour);
     psi[idx] = x1;
-    return !(x1 == x0);
+    return fabs(x1 - x0) > 8.8817841970012523e-16 * fabs(x0);   // 4 ulp (2^-50 |x0|)
 }
 
-// The update of unknown (i, j, k); true if it changed the stored value.
+// The update of unknown (i, j, k); true if it moved the stored value by more
+// than 4 ulp.
 template <int MODEL, bool SINK, int DIM>
 __device__ __forceinline__ bool ngs_cell(const Geo &g, const Law &L, double a, const double *beta,
                                          double lambdaU, const double *K, const double *gv,
@@ -965,21 +966,27 @@ __global__ __launch_bounds__(256) void k_sweep_small(Geo g, Law L, Step st, cons
 // with work-group barriers between the steps instead of launches.
 // ---------------------------------------------------------------------------
 
+// n sweeps of a level; with exit set (the coarsest level) the loop stops after
+// a sweep that moved no value by more than 4 ulp: the coarse problem is then
+// solved to rounding, and further sweeps only move values within rounding.
 template <int MODEL, bool SINK, int DIM>
-__device__ void tail_sweeps64(const TailLevel &T, const Law &L, double a, int n)
+__device__ void tail_sweeps64(const TailLevel &T, const Law &L, double a, int n, bool exit = false)
 {
     const ColourMap cm = tail_cm(T);
-    for (int sw = 0; sw < n; ++sw)
+    for (int sw = 0; sw < n; ++sw) {
+        int changed = 0;
         for (int colour = 0; colour < 2; ++colour) {
             for (unsigned long long t = threadIdx.x; t < cm.total; t += blockDim.x) {
                 int i, j, k;
                 if (!colour_ijk(T.g, cm, t, colour, i, j, k)) continue;
                 if (dirichlet_at(T.g, i, j, k, nullptr)) continue;
-                ngs_cell<MODEL, SINK, DIM>(T.g, L, a, T.beta, T.lambdaU, T.K, T.gv, T.psi, i, j, k,
-                                           colour);
+                changed |= ngs_cell<MODEL, SINK, DIM>(T.g, L, a, T.beta, T.lambdaU, T.K, T.gv,
+                                                      T.psi, i, j, k, colour);
             }
-            __syncthreads();
+            if (colour == 0 || !exit) __syncthreads();
+            else if (!__syncthreads_or(changed)) return;
         }
+    }
 }
 
 // Levels lds_from..last live in LDS for the duration of the cycle (psi, K*, g,
@@ -1057,7 +1064,7 @@ __global__ __launch_bounds__(512) void k_vcycle_tail(const TailArgs *A, int top,
         }
         __syncthreads();
     }
-    tail_sweeps64<MODEL, SINK, DIM>(SL[last], L, a, nuc);
+    tail_sweeps64<MODEL, SINK, DIM>(SL[last], L, a, nuc, true);
     for (int l = last - 1; l >= top; --l) {
         const TailLevel &F = SL[l], &C = SL[l + 1];
         const NodeMap nf = tail_nm(F);
