@@ -328,8 +328,10 @@ Law make_law(const rs_constitutive *c)
             b[k - 1] = v;
         }
     };
-    binom(c->model == RS_HAVERKAMP ? L.hk_beta : L.vg_n, L.bin1);
+    const double e1 = c->model == RS_HAVERKAMP ? L.hk_beta : L.vg_n;
+    binom(e1, L.bin1);
     binom(-L.vg_m, L.bin2);
+    L.series_u = (e1 >= -1.0 && e1 <= 7.0 && -L.vg_m >= -1.0) ? 0.00390625 : 0.0;
     if (c->n_soils > 0) L.model = kMulti;   // the table is attached by the grid
     return L;
 }

@@ -451,8 +451,10 @@ Law32 make_law32(const Law &L)
             c[k - 1] = (float)b;
         }
     };
-    binom(L.model == kHaverkamp ? L.hk_beta : L.vg_n, f.bin1);
+    const double e1 = L.model == kHaverkamp ? L.hk_beta : L.vg_n;
+    binom(e1, f.bin1);
     binom(-L.vg_m, f.bin2);
+    f.series_u = (e1 >= -1.0 && e1 <= 7.0 && -L.vg_m >= -1.0) ? 0.0625f : 0.0f;
     return f;
 }
 

@@ -65,8 +65,11 @@ struct Law {
     double gd_alpha;     // Gardner exponent (per law unit of psi)
     const Law *soils;    // kMulti: device table of per-soil laws, indexed by Geo::soil
     // binomial coefficients binom(e, k), k = 1..7, of (1 + u)^e - 1: e = hk_beta
-    // (Haverkamp) or vg_n (vGM) in bin1, e = -vg_m (vGM) in bin2
+    // (Haverkamp) or vg_n (vGM) in bin1, e = -vg_m (vGM) in bin2; the series is
+    // used while |u| < series_u (2^-8, or 0 when an exponent lies outside
+    // [-1, 7], where the truncation bound below does not hold)
     double bin1[7], bin2[7];
+    double series_u;
 };
 
 // Step coefficients (by value).

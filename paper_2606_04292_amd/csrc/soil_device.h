@@ -179,8 +179,6 @@ __device__ __forceinline__ double pow1p_m1_series(double u, const double *c)
     return p * u;
 }
 
-constexpr double kSeriesU = 0.00390625;   // 2^-8
-
 // Power terms of the last law evaluation of a pointwise Newton solve.
 struct PowState {
     bool ok;       // the last iterate was unsaturated (Haverkamp, vGM)
@@ -195,8 +193,8 @@ struct PowState {
 // Haverkamp and vGM laws scale from the last iterate's: Q(x) = Q(x') (1 + u)^beta
 // and P(x) = P(x') (1 + u)^n with u = x / x' - 1, then Se(x) = Se(x') (1 + v)^-m
 // with v = (P(x) - P(x')) / (1 + P(x')); each factor is taken by the binomial
-// series while its u or v is below 2^-8 in magnitude (a few units in the last
-// place, like the ln/exp series), else the powers are evaluated afresh.
+// series while its u or v is below L.series_u (2^-8; 0 for exponents outside
+// [-1, 7]) in magnitude, else the powers are evaluated afresh.
 template <int MODEL>
 __device__ __forceinline__ ThetaEval theta_next(const Law &L, double x, PowState &s)
 {
@@ -209,7 +207,7 @@ __device__ __forceinline__ ThetaEval theta_next(const Law &L, double x, PowState
         return r;
     }
     const double u = (x - s.x) * s.ix;
-    const bool ser = s.ok && fabs(u) < kSeriesU;
+    const bool ser = s.ok && fabs(u) < L.series_u;
     if (MODEL == kHaverkamp) {
         const double hu = -L.unit * x;
         double Q;
@@ -229,7 +227,7 @@ __device__ __forceinline__ ThetaEval theta_next(const Law &L, double x, PowState
             const double dP = s.q * pow1p_m1_series(u, L.bin1);
             const double v = dP * s.ix1p;
             P = s.q + dP;
-            if (fabs(v) < kSeriesU) Se = fma(s.se, pow1p_m1_series(v, L.bin2), s.se);
+            if (fabs(v) < L.series_u) Se = fma(s.se, pow1p_m1_series(v, L.bin2), s.se);
             else fresh = true;
         }
         if (fresh) {

@@ -78,16 +78,17 @@ struct Law32 {
     // exponents of the increments: e = hk_beta (Haverkamp) or vg_n (vGM) in
     // bin1, e = -vg_m (vGM) in bin2
     float bin1[6], bin2[6];
+    float series_u;   // 1/16, or 0 when an exponent lies outside [-1, 7]
 };
 
-// (1 + u)^e - 1.  For |u| < 1/16 the binomial series u (c1 + u (c2 + ... + u c6))
+// (1 + u)^e - 1.  For |u| < series_u (1/16) the binomial series u (c1 + u (c2 + ... + u c6))
 // with c_k = binom(e, k): for -1 <= e <= 7, |binom(e, k)| <= |e| for k >= 7, so the
 // terms left out sum to at most |e u| |u|^6 / (1 - |u|) < 1.07 * 2^-24 |e u|, about
 // an FP32 rounding of the leading term; otherwise expm1(e log1p(u)).
 // Proportional to u, so u = 0 gives 0.
-__device__ __forceinline__ float pow1p_m1(float u, float e, const float *c)
+__device__ __forceinline__ float pow1p_m1(float u, float e, const float *c, float series_u)
 {
-    if (fabsf(u) < 0.0625f) {
+    if (fabsf(u) < series_u) {
         float p = c[5];
         p = fmaf(p, u, c[4]);
         p = fmaf(p, u, c[3]);
@@ -172,7 +173,7 @@ __device__ __forceinline__ void dtheta32(const Law32 &L, const Base &b, float de
     if (MODEL == kHaverkamp) {
         if (!b.sat && !xsat) {
             const float t = delta * b.ipsi;
-            const float dq = b.q * pow1p_m1(-t, L.hk_beta, L.bin1);
+            const float dq = b.q * pow1p_m1(-t, L.hk_beta, L.bin1, L.series_u);
             const float den = b.den + dq;
             const float hu = -L.unit * x;
             // one reciprocal serves 1/den = hu w and 1/hu = den w
@@ -197,8 +198,8 @@ __device__ __forceinline__ void dtheta32(const Law32 &L, const Base &b, float de
     // van Genuchten - Mualem
     if (!b.sat && !xsat) {
         const float t = delta * b.ipsi;
-        const float dp = b.q * pow1p_m1(-t, L.vg_n, L.bin1);
-        const float dse = b.se * pow1p_m1(dp * b.iden, -L.vg_m, L.bin2);
+        const float dp = b.q * pow1p_m1(-t, L.vg_n, L.bin1, L.series_u);
+        const float dse = b.se * pow1p_m1(dp * b.iden, -L.vg_m, L.bin2, L.series_u);
         dth = L.dT * dse;
         const float P = b.q + dp, X = b.den + dp, Se = b.se + dse;
         slope = L.dT * L.vg_m * L.vg_n * P * Se * f_rcp(X * (-x));
