@@ -952,7 +952,7 @@ __global__ __launch_bounds__(256) void k_sweep_small(Geo g, Law L, Step st, cons
                 int j = r % g.n[1];
                 int k = r / g.n[1];
                 if (((i + j + k) & 1) != colour) continue;
-                if (dirichlet_at(g, i, j, k, nullptr)) continue;
+                if (dirichlet_t<DIM>(g, i, j, k)) continue;
                 ngs_cell<MODEL, SINK, DIM>(g, L, st.a, beta, lambdaU, K, gv, psi, i, j, k, colour);
             }
             __syncthreads();
@@ -979,7 +979,7 @@ __device__ void tail_sweeps64(const TailLevel &T, const Law &L, double a, int n,
             for (unsigned long long t = threadIdx.x; t < cm.total; t += blockDim.x) {
                 int i, j, k;
                 if (!colour_ijk(T.g, cm, t, colour, i, j, k)) continue;
-                if (dirichlet_at(T.g, i, j, k, nullptr)) continue;
+                if (dirichlet_t<DIM>(T.g, i, j, k)) continue;
                 changed |= ngs_cell<MODEL, SINK, DIM>(T.g, L, a, T.beta, T.lambdaU, T.K, T.gv,
                                                       T.psi, i, j, k, colour);
             }
@@ -1041,7 +1041,7 @@ __global__ __launch_bounds__(512) void k_vcycle_tail(const TailArgs *A, int top,
             int i, j, k;
             node_ijk(nf, t, i, j, k);
             double r = 0.0;
-            if (!dirichlet_at(F.g, i, j, k, nullptr))
+            if (!dirichlet_t<DIM>(F.g, i, j, k))
                 r = F.gv[t] - apply_N_t<MODEL, SINK, DIM, true>(F.g, L, a, F.beta, F.K, F.psi, i, j, k,
                                                           (long long)t);
             F.d[t] = r;
@@ -1056,7 +1056,7 @@ __global__ __launch_bounds__(512) void k_vcycle_tail(const TailArgs *A, int top,
         for (unsigned long long t = threadIdx.x; t < (unsigned long long)C.g.N; t += blockDim.x) {
             int i, j, k;
             node_ijk(nc, t, i, j, k);
-            if (!dirichlet_at(C.g, i, j, k, nullptr))
+            if (!dirichlet_t<DIM>(C.g, i, j, k))
                 C.gv[t] = apply_N_t<MODEL, SINK, DIM, true>(C.g, L, a, C.beta, C.K, C.psibar, i, j, k,
                                                       (long long)t) +
                           C.gv[t];

@@ -184,7 +184,7 @@ __global__ __launch_bounds__(256) void k_sweep32_small(Geo g, Law32 L, float a, 
                 int j = r % g.n[1];
                 int k = r / g.n[1];
                 if (((i + j + k) & 1) != colour) continue;
-                if (dirichlet_at(g, i, j, k, nullptr)) continue;
+                if (dirichlet_t<DIM>(g, i, j, k)) continue;
                 changed |= ngs_cell32<MODEL, SINK, DIM, true, true>(g, L, a, beta, lambdaU, K, rhs, pb,
                                                                     dl, i, j, k, colour);
             }
@@ -261,7 +261,7 @@ __device__ void tail_sweeps32(const TailLevel &T, const Law32 &L, float a, int n
             for (unsigned long long t = threadIdx.x; t < cm.total; t += blockDim.x) {
                 int i, j, k;
                 if (!colour_ijk(T.g, cm, t, colour, i, j, k)) continue;
-                if (dirichlet_at(T.g, i, j, k, nullptr)) continue;
+                if (dirichlet_t<DIM>(T.g, i, j, k)) continue;
                 changed |= ngs_cell32<MODEL, SINK, DIM, true, true>(T.g, L, a, T.beta, T.lambdaU32,
                                                                     T.K32, T.rhs32, T.pb32, T.dl,
                                                                     i, j, k, colour);
@@ -292,7 +292,7 @@ __global__ __launch_bounds__(512) void k_vcycle_tail32(const TailArgs *A, int to
             int i, j, k;
             node_ijk(nf, t, i, j, k);
             float v = 0.0f;
-            if (!dirichlet_at(F.g, i, j, k, nullptr))
+            if (!dirichlet_t<DIM>(F.g, i, j, k))
                 v = F.rhs32[t] - apply_Nd<MODEL, SINK, DIM, true>(F.g, L, a, F.beta, F.K32, F.pb32,
                                                                    F.dl, i, j, k, (long long)t);
             F.r32[t] = v;
@@ -307,7 +307,7 @@ __global__ __launch_bounds__(512) void k_vcycle_tail32(const TailArgs *A, int to
         for (unsigned long long t = threadIdx.x; t < (unsigned long long)C.g.N; t += blockDim.x) {
             int i, j, k;
             node_ijk(nc, t, i, j, k);
-            if (!dirichlet_at(C.g, i, j, k, nullptr))
+            if (!dirichlet_t<DIM>(C.g, i, j, k))
                 C.rhs32[t] = apply_Nd<MODEL, SINK, DIM, true>(C.g, L, a, C.beta, C.K32, C.pb32,
                                                               C.dbar32, i, j, k, (long long)t) +
                              C.rhs32[t];

@@ -47,7 +47,7 @@ __device__ __forceinline__ void restrict_at(const Geo &gc, const Geo &gf, const 
 {
     const long long I = lin(gc, I0, I1, I2);
     const int F[3] = {2 * I0, 2 * I1, 2 * I2};
-    if (dirichlet_at(gc, I0, I1, I2, nullptr)) {
+    if (dirichlet_t<DIM>(gc, I0, I1, I2)) {
         psibar_c[I] = psi_f[lin(gf, F[0], F[1], F[2])];
         g_c[I] = T(0);
         return;
@@ -126,7 +126,7 @@ template <int DIM, typename T>
 __device__ __forceinline__ void prolong_at(const Geo &gf, const Geo &gc, const T *psi_c,
                                            const T *psibar_c, T *psi_f, int i, int j, int k)
 {
-    if (dirichlet_at(gf, i, j, k, nullptr)) return;
+    if (dirichlet_t<DIM>(gf, i, j, k)) return;
     const int c[3] = {i, j, k};
     long long off[3][2];
     T wt[3][2];
@@ -230,7 +230,7 @@ __global__ __launch_bounds__(256) void k_prolong(Geo gf, Geo gc, const T *psi_c,
             for (int a0 = 0; a0 < 2; ++a0) {
                 const int f0 = 2 * Ic[0] + a0;
                 if (f0 >= gf.n[0]) continue;
-                if (dirichlet_at(gf, f0, f1, f2, nullptr)) continue;
+                if (dirichlet_t<DIM>(gf, f0, f1, f2)) continue;
                 // weights of the two taps along an axis: even fine index (1, 0),
                 // odd (1/2, 1/2)
                 const T w0[2] = {a0 ? T(0.5) : T(1), a0 ? T(0.5) : T(0)};
@@ -334,7 +334,7 @@ __global__ __launch_bounds__(256) void k_restrict_pair(Geo gc, Geo gf, const T *
         if (a == 1 && !has_b) break;
         const int I0 = 2 * m + a;
         const long long I = rc + (a ? gc.xh + m : m);
-        if (dirichlet_at(gc, I0, J1, J2, nullptr)) {
+        if (dirichlet_t<DIM>(gc, I0, J1, J2)) {
             psibar_c[I] = pin[a];
             g_c[I] = T(0);
         } else {
@@ -426,7 +426,7 @@ __global__ __launch_bounds__(256) void k_prolong_pair(Geo gf, Geo gc, const T *p
                 for (int a = 0; a < 2; ++a) {
                     const int f0 = 4 * m + 2 * a + b;
                     in[a] = f0 < n0;
-                    if (!in[a] || dirichlet_at(gf, f0, f1, f2, nullptr)) continue;
+                    if (!in[a] || dirichlet_t<DIM>(gf, f0, f1, f2)) continue;
                     const T w0[2] = {b ? T(0.5) : T(1), b ? T(0.5) : T(0)};
                     const T w1[2] = {a1 ? T(0.5) : T(1), a1 ? T(0.5) : T(0)};
                     const T w2[2] = {a2 ? T(0.5) : T(1), a2 ? T(0.5) : T(0)};
