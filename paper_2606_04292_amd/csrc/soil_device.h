@@ -184,7 +184,7 @@ struct PowState {
     bool ok;       // the last iterate was unsaturated (Haverkamp, vGM)
     double x;      // that iterate
     double ix;     // 1 / x
-    double q;      // Haverkamp: Q = |u x|^beta; vGM: P = (alpha |x|)^n
+    double q;      // Haverkamp: Q = (unit |x|)^beta; vGM: P = (alpha |x|)^n
     double se;     // vGM: Se = (1 + P)^-m
     double ix1p;   // vGM: 1 / (1 + P)
 };
