@@ -401,9 +401,9 @@ __global__ __launch_bounds__(256) void e_sweep32(const EList *DL, const ESlot *s
         if (!colour_ijk(Lv.geo, Lv.cm, (unsigned long long)tile * kTile + threadIdx.x, colour, i,
                         j, k))
             return;
-        if (dirichlet_at(Lv.geo, i, j, k, nullptr)) return;
         const float a = (float)dyn[s].a;
         law_dim(S.law.model, Lv.geo.dim, [&](auto M, auto Dm) {
+            if (dirichlet_t<decltype(Dm)::value>(Lv.geo, i, j, k)) return;
             ngs_cell32<decltype(M)::value, false, decltype(Dm)::value, true>(
                 Lv.geo, S.law32, a, nullptr, 0.0f, Lv.K32, Lv.rhs, Lv.pb, Lv.dl, i, j, k, colour);
         });
@@ -416,13 +416,11 @@ __device__ __forceinline__ void resid32_node(const ESlot &S, float a, const ELev
     int i, j, k;
     node_ijk(Lv.nm, t, i, j, k);
     float v = 0.0f;
-    if (!dirichlet_at(Lv.geo, i, j, k, nullptr)) {
-        law_dim(S.law.model, Lv.geo.dim, [&](auto M, auto Dm) {
-            v = A.rhs[t] - apply_Nd<decltype(M)::value, false, decltype(Dm)::value>(
-                               Lv.geo, S.law32, a, nullptr, A.K32, A.pb, A.dl, i, j, k,
-                               (long long)t);
-        });
-    }
+    law_dim(S.law.model, Lv.geo.dim, [&](auto M, auto Dm) {
+        if (dirichlet_t<decltype(Dm)::value>(Lv.geo, i, j, k)) return;
+        v = A.rhs[t] - apply_Nd<decltype(M)::value, false, decltype(Dm)::value>(
+                           Lv.geo, S.law32, a, nullptr, A.K32, A.pb, A.dl, i, j, k, (long long)t);
+    });
     A.r[t] = v;
 }
 
@@ -442,14 +440,13 @@ __device__ __forceinline__ void crhs32_node(const ESlot &S, float a, const ELeve
 {
     int i, j, k;
     node_ijk(C.nm, t, i, j, k);
-    if (!dirichlet_at(C.geo, i, j, k, nullptr)) {
-        law_dim(S.law.model, C.geo.dim, [&](auto M, auto Dm) {
-            AC.rhs[t] = apply_Nd<decltype(M)::value, false, decltype(Dm)::value>(
-                            C.geo, S.law32, a, nullptr, AC.K32, AC.pb, AC.dbar, i, j, k,
-                            (long long)t) +
-                        AC.rhs[t];
-        });
-    }
+    law_dim(S.law.model, C.geo.dim, [&](auto M, auto Dm) {
+        if (dirichlet_t<decltype(Dm)::value>(C.geo, i, j, k)) return;
+        AC.rhs[t] = apply_Nd<decltype(M)::value, false, decltype(Dm)::value>(
+                        C.geo, S.law32, a, nullptr, AC.K32, AC.pb, AC.dbar, i, j, k,
+                        (long long)t) +
+                    AC.rhs[t];
+    });
     AC.dl[t] = AC.dbar[t];
 }
 
@@ -508,8 +505,8 @@ __device__ __forceinline__ void tail_sweeps(const ESlot &S, float a, const ELeve
             for (unsigned long long t = threadIdx.x; t < Lv.cm.total; t += blockDim.x) {
                 int i, j, k;
                 if (!colour_ijk(Lv.geo, Lv.cm, t, colour, i, j, k)) continue;
-                if (dirichlet_at(Lv.geo, i, j, k, nullptr)) continue;
                 law_dim(S.law.model, Lv.geo.dim, [&](auto M, auto Dm) {
+                    if (dirichlet_t<decltype(Dm)::value>(Lv.geo, i, j, k)) return;
                     changed |= ngs_cell32<decltype(M)::value, false, decltype(Dm)::value>(
                         Lv.geo, S.law32, a, nullptr, 0.0f, A.K32, A.rhs, A.pb, A.dl, i, j, k,
                         colour);
