@@ -269,16 +269,14 @@ __global__ __launch_bounds__(256) void e_defect(const EList *FL, const ESlot *sl
         const double a = dyn[s].a;
         const double x = S.psi[t];
         double r = 0.0;
-        if (!dirichlet_at(L0.geo, i, j, k, nullptr)) {
+        law_dim(S.law.model, L0.geo.dim, [&](auto M, auto Dm) {
+            if (dirichlet_t<decltype(Dm)::value>(L0.geo, i, j, k)) return;
             double terms = 0.0;
-            law_dim(S.law.model, L0.geo.dim, [&](auto M, auto Dm) {
-                r = S.g[t] - apply_N_t<decltype(M)::value, false, decltype(Dm)::value, true>(
-                                 L0.geo, S.law, a, nullptr, S.K, S.psi, i, j, k, (long long)t,
-                                 &terms);
-            });
+            r = S.g[t] - apply_N_t<decltype(M)::value, false, decltype(Dm)::value, true>(
+                             L0.geo, S.law, a, nullptr, S.K, S.psi, i, j, k, (long long)t, &terms);
             const double sc = fabs(S.g[t]) + terms;
             vs = sc > vs ? sc : vs;
-        }
+        });
         const double ar = fabs(r);
         v = (ar > v || ar != ar) ? ar : v;
         L0.rhs[t] = (float)r;

@@ -1147,7 +1147,7 @@ __global__ __launch_bounds__(256) void k_residual_pair(Geo g, Law L, Step st, co
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
             const int i = ia + 2 * a;
-            if ((a == 1 && !has_b) || dirichlet_at(g, i, j, k, nullptr)) continue;
+            if ((a == 1 && !has_b) || dirichlet_t<DIM>(g, i, j, k)) continue;
             double po[NO > 0 ? NO : 1], ko[NO > 0 ? NO : 1];
 #pragma unroll
             for (int o = 0; o < NO; ++o) {
@@ -1239,7 +1239,7 @@ __global__ __launch_bounds__(256) void k_coarse_rhs(Geo g, Law L, Step st, const
     if (t >= (unsigned long long)g.N) return;
     int i, j, k;
     node_ijk(nm, t, i, j, k);
-    if (!dirichlet_at(g, i, j, k, nullptr))
+    if (!dirichlet_t<DIM>(g, i, j, k))
         gv[t] = apply_N_t<MODEL, SINK, DIM, true>(g, L, st.a, beta, K, psibar, i, j, k, (long long)t) +
                 gv[t];
     psi[t] = psibar[t];

@@ -211,7 +211,7 @@ __global__ __launch_bounds__(256) void k_residual32(Geo g, Law32 L, float a, con
     node_ijk(nm, t, i, j, k);
     const long long idx = (long long)t;
     float v = 0.0f;
-    if (!dirichlet_at(g, i, j, k, nullptr))
+    if (!dirichlet_t<DIM>(g, i, j, k))
         v = rhs[idx] - apply_Nd<MODEL, SINK, DIM, true>(g, L, a, beta, K, pb, dl, i, j, k, idx);
     r[idx] = v;
 }
@@ -230,7 +230,7 @@ __global__ __launch_bounds__(256) void k_coarse_rhs32(Geo g, Law32 L, float a, c
     int i, j, k;
     node_ijk(nm, t, i, j, k);
     const long long idx = (long long)t;
-    if (!dirichlet_at(g, i, j, k, nullptr))
+    if (!dirichlet_t<DIM>(g, i, j, k))
         rhs[idx] = apply_Nd<MODEL, SINK, DIM, true>(g, L, a, beta, K, pb, dbar, i, j, k, idx) + rhs[idx];
     dl[idx] = dbar[idx];
 }
