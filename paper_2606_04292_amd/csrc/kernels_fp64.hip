@@ -1388,16 +1388,16 @@ bool fused_enabled()
 }
 
 // Two nodes per lane in the colour sweeps of the large buffer-path levels
-// (at least 2^22 nodes: on smaller levels the lane's two solves in sequence
-// cost more than they save, 15.1 against 14.2 us at 129^3); RS_SWEEP=single
-// keeps one node per lane on every level, RS_SWEEP=pair takes two on every
-// buffer-path level.
+// (at least 2^21 nodes: 129^3 takes 13.9 us per colour with two, 15.1 with
+// one; on smaller levels the lane's two solves in sequence cost more than
+// they save); RS_SWEEP=single keeps one node per lane on every level,
+// RS_SWEEP=pair takes two on every buffer-path level.
 bool pair_sweep_level(const Geo &g)
 {
     const char *e = getenv("RS_SWEEP");
     if (e && strcmp(e, "single") == 0) return false;
     if (e && strcmp(e, "pair") == 0) return true;
-    return g.N >= (1ll << 22);
+    return g.N >= (1ll << 21);
 }
 
 // The z-marching LDS sweep: 3-D levels whose rows are split by parity into
